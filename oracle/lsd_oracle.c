@@ -1,0 +1,253 @@
+/*
+ * lsd_oracle.c -- CPU oracle for the stable LSD radix sort.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it; the
+ * library under paper_1008_2849_amd/ never includes, links or calls it, and
+ * it shares no code with that library.
+ *
+ * What it computes, from Wassenberg & Sanders, "Faster Radix Sort via Virtual
+ * Memory and Write-Combining" (arXiv:1008.2849):
+ *
+ *   - Section 3 (naive counting sort): build the histogram of the N keys;
+ *     an exclusive prefix sum of it gives the first output slot of every key
+ *     value; then each item is written at its key's slot, and that slot is
+ *     incremented.  Here the "key" of a pass is one digit of the 32-bit key.
+ *   - Section 4 (LSD radix sort): D-bit digits of the K-bit keys are taken
+ *     from the least significant one upward; each pass partitions all items
+ *     by the current digit and preserves the order of items with equal
+ *     digits (stability), so after the last pass the items are in ascending
+ *     key order with equal keys in input order.
+ *   - Items are a 32-bit key with an optional 32-bit value (abstract,
+ *     Section 1); values travel with their keys.
+ *
+ * Plain choices, made on purpose: one thread, no SIMD, no pass skipping,
+ * 64-bit counters, a fresh output array per pass (out of place, as the
+ * paper's passes are), and the items visited in increasing input order in
+ * every scatter.
+ *
+ * Digit widths are given per pass, least significant first, and must sum
+ * to 32; each width is 1..16 (a wider digit would need a 2^width counter
+ * array, which a plain oracle has no reason to allocate).
+ *
+ * Return codes: 0 = ok, -1 = invalid arguments, -2 = out of host memory.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* Digit of a key: bits [shift, shift + width) (Section 4, digit extraction). */
+static uint32_t digit_of(uint32_t key, unsigned shift, unsigned width)
+{
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 5
+    /* planted mistake: the mask drops the digit's top bit */
+    return (key >> shift) & ((1u << (width - 1)) - 1u);
+#elif defined(ORACLE_MUTANT) && ORACLE_MUTANT == 6
+    /* planted mistake: keys compared as signed (sign bit flipped) */
+    return ((key ^ 0x80000000u) >> shift) & ((1u << width) - 1u);
+#else
+    return (key >> shift) & ((1u << width) - 1u);
+#endif
+}
+
+static int widths_ok(const unsigned *widths, unsigned npasses)
+{
+    unsigned total = 0, p;
+    if (widths == NULL || npasses == 0 || npasses > 32)
+        return 0;
+    for (p = 0; p < npasses; ++p) {
+        if (widths[p] < 1 || widths[p] > 16)
+            return 0;
+        total += widths[p];
+    }
+    return total == 32;
+}
+
+/*
+ * Histogram of one digit over n keys (Section 3, first step of counting
+ * sort).  hist must hold 2^width counters; it is overwritten.
+ */
+int oracle_digit_histogram(const uint32_t *keys, uint64_t n, unsigned shift,
+                           unsigned width, uint64_t *hist)
+{
+    uint64_t i, buckets;
+    if (width < 1 || width > 16 || shift + width > 32 || hist == NULL ||
+        (keys == NULL && n > 0))
+        return ORACLE_EINVAL;
+    buckets = (uint64_t)1 << width;
+    for (i = 0; i < buckets; ++i)
+        hist[i] = 0;
+    for (i = 0; i < n; ++i)
+        hist[digit_of(keys[i], shift, width)] += 1;
+    return ORACLE_OK;
+}
+
+/*
+ * One counting-sort pass (Section 3, naive algorithm), out of place:
+ * histogram, exclusive prefix sum, then every item in increasing input
+ * order written at its digit's next slot.  vin/vout are both NULL for a
+ * keys-only pass.
+ */
+int oracle_counting_pass(const uint32_t *kin, const uint32_t *vin,
+                         uint32_t *kout, uint32_t *vout, uint64_t n,
+                         unsigned shift, unsigned width)
+{
+    uint64_t buckets, d, i, running;
+    uint64_t *next;
+    int rc;
+    if ((vin == NULL) != (vout == NULL))
+        return ORACLE_EINVAL;
+    if (n > 0 && (kin == NULL || kout == NULL))
+        return ORACLE_EINVAL;
+    if (width < 1 || width > 16 || shift + width > 32)
+        return ORACLE_EINVAL;
+    buckets = (uint64_t)1 << width;
+    next = (uint64_t *)malloc(buckets * sizeof(uint64_t));
+    if (next == NULL)
+        return ORACLE_ENOMEM;
+
+    /* step 1: histogram of the digit */
+    rc = oracle_digit_histogram(kin, n, shift, width, next);
+    if (rc != ORACLE_OK) {
+        free(next);
+        return rc;
+    }
+
+    /* step 2: exclusive prefix sum -> first output slot of each digit */
+    running = 0;
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 2
+    /* planted mistake: the sum runs over the digits in descending order */
+    for (d = buckets; d-- > 0;) {
+        uint64_t count = next[d];
+        next[d] = running;
+        running += count;
+    }
+#else
+    for (d = 0; d < buckets; ++d) {
+        uint64_t count = next[d];
+        next[d] = running;
+        running += count;
+    }
+#endif
+
+    /* step 3: scatter; each item goes to its digit's slot, then the slot
+     * moves on by one, so equal digits keep their input order */
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 1
+    /* planted mistake: items visited in decreasing order while the slots
+     * still move forward, which reverses every run of equal digits */
+    for (i = n; i-- > 0;) {
+        uint32_t dd = digit_of(kin[i], shift, width);
+        kout[next[dd]] = kin[i];
+        if (vin != NULL)
+            vout[next[dd]] = vin[i];
+        next[dd] += 1;
+    }
+#else
+    for (i = 0; i < n; ++i) {
+        uint32_t dd = digit_of(kin[i], shift, width);
+        uint64_t slot = next[dd];
+        kout[slot] = kin[i];
+        if (vin != NULL) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 4
+            /* planted mistake: values stay in input order */
+            vout[i] = vin[i];
+#else
+            vout[slot] = vin[i];
+#endif
+        }
+        next[dd] = slot + 1;
+    }
+#endif
+    free(next);
+    return ORACLE_OK;
+}
+
+/*
+ * Full LSD radix sort (Section 4): passes over the digits from the least
+ * significant upward, each a stable counting-sort pass.  The result
+ * replaces keys[] (and vals[] when not NULL).
+ */
+int oracle_lsd_sort(uint32_t *keys, uint32_t *vals, uint64_t n,
+                    const unsigned *widths, unsigned npasses)
+{
+    uint32_t *ka, *kb, *va = NULL, *vb = NULL, *tmp;
+    unsigned p, shift = 0, last = npasses;
+    int rc = ORACLE_OK;
+    if (!widths_ok(widths, npasses))
+        return ORACLE_EINVAL;
+    if (n > 0 && keys == NULL)
+        return ORACLE_EINVAL;
+    if (n < 2)
+        return ORACLE_OK;
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 3
+    /* planted mistake: the most significant pass is dropped */
+    last = npasses - 1;
+#endif
+    ka = keys;
+    kb = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (kb == NULL)
+        return ORACLE_ENOMEM;
+    if (vals != NULL) {
+        va = vals;
+        vb = (uint32_t *)malloc(n * sizeof(uint32_t));
+        if (vb == NULL) {
+            free(kb);
+            return ORACLE_ENOMEM;
+        }
+    }
+    for (p = 0; p < last; ++p) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 7
+        /* planted mistake: digits taken most significant first */
+        unsigned s = 32 - shift - widths[p];
+#else
+        unsigned s = shift;
+#endif
+        rc = oracle_counting_pass(ka, va, kb, vb, n, s, widths[p]);
+        if (rc != ORACLE_OK)
+            break;
+        tmp = ka; ka = kb; kb = tmp;
+        tmp = va; va = vb; vb = tmp;
+        shift += widths[p];
+    }
+    /* the sorted data is in ka/va; bring it back into the caller's arrays */
+    if (rc == ORACLE_OK && ka != keys) {
+        memcpy(keys, ka, n * sizeof(uint32_t));
+        if (vals != NULL)
+            memcpy(vals, va, n * sizeof(uint32_t));
+    }
+    free(ka == keys ? kb : ka);
+    if (vals != NULL)
+        free(va == vals ? vb : va);
+    return rc;
+}
+
+/*
+ * Segmented form: segment s is [off[s], off[s+1]) and is sorted on its own
+ * with the full LSD sort above; items outside [off[0], off[nseg]) are not
+ * touched.  Offsets must be nondecreasing.
+ */
+int oracle_lsd_sort_segmented(uint32_t *keys, uint32_t *vals,
+                              const uint32_t *off, uint32_t nseg,
+                              const unsigned *widths, unsigned npasses)
+{
+    uint32_t s;
+    int rc;
+    if (!widths_ok(widths, npasses) || (off == NULL && nseg > 0))
+        return ORACLE_EINVAL;
+    for (s = 0; s < nseg; ++s)
+        if (off[s + 1] < off[s])
+            return ORACLE_EINVAL;
+    for (s = 0; s < nseg; ++s) {
+        uint64_t lo = off[s], len = (uint64_t)off[s + 1] - off[s];
+        rc = oracle_lsd_sort(keys + lo, vals ? vals + lo : NULL, len, widths,
+                             npasses);
+        if (rc != ORACLE_OK)
+            return rc;
+    }
+    return ORACLE_OK;
+}
