@@ -1,0 +1,265 @@
+/*
+ * rtsort.h -- C ABI of the MI355X (gfx950) stable LSD radix sort.
+ *
+ * The library sorts 32-bit unsigned keys, optionally carrying 32-bit values,
+ * in ascending unsigned order; equal keys keep their input order (stable).
+ * This is the problem of Wassenberg & Sanders, "Faster Radix Sort via Virtual
+ * Memory and Write-Combining" (arXiv:1008.2849): abstract and Section 1 fix
+ * the item (32-bit key, optional 32-bit value), Section 3 the counting-sort
+ * pass (digit histogram, exclusive prefix sum, scatter with increment) and
+ * Section 4 the LSD order of passes and their stability.
+ *
+ * Conventions shared by every call below
+ *  - Arrays are device pointers into HBM (hipMalloc'd or torch tensors) owned
+ *    by the caller; the library never frees them.  Any 4-byte alignment works.
+ *  - Every sort call is stream-ordered: it enqueues kernels on `stream` and
+ *    returns; results are valid once the stream has synchronised.  No call
+ *    synchronises the host, except that with the environment variable
+ *    RT_DEBUG_SYNC=1 each call waits for its own work and reports kernel
+ *    errors.
+ *  - Argument errors are reported synchronously, before any device work.
+ *    n = 0 and n = 1 are valid and do nothing.  n >= 2^32 is RT_ERR_TOO_LARGE.
+ *  - The result is in place from the caller's view.  The library keeps a
+ *    workspace per (device, stream) (temporary ping-pong buffers, digit
+ *    histograms, lookback state); calls on different streams may run
+ *    concurrently.  Calls that pass their own workspace (the _ex forms) may
+ *    be captured into a HIP graph: they then issue kernel launches only.
+ *  - rt_last_error() returns a thread-local text for the last failure.
+ */
+#ifndef RTSORT_H
+#define RTSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+    RT_OK = 0,
+    RT_ERR_INVALID_ARG = 1,   /* null pointer with n > 0, aliasing, bad config */
+    RT_ERR_TOO_LARGE = 2,     /* n or a segment offset >= 2^32 */
+    RT_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+    RT_ERR_HIP = 4,           /* a HIP call or kernel launch failed */
+    RT_ERR_BUDGET = 5,        /* serving: request larger than the HBM budget */
+    RT_ERR_UNSUPPORTED = 6,   /* configuration this build does not provide */
+    RT_ERR_CANCELLED = 7,     /* serving: request dropped at shutdown */
+    RT_ERR_TIMEOUT = 8,       /* serving: wait timed out, request still live */
+    RT_ERR_NOT_FOUND = 9      /* serving: unknown or already collected ticket */
+} rt_status;
+
+#define RT_MAX_PASSES 8
+#define RT_MAX_DIGIT_BITS 11
+
+/* rt_config.flags */
+#define RT_FLAG_NO_SKIP 0x1u   /* run every pass, even when its digit is constant */
+#define RT_FLAG_NT_STORES 0x2u /* scatter with non-temporal stores */
+
+/*
+ * Sort configuration.  Zero-initialised fields mean "tuned default".
+ * digit_bits[p] is the width of pass p's digit, least significant first
+ * (Section 4: digits are processed from the least significant one upward);
+ * the widths must sum to 32 and each lies in 1..RT_MAX_DIGIT_BITS.
+ * Every decomposition gives the same result; they differ in speed.
+ */
+typedef struct rt_config {
+    uint32_t num_passes;                 /* 0 = tuned default */
+    uint32_t digit_bits[RT_MAX_PASSES];  /* used when num_passes > 0 */
+    uint32_t block_threads;              /* 0 = tuned (256 or 512) */
+    uint32_t items_per_thread;           /* 0 = tuned */
+    uint32_t flags;                      /* RT_FLAG_* */
+} rt_config;
+
+/* ------------------------------------------------------------------------
+ * Single-array sorts
+ * --------------------------------------------------------------------- */
+
+/*
+ * Sort n keys in place (stable LSD radix sort, Section 4; each pass the
+ * counting sort of Section 3).  keys: device u32[n].
+ */
+rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream);
+
+/*
+ * Sort n key/value pairs in place by key; each value moves with its key and
+ * equal keys keep their input order.  keys, vals: device u32[n], distinct
+ * and not overlapping.  vals == NULL is RT_ERR_INVALID_ARG (use
+ * rt_sort_keys).
+ */
+rt_status rt_sort_pairs(uint32_t *keys, uint32_t *vals, size_t n, hipStream_t stream);
+
+/*
+ * Bytes of workspace rt_sort_ex needs for n items (with_values 0 or 1)
+ * under cfg (NULL = tuned default).  Returns 0 for n < 2.
+ */
+size_t rt_workspace_bytes(size_t n, int with_values, const rt_config *cfg);
+
+/*
+ * Explicit form: cfg (NULL = tuned default) and a caller-owned device
+ * workspace of at least rt_workspace_bytes() bytes (NULL = library cache).
+ * vals may be NULL (keys only).  With a caller workspace the call issues
+ * kernel launches only, so it may be captured into a HIP graph; concurrent
+ * calls must not share a workspace.
+ */
+rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched segmented sort
+ * --------------------------------------------------------------------- */
+
+/*
+ * Sort every segment s = [seg_offsets[s], seg_offsets[s+1]) of keys/vals
+ * independently and stably, in one graph-launched sequence.  seg_offsets:
+ * device u32[num_segments + 1], nondecreasing.  Items outside
+ * [seg_offsets[0], seg_offsets[num_segments]) are not touched; empty
+ * segments are fine.  vals may be NULL (keys only).  Malformed offsets are
+ * undefined behaviour unless RT_FLAG_VALIDATE-style checking is requested
+ * through rt_sort_batched_ex; the plain call does not read offsets on the
+ * host.  max_total bounds seg_offsets[num_segments] - seg_offsets[0] (the
+ * library sizes its workspace from it; pass the total when known).
+ */
+rt_status rt_sort_pairs_batched(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
+                                uint32_t num_segments, size_t max_total, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Pieces of the path, exported for parity tests and measurement
+ * --------------------------------------------------------------------- */
+
+/*
+ * Digit histograms of all passes in one read of the keys (Section 3's
+ * counting step for every digit at once).  hist: device
+ * u32[num_passes * 2^RT_MAX_DIGIT_BITS]; pass p's 2^digit_bits[p] counters
+ * start at offset p * 2^RT_MAX_DIGIT_BITS; the whole array is overwritten.
+ * cfg as for rt_sort_ex (NULL = tuned default).
+ */
+rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const rt_config *cfg,
+                              uint32_t *hist, hipStream_t stream);
+
+/*
+ * One stable counting-sort pass, out of place (Section 3, naive algorithm:
+ * histogram, exclusive prefix sum, scatter with increment) on digit
+ * [shift, shift + width).  kin/vin are read, kout/vout written (vin and vout
+ * both NULL for keys only); inputs and outputs must not overlap.
+ * width 1..RT_MAX_DIGIT_BITS, shift + width <= 32.
+ */
+rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                           uint32_t *vout, size_t n, uint32_t shift, uint32_t width,
+                           hipStream_t stream);
+
+/*
+ * Streaming copy of `bytes` bytes (a multiple of 4) from src to dst: the
+ * achievable read+write bandwidth probe the per-pass figures are set
+ * against.
+ */
+rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Device input generator (counter-based SplitMix64)
+ * --------------------------------------------------------------------- */
+
+#define RT_DIST_UNIFORM 0u /* low 32 bits of word i */
+#define RT_DIST_AND4 1u    /* AND of the four 32-bit halves of words 2i, 2i+1 */
+#define RT_DIST_ZIPF16 2u  /* dictionary[first r with hi32(word i) < thresholds[r]] */
+
+typedef struct rt_gen_params {
+    uint32_t dist;            /* RT_DIST_* */
+    uint64_t state;           /* SplitMix64 state of the stream */
+    uint32_t dictionary[16];  /* RT_DIST_ZIPF16 only */
+    uint64_t thresholds[16];  /* RT_DIST_ZIPF16 only; increasing, last = 2^32 */
+} rt_gen_params;
+
+/*
+ * Fill keys[0..n) from the counter-based generator: word i of the stream is
+ * mix64(state + (i + 1) * 0x9E3779B97F4A7C15) (SplitMix64, Steele, Lea &
+ * Flood, OOPSLA 2014).  vals (may be NULL) receives vals[i] = value_base + i.
+ * params is a host pointer, read during the call.
+ */
+rt_status rt_generate(uint32_t *keys, uint32_t *vals, size_t n, const rt_gen_params *params,
+                      uint32_t value_base, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Serving loop
+ * --------------------------------------------------------------------- */
+
+typedef struct rt_server rt_server;
+
+/*
+ * Start a server on the current device.  hbm_budget_bytes bounds the device
+ * memory its admitted requests hold (inputs it generates, ping-pong buffers,
+ * metadata); max_active bounds how many requests are in flight.  The server
+ * owns a scheduler thread and a stream of its own.
+ */
+rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_active, rt_server **out);
+
+/*
+ * Submit a request whose key/value arrays already live on the device
+ * (caller-owned, not touched by the caller until rt_server_wait returns).
+ * The sorted result replaces keys/vals.  vals may be NULL.  A request whose
+ * footprint exceeds the whole budget is RT_ERR_BUDGET.
+ */
+rt_status rt_server_submit(rt_server *s, uint32_t *keys, uint32_t *vals, size_t n,
+                           uint64_t *ticket);
+
+/*
+ * Submit a request whose input the server generates on the device at
+ * admission from params (rt_generate's definition) with vals[i] = i; the
+ * result stays in server memory until rt_server_fetch or rt_server_release.
+ */
+rt_status rt_server_submit_generated(rt_server *s, const rt_gen_params *params, size_t n,
+                                     uint64_t *ticket);
+
+/*
+ * Wait for a request.  timeout_us < 0 waits forever; on expiry returns
+ * RT_ERR_TIMEOUT and the request stays live.  latency_us (may be NULL)
+ * receives completion time minus submit time.  The request's own status is
+ * returned (RT_OK, RT_ERR_HIP, RT_ERR_CANCELLED, ...).
+ */
+rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
+
+/*
+ * Copy a finished generated request's sorted arrays into caller device
+ * buffers (out_vals may be NULL) and release its memory.
+ */
+rt_status rt_server_fetch(rt_server *s, uint64_t ticket, uint32_t *out_keys, uint32_t *out_vals);
+
+/* Release a finished request's server memory without copying it. */
+rt_status rt_server_release(rt_server *s, uint64_t ticket);
+
+/*
+ * Latency percentiles (us) over completed requests and throughput
+ * (completed items / (last completion - first admission), Gkeys/s).
+ * Any output pointer may be NULL.  peak_bytes: high-water mark of budgeted
+ * device memory.
+ */
+rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
+                          uint64_t *completed, size_t *peak_bytes);
+
+/* Stop the scheduler; requests not yet finished end as RT_ERR_CANCELLED. */
+rt_status rt_server_destroy(rt_server *s);
+
+/* ------------------------------------------------------------------------
+ * Tuning and diagnostics
+ * --------------------------------------------------------------------- */
+
+/*
+ * Load a tuning table (JSON written by the autotuner) that maps
+ * (with_values, size class) to digit widths, block size, items per thread
+ * and flags.  NULL restores the built-in defaults.
+ */
+rt_status rt_load_tuning(const char *json_path);
+
+/* Tuned configuration the library would use for n items. */
+rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
+
+const char *rt_status_string(rt_status s);
+const char *rt_last_error(void);
+const char *rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSORT_H */

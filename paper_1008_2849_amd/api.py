@@ -1,0 +1,201 @@
+"""Python binding of librtsort: argument marshalling only.
+
+Every function takes torch tensors that live on the GPU (dtype uint32 or
+int32, bit patterns read as unsigned 32-bit keys), hands their device
+pointers and the current HIP stream to the C ABI, and returns.  All sorting
+work happens in the library's HIP kernels; there is no other implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import RtConfig, RtGenParams, check, lib
+
+FLAG_NO_SKIP = _lib.RT_FLAG_NO_SKIP
+FLAG_NT_STORES = _lib.RT_FLAG_NT_STORES
+MAX_DIGIT_BITS = _lib.RT_MAX_DIGIT_BITS
+MAX_PASSES = _lib.RT_MAX_PASSES
+
+
+@dataclasses.dataclass
+class Config:
+    """Sort configuration; zeros / empty mean "tuned default"."""
+    digit_bits: Sequence[int] = ()
+    block_threads: int = 0
+    items_per_thread: int = 0
+    flags: int = 0
+
+    def to_c(self) -> RtConfig:
+        c = RtConfig()
+        c.num_passes = len(self.digit_bits)
+        for i, w in enumerate(self.digit_bits):
+            c.digit_bits[i] = int(w)
+        c.block_threads = int(self.block_threads)
+        c.items_per_thread = int(self.items_per_thread)
+        c.flags = int(self.flags)
+        return c
+
+    @staticmethod
+    def from_c(c: RtConfig) -> "Config":
+        return Config(tuple(int(c.digit_bits[i]) for i in range(c.num_passes)),
+                      int(c.block_threads), int(c.items_per_thread), int(c.flags))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_tensor(t, name: str):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"{name} must be int32 or uint32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def current_stream(device=None) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return current_stream()
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _cfg_ptr(cfg: Optional[Config]):
+    if cfg is None:
+        return None, None
+    c = cfg.to_c()
+    return c, ctypes.byref(c)
+
+
+def sort_keys(keys, stream=None) -> None:
+    """Sort a 1-D uint32/int32 GPU tensor in place (unsigned order)."""
+    _check_tensor(keys, "keys")
+    check(lib().rt_sort_keys(_ptr(keys), keys.numel(), _stream(stream)), "rt_sort_keys")
+
+
+def sort_pairs(keys, vals, stream=None) -> None:
+    """Sort keys in place and move vals with them (stable)."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    if vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    check(lib().rt_sort_pairs(_ptr(keys), _ptr(vals), keys.numel(), _stream(stream)), "rt_sort_pairs")
+
+
+def workspace_bytes(n: int, with_values: bool, cfg: Optional[Config] = None) -> int:
+    c, p = _cfg_ptr(cfg)
+    return int(lib().rt_workspace_bytes(n, 1 if with_values else 0, p))
+
+
+def sort_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, stream=None) -> None:
+    """Sort with an explicit configuration and (optionally) a caller-owned
+    workspace tensor of at least workspace_bytes() bytes."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    if vals is not None and vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    c, p = _cfg_ptr(cfg)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr = workspace.data_ptr()
+        ws_bytes = workspace.numel() * workspace.element_size()
+    check(lib().rt_sort_ex(_ptr(keys), _ptr(vals), keys.numel(), p, ws_ptr, ws_bytes, _stream(stream)),
+          "rt_sort_ex")
+
+
+def sort_pairs_batched(keys, vals, offsets, max_total: Optional[int] = None, stream=None) -> None:
+    """Sort every segment [offsets[s], offsets[s+1]) independently (stable).
+    vals may be None."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    _check_tensor(offsets, "offsets")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs num_segments + 1 entries")
+    total = keys.numel() if max_total is None else int(max_total)
+    check(lib().rt_sort_pairs_batched(_ptr(keys), _ptr(vals), _ptr(offsets), offsets.numel() - 1, total,
+                                      _stream(stream)), "rt_sort_pairs_batched")
+
+
+def digit_histograms(keys, cfg: Optional[Config] = None, stream=None):
+    """Per-pass digit counts, shape [passes, 2^MAX_DIGIT_BITS] (uint32 as int32)."""
+    torch = _torch()
+    _check_tensor(keys, "keys")
+    passes = len(cfg.digit_bits) if cfg is not None and cfg.digit_bits else tuned_config(
+        keys.numel(), False).digit_bits.__len__()
+    hist = torch.empty((MAX_PASSES, 1 << MAX_DIGIT_BITS), dtype=torch.int32, device=keys.device)
+    c, p = _cfg_ptr(cfg)
+    check(lib().rt_digit_histograms(_ptr(keys), keys.numel(), p, hist.data_ptr(), _stream(stream)),
+          "rt_digit_histograms")
+    return hist[:passes]
+
+
+def counting_pass(kin, vin, kout, vout, shift: int, width: int, stream=None) -> None:
+    """One stable counting-sort pass on bits [shift, shift+width), out of place."""
+    for t, nm in ((kin, "kin"), (vin, "vin"), (kout, "kout"), (vout, "vout")):
+        _check_tensor(t, nm)
+    check(lib().rt_counting_pass(_ptr(kin), _ptr(vin), _ptr(kout), _ptr(vout), kin.numel(), shift, width,
+                                 _stream(stream)), "rt_counting_pass")
+
+
+def copy(src, dst, stream=None) -> None:
+    """Streaming device copy (the bandwidth probe)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    check(lib().rt_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream(stream)), "rt_copy")
+
+
+def gen_params_to_c(p) -> RtGenParams:
+    """Convert inputs.CounterGenParams to the C struct."""
+    g = RtGenParams()
+    g.dist = int(p.dist)
+    g.state = int(p.state) & ((1 << 64) - 1)
+    for i, x in enumerate(p.dictionary):
+        g.dictionary[i] = int(x)
+    for i, x in enumerate(p.thresholds):
+        g.thresholds[i] = int(x)
+    return g
+
+
+def generate(keys, vals, params, value_base: int = 0, stream=None) -> None:
+    """Fill keys (and vals = value_base + i) from the counter-based generator."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    g = gen_params_to_c(params)
+    check(lib().rt_generate(_ptr(keys), _ptr(vals), keys.numel(), ctypes.byref(g), int(value_base),
+                            _stream(stream)), "rt_generate")
+
+
+def load_tuning(path: Optional[str]) -> None:
+    check(lib().rt_load_tuning(None if path is None else path.encode()), "rt_load_tuning")
+
+
+def tuned_config(n: int, with_values: bool) -> Config:
+    c = RtConfig()
+    check(lib().rt_tuned_config(n, 1 if with_values else 0, ctypes.byref(c)), "rt_tuned_config")
+    return Config.from_c(c)
+
+
+def version() -> str:
+    return lib().rt_version().decode()

@@ -1,0 +1,60 @@
+// rt_common.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rt_internal.h"
+
+// Tile shapes (digit bits class, threads per block, items per thread) for
+// which onesweep kernels are compiled.  Every shape exists for both digit
+// classes so that any mix of digit widths can use any shape.
+#define RT_FOR_EACH_SHAPE(X) \
+    X(8, 256, 16)            \
+    X(8, 256, 32)            \
+    X(8, 512, 16)            \
+    X(11, 256, 16)           \
+    X(11, 256, 32)           \
+    X(11, 512, 16)
+
+namespace rt {
+
+// A validated sort configuration.
+struct Resolved {
+    uint32_t num_passes;
+    uint32_t shift[kMaxPasses];
+    uint32_t width[kMaxPasses];
+    int block;
+    int ipt;
+    uint32_t flags;
+    bool with_values;
+};
+
+// Byte offsets of the workspace regions.
+struct Layout {
+    size_t hist, base, plan, ctr, status, status_bytes;
+    size_t status_pass[kMaxPasses];
+    size_t t1k, t1v, t2k, t2v;
+    size_t total;
+    uint32_t tiles;
+    bool wide_status;
+};
+
+rt_status set_error(rt_status s, const char *fmt, ...);
+const char *last_error();
+bool debug_sync_enabled();
+rt_status finish_call(hipStream_t stream, const char *what, const uint32_t *device_error_word);
+const uint32_t *error_word(const void *ws, const Layout &L);
+int device_cu_count();
+
+bool shape_supported(int bits_class, int block, int ipt);
+rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolved *out);
+Layout make_layout(size_t n, const Resolved &r, bool direct);
+rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);
+void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
+                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream);
+
+// Tuned configuration for n items (from the loaded table, else built in).
+void tuned_config(size_t n, int with_values, rt_config *out);
+
+}  // namespace rt

@@ -1,0 +1,524 @@
+// rt_sort.hip -- host side of the single-array sort: argument checks, tuned
+// configuration, workspace layout and cache, kernel launch sequence, and the
+// C ABI entry points declared in include/rtsort.h.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "rt_common.h"
+#include "rt_kernels.h"
+
+namespace rt {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string t_last_error;
+
+rt_status set_error(rt_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return s;
+}
+
+const char *last_error() { return t_last_error.c_str(); }
+
+bool debug_sync_enabled() {
+    static const bool on = [] {
+        const char *e = getenv("RT_DEBUG_SYNC");
+        return e != nullptr && atoi(e) != 0;
+    }();
+    return on;
+}
+
+rt_status finish_call(hipStream_t stream, const char *what, const uint32_t *device_error_word) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+    if (debug_sync_enabled()) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+        if (device_error_word != nullptr) {
+            uint32_t word = 0;
+            e = hipMemcpy(&word, device_error_word, sizeof word, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+            if (word & kErrLookbackTimeout)
+                return set_error(RT_ERR_HIP, "%s: a lookback wait timed out on the device", what);
+        }
+    }
+    return RT_OK;
+}
+
+int device_cu_count() {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
+
+// ---------------------------------------------------------------------------
+// configuration
+// ---------------------------------------------------------------------------
+
+bool shape_supported(int bits_class, int block, int ipt) {
+#define RT_SHAPE_CASE(B, BLK, I) \
+    if (bits_class == B && block == BLK && ipt == I) return true;
+    RT_FOR_EACH_SHAPE(RT_SHAPE_CASE)
+#undef RT_SHAPE_CASE
+    return false;
+}
+
+static int bits_class_of(uint32_t width) { return width <= 8 ? 8 : 11; }
+
+rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolved *out) {
+    rt_config c;
+    if (cfg == nullptr || cfg->num_passes == 0) {
+        tuned_config(n, with_values, &c);
+        if (cfg != nullptr) {  // keep explicit block / ipt / flags over the tuned widths
+            if (cfg->block_threads) c.block_threads = cfg->block_threads;
+            if (cfg->items_per_thread) c.items_per_thread = cfg->items_per_thread;
+            c.flags |= cfg->flags;
+        }
+    } else {
+        c = *cfg;
+        rt_config t;
+        tuned_config(n, with_values, &t);
+        if (c.block_threads == 0) c.block_threads = t.block_threads;
+        if (c.items_per_thread == 0) c.items_per_thread = t.items_per_thread;
+    }
+    if (c.num_passes < 1 || c.num_passes > kMaxPasses)
+        return set_error(RT_ERR_INVALID_ARG, "num_passes %u outside 1..%d", c.num_passes, kMaxPasses);
+    uint32_t total = 0;
+    Resolved r{};
+    r.num_passes = c.num_passes;
+    for (uint32_t p = 0; p < c.num_passes; ++p) {
+        const uint32_t w = c.digit_bits[p];
+        if (w < 1 || w > static_cast<uint32_t>(kMaxBits))
+            return set_error(RT_ERR_INVALID_ARG, "digit_bits[%u] = %u outside 1..%d", p, w, kMaxBits);
+        r.shift[p] = total;
+        r.width[p] = w;
+        total += w;
+    }
+    if (total != 32) return set_error(RT_ERR_INVALID_ARG, "digit widths sum to %u, not 32", total);
+    r.block = static_cast<int>(c.block_threads);
+    r.ipt = static_cast<int>(c.items_per_thread);
+    for (uint32_t p = 0; p < r.num_passes; ++p)
+        if (!shape_supported(bits_class_of(r.width[p]), r.block, r.ipt))
+            return set_error(RT_ERR_UNSUPPORTED, "no kernel for %d-bit digits with %d threads x %d items",
+                             bits_class_of(r.width[p]), r.block, r.ipt);
+    r.flags = c.flags;
+    r.with_values = with_values != 0;
+    *out = r;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+Layout make_layout(size_t n, const Resolved &r, bool direct) {
+    Layout L{};
+    const size_t tile = static_cast<size_t>(r.block) * r.ipt;
+    const size_t tiles = (n + tile - 1) / tile;
+    L.tiles = static_cast<uint32_t>(tiles);
+    L.wide_status = n >= (static_cast<size_t>(1) << 30);
+    const size_t sw = L.wide_status ? 8 : 4;
+    size_t off = 0;
+    L.hist = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.base = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.plan = off;    off += align256(sizeof(SortPlan));
+    L.ctr = off;     off += align256(sizeof(uint32_t) * kMaxPasses);
+    L.status = off;
+    for (uint32_t p = 0; p < r.num_passes; ++p) {
+        L.status_pass[p] = off - L.status;
+        off += tiles * (static_cast<size_t>(1) << (r.width[p] <= 8 ? 8 : 11)) * sw;
+    }
+    off = align256(off);
+    L.status_bytes = off - L.status;
+    L.t1k = L.t1v = L.t2k = L.t2v = 0;
+    if (!direct) {
+        // A second temporary is needed whenever the executed pass count can
+        // be odd and at least three: the pass count is odd, or passes may be
+        // skipped at run time.
+        const bool need_t2 = (r.num_passes & 1u) || !(r.flags & RT_FLAG_NO_SKIP);
+        const size_t arr = align256(n * sizeof(uint32_t));
+        L.t1k = off; off += arr;
+        if (r.with_values) { L.t1v = off; off += arr; }
+        if (need_t2) {
+            L.t2k = off; off += arr;
+            if (r.with_values) { L.t2v = off; off += arr; }
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// workspace cache: one growable buffer per (device, stream)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct CacheEntry {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, CacheEntry> g_ws;
+}  // namespace
+
+rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    CacheEntry &c = g_ws[{dev, stream}];
+    if (c.bytes < bytes) {
+        if (c.ptr != nullptr) {
+            // earlier work on this stream may still use the old buffer
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return set_error(RT_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+            (void)hipFree(c.ptr);
+            c.ptr = nullptr;
+            c.bytes = 0;
+        }
+        void *p = nullptr;
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(RT_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) for the workspace: %s", bytes,
+                             hipGetErrorString(e));
+        }
+        c.ptr = p;
+        c.bytes = bytes;
+    }
+    *out = c.ptr;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+
+const uint32_t *error_word(const void *ws, const Layout &L) {
+    return reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.ctr) + kMaxPasses;
+}
+
+template <int BITS, int BLOCK, int IPT>
+static void launch_onesweep_shape(bool vals, bool nt, bool wide, dim3 grid, hipStream_t stream,
+                                  const SortPlan *plan, int pass, uint32_t n, const uint32_t *base,
+                                  void *status, uint32_t *ctr) {
+#define RT_OS(V, NTV, S)                                                                           \
+    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S>), grid, dim3(BLOCK), 0, stream, plan, \
+                       pass, n, base, static_cast<S *>(status), ctr, ctr + kMaxPasses)
+    if (wide) {
+        if (vals) { if (nt) RT_OS(true, true, uint64_t); else RT_OS(true, false, uint64_t); }
+        else      { if (nt) RT_OS(false, true, uint64_t); else RT_OS(false, false, uint64_t); }
+    } else {
+        if (vals) { if (nt) RT_OS(true, true, uint32_t); else RT_OS(true, false, uint32_t); }
+        else      { if (nt) RT_OS(false, true, uint32_t); else RT_OS(false, false, uint32_t); }
+    }
+#undef RT_OS
+}
+
+static void launch_onesweep(int bits_class, int block, int ipt, bool vals, bool nt, bool wide,
+                            dim3 grid, hipStream_t stream, const SortPlan *plan, int pass, uint32_t n,
+                            const uint32_t *base, void *status, uint32_t *ctr) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                   \
+    if (bits_class == B && block == BLK && ipt == I) {                                               \
+        launch_onesweep_shape<B, BLK, I>(vals, nt, wide, grid, stream, plan, pass, n, base, status, ctr); \
+        return;                                                                                      \
+    }
+    RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
+#undef RT_SHAPE_LAUNCH
+}
+
+static HistArgs hist_args(const Resolved &r) {
+    HistArgs ha{};
+    ha.num_passes = r.num_passes;
+    uint32_t off = 0;
+    for (uint32_t p = 0; p < r.num_passes; ++p) {
+        ha.shift[p] = r.shift[p];
+        ha.mask[p] = (1u << r.width[p]) - 1u;
+        ha.lds_offset[p] = off;
+        off += 1u << r.width[p];
+    }
+    ha.total_bins = off;
+    return ha;
+}
+
+static uint32_t grid_for(size_t items, size_t per_block, uint32_t cap) {
+    size_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<uint32_t>(g);
+}
+
+void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist,
+                       void *zero_ptr, size_t zero_bytes, hipStream_t stream) {
+    const HistArgs ha = hist_args(r);
+    const int cus = device_cu_count();
+    hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
+                       static_cast<size_t>(r.num_passes) * kMaxRadix);
+    const uint32_t grid = grid_for(n, 256 * 16, static_cast<uint32_t>(cus) * 4);
+    hipLaunchKernelGGL(k_histogram<256>, dim3(grid), dim3(256), ha.total_bins * sizeof(uint32_t), stream,
+                       keys, n, ha, hist, static_cast<uint4 *>(zero_ptr), zero_bytes / 16);
+}
+
+// The whole sort (direct == false) or one explicit pass (direct == true,
+// user_* read and t1_* written).
+void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L,
+                 char *ws, bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v,
+                 hipStream_t stream) {
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *base = reinterpret_cast<uint32_t *>(ws + L.base);
+    SortPlan *plan = reinterpret_cast<SortPlan *>(ws + L.plan);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(ws + L.ctr);
+    char *status = ws + L.status;
+
+    launch_histograms(keys, n, r, hist, status, L.status_bytes, stream);
+
+    PlanArgs a{};
+    a.num_passes = r.num_passes;
+    for (uint32_t p = 0; p < r.num_passes; ++p) {
+        a.shift[p] = r.shift[p];
+        a.width[p] = r.width[p];
+    }
+    a.no_skip = (r.flags & RT_FLAG_NO_SKIP) ? 1u : 0u;
+    a.n = n;
+    a.user_k = keys;
+    a.user_v = r.with_values ? vals : nullptr;
+    if (direct) {
+        a.t1_k = direct_out_k;
+        a.t1_v = r.with_values ? direct_out_v : nullptr;
+    } else {
+        a.t1_k = reinterpret_cast<uint32_t *>(ws + L.t1k);
+        a.t1_v = r.with_values ? reinterpret_cast<uint32_t *>(ws + L.t1v) : nullptr;
+        a.t2_k = L.t2k ? reinterpret_cast<uint32_t *>(ws + L.t2k) : nullptr;
+        a.t2_v = (L.t2v && r.with_values) ? reinterpret_cast<uint32_t *>(ws + L.t2v) : nullptr;
+    }
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, stream, a, hist, base, plan, ctr,
+                       direct ? 1u : 0u);
+
+    const dim3 grid(L.tiles);
+    const bool nt = (r.flags & RT_FLAG_NT_STORES) != 0;
+    for (uint32_t p = 0; p < r.num_passes; ++p)
+        launch_onesweep(bits_class_of(r.width[p]), r.block, r.ipt, r.with_values, nt, L.wide_status, grid,
+                        stream, plan, static_cast<int>(p), n, base + p * kMaxRadix,
+                        status + L.status_pass[p], ctr);
+
+    if (!direct && (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP))) {
+        const uint32_t grid_c = grid_for(n, 256 * 8, static_cast<uint32_t>(device_cu_count()) * 8);
+        hipLaunchKernelGGL(k_copy_back, dim3(grid_c), dim3(256), 0, stream, plan, a.t1_k, a.t1_v, keys,
+                           a.user_v, n);
+    }
+}
+
+}  // namespace rt
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using namespace rt;
+
+static rt_status check_ranges(const uint32_t *keys, const uint32_t *vals, size_t n, const char *what) {
+    if (n >= (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_TOO_LARGE, "%s: n = %zu, the limit is 2^32 - 1", what, n);
+    if (n < 2) return RT_OK;
+    if (keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "%s: keys is NULL with n = %zu", what, n);
+    if ((reinterpret_cast<uintptr_t>(keys) & 3u) || (vals && (reinterpret_cast<uintptr_t>(vals) & 3u)))
+        return set_error(RT_ERR_INVALID_ARG, "%s: arrays must be 4-byte aligned", what);
+    if (vals != nullptr) {
+        const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), v0 = reinterpret_cast<uintptr_t>(vals);
+        const uintptr_t bytes = n * sizeof(uint32_t);
+        if (k0 < v0 + bytes && v0 < k0 + bytes)
+            return set_error(RT_ERR_INVALID_ARG, "%s: keys and values overlap", what);
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    rt_status s = check_ranges(keys, vals, n, "rt_sort_ex");
+    if (s != RT_OK || n < 2) return s;
+    Resolved r;
+    s = resolve_config(cfg, n, vals != nullptr, &r);
+    if (s != RT_OK) return s;
+    const Layout L = make_layout(n, r, false);
+    void *ws = workspace;
+    if (ws != nullptr) {
+        if (workspace_bytes < L.total)
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_ex: workspace of %zu bytes, %zu needed",
+                             workspace_bytes, L.total);
+        if (reinterpret_cast<uintptr_t>(ws) & 255u)
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_ex: workspace must be 256-byte aligned");
+    } else {
+        s = cached_workspace(L.total, stream, &ws);
+        if (s != RT_OK) return s;
+    }
+    launch_sort(keys, vals, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws), false, nullptr, nullptr,
+                stream);
+    return finish_call(stream, "rt_sort_ex", error_word(ws, L));
+}
+
+extern "C" rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream) {
+    return rt_sort_ex(keys, nullptr, n, nullptr, nullptr, 0, stream);
+}
+
+extern "C" rt_status rt_sort_pairs(uint32_t *keys, uint32_t *vals, size_t n, hipStream_t stream) {
+    if (vals == nullptr && n >= 2 && n < (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_INVALID_ARG, "rt_sort_pairs: vals is NULL (use rt_sort_keys)");
+    return rt_sort_ex(keys, vals, n, nullptr, nullptr, 0, stream);
+}
+
+extern "C" size_t rt_workspace_bytes(size_t n, int with_values, const rt_config *cfg) {
+    if (n < 2 || n >= (static_cast<size_t>(1) << 32)) return 0;
+    Resolved r;
+    if (resolve_config(cfg, n, with_values, &r) != RT_OK) return 0;
+    return make_layout(n, r, false).total;
+}
+
+extern "C" rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const rt_config *cfg,
+                                         uint32_t *hist, hipStream_t stream) {
+    if (n >= (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_TOO_LARGE, "rt_digit_histograms: n = %zu", n);
+    if (hist == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_digit_histograms: hist is NULL");
+    if (keys == nullptr && n > 0) return set_error(RT_ERR_INVALID_ARG, "rt_digit_histograms: keys is NULL");
+    Resolved r;
+    rt_status s = resolve_config(cfg, n < 2 ? 2 : n, 0, &r);
+    if (s != RT_OK) return s;
+    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, nullptr, 0, stream);
+    return finish_call(stream, "rt_digit_histograms", nullptr);
+}
+
+extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                                      uint32_t *vout, size_t n, uint32_t shift, uint32_t width,
+                                      hipStream_t stream) {
+    if ((vin == nullptr) != (vout == nullptr))
+        return set_error(RT_ERR_INVALID_ARG, "rt_counting_pass: vin and vout must both be set or both NULL");
+    if (width < 1 || width > static_cast<uint32_t>(kMaxBits) || shift + width > 32)
+        return set_error(RT_ERR_INVALID_ARG, "rt_counting_pass: digit [%u, %u) invalid", shift, shift + width);
+    rt_status s = check_ranges(kin, vin, n, "rt_counting_pass");
+    if (s != RT_OK) return s;
+    if (n == 0) return RT_OK;
+    if (kout == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_counting_pass: kout is NULL");
+    {
+        const uintptr_t bytes = n * sizeof(uint32_t);
+        const uintptr_t ins[2] = {reinterpret_cast<uintptr_t>(kin), reinterpret_cast<uintptr_t>(vin)};
+        const uintptr_t outs[2] = {reinterpret_cast<uintptr_t>(kout), reinterpret_cast<uintptr_t>(vout)};
+        for (int i = 0; i < 2; ++i)
+            for (int o = 0; o < 2; ++o)
+                if (ins[i] && outs[o] && ins[i] < outs[o] + bytes && outs[o] < ins[i] + bytes)
+                    return set_error(RT_ERR_INVALID_ARG, "rt_counting_pass: inputs and outputs overlap");
+        if (vout && reinterpret_cast<uintptr_t>(kout) < reinterpret_cast<uintptr_t>(vout) + bytes &&
+            reinterpret_cast<uintptr_t>(vout) < reinterpret_cast<uintptr_t>(kout) + bytes)
+            return set_error(RT_ERR_INVALID_ARG, "rt_counting_pass: the outputs overlap");
+    }
+    if (n == 1) {
+        hipError_t e = hipMemcpyAsync(kout, kin, 4, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess && vin) e = hipMemcpyAsync(vout, vin, 4, hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_counting_pass: %s", hipGetErrorString(e));
+        return finish_call(stream, "rt_counting_pass", nullptr);
+    }
+    rt_config c{};
+    rt_config t;
+    tuned_config(n, vin != nullptr, &t);
+    c.num_passes = 1;
+    c.digit_bits[0] = width;
+    c.block_threads = t.block_threads;
+    c.items_per_thread = t.items_per_thread;
+    c.flags = RT_FLAG_NO_SKIP;
+    // resolve with a placeholder full-width layout, then set the real digit
+    Resolved r{};
+    r.num_passes = 1;
+    r.shift[0] = shift;
+    r.width[0] = width;
+    r.block = static_cast<int>(c.block_threads);
+    r.ipt = static_cast<int>(c.items_per_thread);
+    r.flags = c.flags;
+    r.with_values = vin != nullptr;
+    if (!shape_supported(bits_class_of(width), r.block, r.ipt))
+        return set_error(RT_ERR_UNSUPPORTED, "rt_counting_pass: no kernel for this shape");
+    const Layout L = make_layout(n, r, true);
+    void *ws = nullptr;
+    s = cached_workspace(L.total, stream, &ws);
+    if (s != RT_OK) return s;
+    launch_sort(const_cast<uint32_t *>(kin), const_cast<uint32_t *>(vin), static_cast<uint32_t>(n), r, L,
+                static_cast<char *>(ws), true, kout, vout, stream);
+    return finish_call(stream, "rt_counting_pass", error_word(ws, L));
+}
+
+extern "C" rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return RT_OK;
+    if (src == nullptr || dst == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_copy: NULL pointer");
+    if (bytes & 3u) return set_error(RT_ERR_INVALID_ARG, "rt_copy: bytes must be a multiple of 4");
+    const int cus = device_cu_count();
+    const bool v16 = !((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes) & 15u);
+    if (v16) {
+        const size_t words = bytes / 16;
+        hipLaunchKernelGGL(k_copy16, dim3(grid_for(words, 256 * 4, static_cast<uint32_t>(cus) * 16)), dim3(256), 0,
+                           stream, static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), words);
+    } else {
+        const size_t words = bytes / 4;
+        hipLaunchKernelGGL(k_copy4, dim3(grid_for(words, 256 * 4, static_cast<uint32_t>(cus) * 16)), dim3(256), 0,
+                           stream, static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), words);
+    }
+    return finish_call(stream, "rt_copy", nullptr);
+}
+
+extern "C" rt_status rt_generate(uint32_t *keys, uint32_t *vals, size_t n, const rt_gen_params *params,
+                                 uint32_t value_base, hipStream_t stream) {
+    if (n >= (static_cast<size_t>(1) << 32)) return set_error(RT_ERR_TOO_LARGE, "rt_generate: n = %zu", n);
+    if (params == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_generate: params is NULL");
+    if (params->dist > RT_DIST_ZIPF16) return set_error(RT_ERR_INVALID_ARG, "rt_generate: unknown dist %u", params->dist);
+    if (n == 0) return RT_OK;
+    if (keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_generate: keys is NULL");
+    GenArgs g{};
+    g.dist = params->dist;
+    g.value_base = value_base;
+    g.state = params->state;
+    memcpy(g.dictionary, params->dictionary, sizeof g.dictionary);
+    memcpy(g.thresholds, params->thresholds, sizeof g.thresholds);
+    const uint32_t grid = grid_for(n, 256 * 4, static_cast<uint32_t>(device_cu_count()) * 16);
+    hipLaunchKernelGGL(k_generate, dim3(grid), dim3(256), 0, stream, keys, vals, static_cast<uint32_t>(n), g);
+    return finish_call(stream, "rt_generate", nullptr);
+}
+
+extern "C" const char *rt_status_string(rt_status s) {
+    switch (s) {
+        case RT_OK: return "ok";
+        case RT_ERR_INVALID_ARG: return "invalid argument";
+        case RT_ERR_TOO_LARGE: return "too large";
+        case RT_ERR_OUT_OF_MEMORY: return "out of memory";
+        case RT_ERR_HIP: return "HIP error";
+        case RT_ERR_BUDGET: return "over the HBM budget";
+        case RT_ERR_UNSUPPORTED: return "unsupported";
+        case RT_ERR_CANCELLED: return "cancelled";
+        case RT_ERR_TIMEOUT: return "timed out";
+        case RT_ERR_NOT_FOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *rt_last_error(void) { return rt::last_error(); }
+
+extern "C" const char *rt_version(void) { return "rtsort 0.1 (gfx950)"; }

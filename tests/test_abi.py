@@ -1,0 +1,128 @@
+"""The C ABI library loads without a GPU, exports what include/rtsort.h
+declares, and rejects bad arguments before any device work."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_1008_2849_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtsort.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for must in ("rt_sort_keys", "rt_sort_pairs", "rt_sort_pairs_batched", "rt_sort_ex",
+                 "rt_server_create", "rt_server_submit", "rt_server_wait", "rt_server_stats"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    so = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(so, n)]
+    assert not missing, missing
+    # and the Python binding binds each of them
+    assert set(header_functions()) == set(_lib.SIGNATURES)
+
+
+@pytest.fixture(scope="module")
+def so():
+    return _lib.lib()
+
+
+def err(so):
+    return so.rt_last_error().decode()
+
+
+def test_argument_errors_are_synchronous(so):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
+    assert so.rt_sort_keys(None, 5, None) == _lib.RT_ERR_INVALID_ARG
+    assert "NULL" in err(so)
+    assert so.rt_sort_keys(fake, 1 << 32, None) == _lib.RT_ERR_TOO_LARGE
+    assert so.rt_sort_pairs(fake, None, 10, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs(fake, fake, 10, None) == _lib.RT_ERR_INVALID_ARG  # aliasing
+    assert "overlap" in err(so)
+    assert so.rt_sort_pairs(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1010), 10, None) \
+        == _lib.RT_ERR_INVALID_ARG  # partial overlap
+    assert so.rt_sort_keys(ctypes.c_void_p(0x1002), 10, None) == _lib.RT_ERR_INVALID_ARG  # misaligned
+    # n = 0 and n = 1 are no-ops, even with NULL pointers
+    assert so.rt_sort_keys(None, 0, None) == _lib.RT_OK
+    assert so.rt_sort_keys(None, 1, None) == _lib.RT_OK
+    assert so.rt_sort_pairs(None, None, 1, None) == _lib.RT_OK
+
+
+def test_config_validation(so):
+    fake_k, fake_v = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
+    for bits, want in [((8, 8, 8), _lib.RT_ERR_INVALID_ARG),        # sums to 24
+                       ((16, 16), _lib.RT_ERR_INVALID_ARG),          # too wide
+                       ((0, 16, 16), _lib.RT_ERR_INVALID_ARG),       # zero width
+                       ((4,) * 9, _lib.RT_ERR_INVALID_ARG)]:         # too many passes
+        c = _lib.RtConfig()
+        c.num_passes = len(bits)
+        for i, b in enumerate(bits[:8]):
+            c.digit_bits[i] = b
+        assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == want, bits
+    c = _lib.RtConfig()
+    c.num_passes = 4
+    for i in range(4):
+        c.digit_bits[i] = 8
+    c.block_threads, c.items_per_thread = 128, 7
+    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+
+
+def test_workspace_bytes(so):
+    assert so.rt_workspace_bytes(0, 1, None) == 0
+    assert so.rt_workspace_bytes(1, 1, None) == 0
+    n = 1 << 20
+    ws_pairs = so.rt_workspace_bytes(n, 1, None)
+    ws_keys = so.rt_workspace_bytes(n, 0, None)
+    # two temporaries per array (skipping may leave an odd pass count)
+    assert ws_pairs >= 4 * 4 * n and ws_keys >= 2 * 4 * n
+    assert ws_pairs - ws_keys == 2 * 4 * n
+    c = _lib.RtConfig()
+    c.num_passes = 4
+    for i in range(4):
+        c.digit_bits[i] = 8
+    c.flags = _lib.RT_FLAG_NO_SKIP  # even pass count, no skipping: one temporary
+    assert so.rt_workspace_bytes(n, 1, ctypes.byref(c)) < ws_pairs - 2 * 4 * n + 4096
+
+
+def test_status_strings(so):
+    for s in range(10):
+        assert so.rt_status_string(s)
+    assert b"gfx950" in so.rt_version()
+
+
+def test_tuning_table_roundtrip(so, tmp_path):
+    good = {"arch": "gfx950", "entries": [
+        {"op": "pairs", "min_n": 0, "max_n": 1 << 30, "digit_bits": [11, 11, 10],
+         "block": 256, "ipt": 32, "flags": 2},
+        {"op": "keys", "min_n": 0, "max_n": 1 << 40, "digit_bits": [8, 8, 8, 8],
+         "block": 512, "ipt": 16, "flags": 0}]}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(good))
+    assert so.rt_load_tuning(str(p).encode()) == _lib.RT_OK
+    c = _lib.RtConfig()
+    assert so.rt_tuned_config(1 << 20, 1, ctypes.byref(c)) == _lib.RT_OK
+    assert [c.digit_bits[i] for i in range(c.num_passes)] == [11, 11, 10]
+    assert (c.block_threads, c.items_per_thread, c.flags) == (256, 32, 2)
+    assert so.rt_tuned_config(1 << 20, 0, ctypes.byref(c)) == _lib.RT_OK
+    assert c.block_threads == 512
+    bad = {"entries": [{"op": "pairs", "min_n": 0, "max_n": 10, "digit_bits": [8, 8],
+                        "block": 256, "ipt": 16}]}
+    p.write_text(json.dumps(bad))
+    assert so.rt_load_tuning(str(p).encode()) == _lib.RT_ERR_INVALID_ARG
+    p.write_text("{not json")
+    assert so.rt_load_tuning(str(p).encode()) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_load_tuning(None) == _lib.RT_OK
+    assert so.rt_tuned_config(1 << 20, 1, ctypes.byref(c)) == _lib.RT_OK
+    assert c.num_passes == 4 and c.block_threads == 256

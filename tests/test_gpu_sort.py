@@ -1,0 +1,261 @@
+"""Parity of the HIP sort with the CPU oracle: bit-exact, on seeded inputs.
+
+Sizes span one to many tiles with ragged tails; the distributions are the
+skewed workloads (low-entropy AND-of-k keys, constant top byte, 16-key Zipf)
+plus sorted, reversed and all-equal arrays; every digit decomposition and
+tile shape the library compiles is exercised.  Values are original indices,
+so any instability or lost item shows up as a value mismatch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1008_2849_amd as rts
+from paper_1008_2849_amd import inputs
+from paper_1008_2849_amd.api import Config, FLAG_NO_SKIP, FLAG_NT_STORES
+from gpu_util import announce, sync, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TILE = 256 * 16
+SIZES = [0, 1, 2, 3, 63, 64, 65, 1000, TILE - 1, TILE, TILE + 1, 3 * TILE + 77, 100_003,
+         (1 << 20) - 1, 1 << 20, (1 << 20) + 1]
+
+
+def gpu_sort(keys, vals=None, cfg=None):
+    k = to_dev(keys)
+    v = None if vals is None else to_dev(vals)
+    if cfg is None:
+        if v is None:
+            rts.sort_keys(k)
+        else:
+            rts.sort_pairs(k, v)
+    else:
+        rts.sort_ex(k, v, cfg)
+    sync()
+    return to_host(k), (None if v is None else to_host(v))
+
+
+def assert_same(got, want, what=""):
+    gk, gv = got
+    wk, wv = want
+    assert gk.shape == wk.shape, what
+    if not np.array_equal(gk, wk):
+        bad = np.nonzero(gk != wk)[0]
+        raise AssertionError(f"{what}: keys differ at {bad.size} positions, first {bad[:5]}")
+    if wv is not None:
+        if not np.array_equal(gv, wv):
+            bad = np.nonzero(gv != wv)[0]
+            raise AssertionError(f"{what}: values differ at {bad.size} positions, first {bad[:5]}")
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_pairs_uniform_sizes(n):
+    announce(f"pairs uniform n={n}")
+    k = inputs.uniform_keys(n, 100 + n % 997)
+    v = inputs.index_values(n)
+    assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), f"n={n}")
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_keys_uniform_sizes(n):
+    announce(f"keys uniform n={n}")
+    k = inputs.uniform_keys(n, 200 + n % 991)
+    assert_same(gpu_sort(k), oracle.lsd_sort(k), f"n={n}")
+
+
+def _dist_cases(n):
+    idx = np.arange(n, dtype=np.uint32)
+    return {
+        "and2": inputs.and_keys(n, 2, 31),
+        "and4": inputs.and_keys(n, 4, 32),
+        "and8": inputs.and_keys(n, 8, 33),
+        "top_a5": inputs.top_byte_keys(n, 0xA5, 34),
+        "top_00": inputs.top_byte_keys(n, 0x00, 36),
+        "zipf16": inputs.zipf16_keys(n, 35),
+        "all_equal": np.full(n, 0x12345678, dtype=np.uint32),
+        "all_zero": np.zeros(n, dtype=np.uint32),
+        "all_ones": np.full(n, 0xFFFFFFFF, dtype=np.uint32),
+        "sorted": idx,
+        "reversed": idx[::-1].copy(),
+        "two_values": np.where(inputs.uniform_keys(n, 37) & 1, 0xFFFFFFFF, 0).astype(np.uint32),
+        "low_byte_only": (inputs.uniform_keys(n, 38) & 0xFF).astype(np.uint32),
+    }
+
+
+@pytest.mark.parametrize("dist", list(_dist_cases(8).keys()))
+def test_distributions_pairs(dist):
+    n = (1 << 20) + 123
+    announce(f"pairs dist={dist} n={n}")
+    k = _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), dist)
+
+
+@pytest.mark.parametrize("dist", ["and8", "top_a5", "zipf16", "all_equal"])
+def test_distributions_keys(dist):
+    n = (1 << 19) + 5
+    announce(f"keys dist={dist} n={n}")
+    k = _dist_cases(n)[dist]
+    assert_same(gpu_sort(k), oracle.lsd_sort(k), dist)
+
+
+WIDTHS = [(8, 8, 8, 8), (11, 11, 10), (10, 11, 11), (4,) * 8, (6, 6, 6, 6, 8), (11, 8, 8, 5),
+          (8, 8, 8, 4, 4), (11, 11, 6, 4)]
+SHAPES = [(256, 16), (256, 32), (512, 16)]
+
+
+@pytest.mark.parametrize("widths", WIDTHS, ids=["-".join(map(str, w)) for w in WIDTHS])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{b}x{i}" for b, i in SHAPES])
+def test_configs(widths, shape):
+    n = 300_001
+    announce(f"config widths={widths} shape={shape} n={n}")
+    k = inputs.and_keys(n, 2, 7)
+    v = inputs.index_values(n)
+    cfg = Config(widths, shape[0], shape[1], 0)
+    assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {shape}")
+
+
+@pytest.mark.parametrize("flags", [FLAG_NO_SKIP, FLAG_NT_STORES, FLAG_NO_SKIP | FLAG_NT_STORES])
+@pytest.mark.parametrize("dist", ["top_a5", "low_byte_only", "all_equal", "and4"])
+def test_flags(flags, dist):
+    n = 200_017
+    announce(f"flags={flags} dist={dist} n={n}")
+    k = _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    cfg = Config((8, 8, 8, 8), 256, 16, flags)
+    assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v), f"flags={flags} {dist}")
+    assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k), f"keys flags={flags} {dist}")
+
+
+@pytest.mark.parametrize("skip_pattern", range(16))
+def test_every_executed_pass_count(skip_pattern):
+    # byte p of every key is constant when bit p of skip_pattern is set, so
+    # each subset of passes (0..4 executed) is covered, odd counts included.
+    n = 50_000 + skip_pattern
+    announce(f"skip pattern {skip_pattern:04b} n={n}")
+    k = inputs.uniform_keys(n, 300 + skip_pattern)
+    for p in range(4):
+        if skip_pattern >> p & 1:
+            k = (k & ~np.uint32(0xFF << (8 * p))) | np.uint32((0x5A + p) << (8 * p))
+    v = inputs.index_values(n)
+    assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), f"pattern {skip_pattern}")
+    assert_same(gpu_sort(k), oracle.lsd_sort(k), f"keys pattern {skip_pattern}")
+
+
+def test_unaligned_views():
+    import torch
+    n = 123_457
+    for off in (1, 2, 3):
+        announce(f"unaligned view offset {off}")
+        k = inputs.uniform_keys(n, 40 + off)
+        v = inputs.index_values(n)
+        kb = to_dev(np.concatenate([np.zeros(off, np.uint32), k, np.zeros(5, np.uint32)]))
+        vb = to_dev(np.concatenate([np.zeros(off + 2, np.uint32), v, np.zeros(5, np.uint32)]))
+        kv, vv = kb[off:off + n], vb[off + 2:off + 2 + n]
+        rts.sort_pairs(kv, vv)
+        torch.cuda.synchronize()
+        got = (to_host(kv), to_host(vv))
+        assert_same(got, oracle.lsd_sort(k, v), f"offset {off}")
+        # guard words around the views are untouched
+        assert np.all(to_host(kb[:off]) == 0) and np.all(to_host(kb[off + n:]) == 0)
+        assert np.all(to_host(vb[:off + 2]) == 0) and np.all(to_host(vb[off + 2 + n:]) == 0)
+
+
+def test_histograms_match_oracle():
+    n = 1_000_003
+    k = inputs.and_keys(n, 2, 50)
+    for widths in [(8, 8, 8, 8), (11, 11, 10), (4,) * 8]:
+        announce(f"histograms {widths}")
+        h = rts.digit_histograms(to_dev(k), Config(widths, 256, 16))
+        sync()
+        h = h.cpu().numpy().view(np.uint32)
+        shift = 0
+        for p, w in enumerate(widths):
+            want = oracle.digit_histogram(k, shift, w)
+            assert np.array_equal(h[p, :1 << w].astype(np.uint64), want), (widths, p)
+            shift += w
+
+
+@pytest.mark.parametrize("shift,width", [(0, 8), (8, 8), (24, 8), (0, 11), (11, 11), (22, 10), (28, 4), (31, 1)])
+def test_single_counting_pass(shift, width):
+    import torch
+    n = 777_777
+    announce(f"counting pass shift={shift} width={width}")
+    k = inputs.uniform_keys(n, 60 + shift)
+    v = inputs.index_values(n)
+    kin, vin = to_dev(k), to_dev(v)
+    kout, vout = torch.empty_like(kin), torch.empty_like(vin)
+    rts.counting_pass(kin, vin, kout, vout, shift, width)
+    sync()
+    want = oracle.counting_pass(k, v, shift, width)
+    assert_same((to_host(kout), to_host(vout)), want, f"pass {shift}/{width}")
+    assert np.array_equal(to_host(kin), k)  # input untouched
+
+
+def test_repeat_is_deterministic():
+    n = (1 << 22) + 3
+    announce(f"determinism x20 n={n}")
+    k = inputs.uniform_keys(n, 70)
+    v = inputs.index_values(n)
+    want = oracle.lsd_sort(k, v)
+    import torch
+    kd0, vd0 = to_dev(k), to_dev(v)
+    for it in range(20):
+        kd, vd = kd0.clone(), vd0.clone()
+        rts.sort_pairs(kd, vd)
+        torch.cuda.synchronize()
+        assert_same((to_host(kd), to_host(vd)), want, f"repeat {it}")
+
+
+def test_explicit_workspace_and_streams():
+    import torch
+    n = 500_000
+    announce("explicit workspace, two streams")
+    cfg = Config((8, 8, 8, 8), 256, 16, 0)
+    need = rts.workspace_bytes(n, True, cfg)
+    assert need > 0
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rts.RtError):
+        rts.sort_ex(to_dev(np.arange(n, dtype=np.uint32)), to_dev(np.arange(n, dtype=np.uint32)), cfg, small)
+    cases = []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for i, s in enumerate(streams):
+        k = inputs.uniform_keys(n, 80 + i)
+        v = inputs.index_values(n)
+        kd, vd = to_dev(k), to_dev(v)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        rts.sort_ex(kd, vd, cfg, ws, stream=s)
+        cases.append((k, v, kd, vd, ws))
+    torch.cuda.synchronize()
+    for k, v, kd, vd, _ in cases:
+        assert_same((to_host(kd), to_host(vd)), oracle.lsd_sort(k, v), "stream case")
+
+
+def test_generator_matches_host_definition():
+    import torch
+    n = 300_000
+    for dist in (inputs.DIST_UNIFORM, inputs.DIST_AND4, inputs.DIST_ZIPF16):
+        announce(f"generator dist={dist}")
+        p = inputs.counter_params(dist, 5, 17 + dist)
+        kd = torch.empty(n, dtype=torch.int32, device="cuda")
+        vd = torch.empty(n, dtype=torch.int32, device="cuda")
+        rts.generate(kd, vd, p, value_base=1000)
+        sync()
+        assert np.array_equal(to_host(kd), inputs.counter_keys(p, n))
+        assert np.array_equal(to_host(vd), np.arange(1000, 1000 + n, dtype=np.uint32))
+
+
+def test_copy_probe():
+    import torch
+    n = (1 << 20) + 3
+    a = to_dev(inputs.uniform_keys(n, 90))
+    b = torch.zeros_like(a)
+    rts.copy(a, b)
+    sync()
+    assert torch.equal(a, b)
+    c = torch.zeros(n + 4, dtype=torch.int32, device="cuda")
+    rts.copy(a[1:], c[1:n])  # not 16-byte aligned
+    sync()
+    assert torch.equal(c[1:n], a[1:])
