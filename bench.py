@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the stable LSD radix sort on one MI355X.
+
+A step is one whole sort (upfront histograms, plan, every counting-sort
+pass) of 2^28 uniform u32 keys carrying u32 values equal to their original
+index, the inputs already resident in HBM.  Each timed step sorts its own
+pre-staged copy of the input, so no restore copy sits inside the timed
+region.  The run prints one JSON line on stdout: whole-sort throughput
+(Gkeys/s), per-pass HBM bandwidth against the chip's peak for the dominant
+kernel (the counting-sort pass), and the CPU oracle timed on this host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
+METRIC = "Gkeys/s and HBM GB/s per pass vs peak (2^28 pairs); batched p50/p99 latency"
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1008_2849_amd", "csrc", f)
+                  for f in ("rt_kernels.h", "rt_internal.h")]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(digest: str):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    or None when that summary predates the current kernel source."""
+    path = os.path.join(PROFILES, "onesweep_pass_pairs_256m_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(keys_h, vals_h, out_k, out_v):
+    """Time the CPU oracle (single thread) on the same input; its output also
+    checks the GPU result bit for bit."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    rk, rv = oracle.lsd_sort(keys_h, vals_h)
+    dt = time.perf_counter() - t0
+    same = bool(np.array_equal(rk, out_k) and np.array_equal(rv, out_v))
+    return dt, same
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28, help="problem size (2^28 is the measured workload)")
+    ap.add_argument("--bits", default="", help="digit widths, e.g. 11,11,10 (default: tuned)")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--ipt", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build sorts on one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_1008_2849_amd as rts
+    from paper_1008_2849_amd import inputs
+    from paper_1008_2849_amd._lib import (RT_KIND_COPY, RT_KIND_HISTOGRAM, RT_KIND_PASS, RT_KIND_SCAN,
+                                          RT_KIND_UPSWEEP)
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    K, W = args.steps, args.warmup
+
+    tuned = rts.tuned_config(n, True)
+    cfg = rts.Config(tuple(int(x) for x in args.bits.split(",")) if args.bits else tuned.digit_bits,
+                     args.block or tuned.block_threads, args.ipt or tuned.items_per_thread,
+                     args.flags or tuned.flags)
+    log(f"n=2^{args.log2n} pairs, config {cfg}, steps {K}, warmup {W}")
+
+    t = time.perf_counter()
+    keys_h = inputs.uniform_keys(n, inputs.SEED_PAIRS_256M)
+    vals_h = inputs.index_values(n)
+    k0 = torch.from_numpy(keys_h.view(np.int32)).to(dev)
+    v0 = torch.from_numpy(vals_h.view(np.int32)).to(dev)
+    # one private copy of the input per step, all resident before timing
+    slots = [(k0.clone(), v0.clone()) for _ in range(K + W)]
+    ws = torch.empty(rts.workspace_bytes(n, True, cfg), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"inputs staged in HBM ({(K + W) * 8 * n / 2**30:.1f} GiB) in {time.perf_counter() - t:.1f}s")
+
+    for i in range(W):
+        rts.sort_ex(slots[i][0], slots[i][1], cfg, ws)
+    torch.cuda.synchronize()
+
+    rts.profile_start(max_marks=16 * K + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        rts.sort_ex(slots[i][0], slots[i][1], cfg, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    marks = rts.profile_stop(capacity=16 * K + 16)
+    ms_per_step = 1e3 * wall / K
+    gkeys = n / (wall / K) / 1e9
+    log(f"{K} sorts in {wall * 1e3:.2f} ms: {ms_per_step:.3f} ms/sort, {gkeys:.2f} Gkeys/s")
+
+    def by_kind(base_kind):
+        out = {}
+        for kind, ms in marks:
+            if base_kind <= kind < base_kind + 8:
+                out.setdefault(kind - base_kind, []).append(ms)
+        return {p: float(np.mean(v)) for p, v in sorted(out.items())}
+
+    down = by_kind(RT_KIND_PASS)
+    up = by_kind(RT_KIND_UPSWEEP)
+    scan = by_kind(RT_KIND_SCAN)
+    hist_ms = [ms for kind, ms in marks if kind == RT_KIND_HISTOGRAM]
+    pass_bytes = 16.0 * n  # the pass must read key + value and write key + value
+    per_pass = []
+    for p in sorted(down):
+        total = down[p] + up.get(p, 0.0) + scan.get(p, 0.0)
+        per_pass.append({"pass": p, "ms": round(total, 4), "upsweep_ms": round(up.get(p, 0.0), 4),
+                         "scan_ms": round(scan.get(p, 0.0), 4), "downsweep_ms": round(down[p], 4),
+                         "GB/s": round(pass_bytes / total / 1e6, 1),
+                         "frac_of_peak": round(pass_bytes / total / 1e6 / PEAK_HBM_GBPS, 4)})
+    all_down = [ms for kind, ms in marks if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+    dom_ms = float(np.mean(all_down)) if all_down else float("nan")
+    achieved = pass_bytes / dom_ms / 1e6
+    hist = None
+    if hist_ms:
+        h = float(np.mean(hist_ms))
+        hist = {"ms": round(h, 4), "GB/s": round(4.0 * n / h / 1e6, 1)}
+
+    # parity of the last timed output, by the properties that fix a stable sort
+    ko, vo = slots[W + K - 1]
+    k64 = ko.to(torch.int64) & 0xFFFFFFFF
+    props = bool((k64[1:] >= k64[:-1]).all().item())
+    vl = vo.to(torch.int64)
+    props &= bool(((vl >= 0) & (vl < n)).all().item())
+    seen = torch.zeros(n, dtype=torch.bool, device=dev)
+    seen[vl] = True
+    props &= bool(seen.all().item())
+    props &= bool(torch.equal(k0[vl], ko))
+    eq = k64[1:] == k64[:-1]
+    props &= bool((vl[1:][eq] > vl[:-1][eq]).all().item())
+    del seen, k64, vl, eq
+
+    # achievable copy bandwidth: 2 GiB read + 2 GiB written
+    src = k0.view(torch.int32)
+    big_src = torch.cat([k0, v0])
+    big_dst = torch.empty_like(big_src)
+    rts.copy(big_src, big_dst)
+    torch.cuda.synchronize()
+    rts.profile_start(64)
+    for _ in range(5):
+        rts.copy(big_src, big_dst)
+    torch.cuda.synchronize()
+    cm = [ms for kind, ms in rts.profile_stop(64) if kind == RT_KIND_COPY]
+    copy_gbps = 2 * big_src.numel() * 4 / float(np.median(cm)) / 1e6 if cm else None
+    del big_src, big_dst, src
+
+    digest = kernel_source_digest()
+    traffic = traffic_from_profiles(digest)
+
+    out_k = to_np = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        out_k = ko.cpu().numpy().view(np.uint32)
+        out_v = vo.cpu().numpy().view(np.uint32)
+        log("timing the CPU oracle on the same input (single thread)")
+        dt, same = cpu_baseline(keys_h, vals_h, out_k, out_v)
+        cpu = {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload: 2^{args.log2n} uniform pairs (seed {inputs.SEED_PAIRS_256M}), "
+                         f"one sort, {dt:.1f} s, host has {os.cpu_count()} logical CPUs",
+               "matches_gpu_bit_exact": same}
+        log(f"oracle {dt:.1f}s, GPU output {'==' if same else '!='} oracle")
+
+    line = {
+        "metric": METRIC,
+        "value": round(gkeys, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"pairs_2^{args.log2n}_uniform", "n": n, "values": "original index",
+                   "digit_bits": list(cfg.digit_bits), "block_threads": cfg.block_threads,
+                   "items_per_thread": cfg.items_per_thread, "flags": cfg.flags},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_downsweep (scatter of one counting-sort pass)",
+                     "algorithmic_bytes_per_launch": pass_bytes,
+                     "avg_launch_ms": round(dom_ms, 4)},
+        "cpu_baseline": cpu,
+        "per_pass": per_pass,
+        "histogram": hist,
+        "copy_peak_GBps": None if copy_gbps is None else round(copy_gbps, 1),
+        "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
+        "parity_properties_ok": props,
+        "kernel_source_digest": digest,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if props and (cpu is None or cpu["matches_gpu_bit_exact"]) else 3
+
+
+if __name__ == "__main__":
+    sys.exit(main())

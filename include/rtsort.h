@@ -254,6 +254,30 @@ rt_status rt_load_tuning(const char *json_path);
 /* Tuned configuration the library would use for n items. */
 rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
 
+/*
+ * Kernel timing, for measurement.  Between rt_profile_start and
+ * rt_profile_stop every kernel the library launches is followed by a HIP
+ * event recorded on the launch's stream (one more event precedes each
+ * call's first kernel), so a kernel's duration is the time between the
+ * event before it and the one after it on that stream.  At most max_marks
+ * events are recorded; later launches go unrecorded.  rt_profile_stop waits
+ * for the events, writes up to `capacity` (kind, milliseconds) pairs into the
+ * host arrays kinds/ms in launch order, stores their number in *count and
+ * frees the events.  Kinds: RT_KIND_* below.
+ */
+#define RT_KIND_FILL 1u
+#define RT_KIND_HISTOGRAM 2u
+#define RT_KIND_PLAN 3u
+#define RT_KIND_COPY_BACK 4u
+#define RT_KIND_COPY 5u
+#define RT_KIND_GENERATE 6u
+#define RT_KIND_SEGMENTED 7u
+#define RT_KIND_PASS 16u    /* + pass index: the pass's scatter (downsweep) */
+#define RT_KIND_UPSWEEP 32u /* + pass index: the pass's per-chunk digit counts */
+#define RT_KIND_SCAN 48u    /* + pass index: the pass's per-chunk offsets */
+rt_status rt_profile_start(uint32_t max_marks);
+rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count);
+
 const char *rt_status_string(rt_status s);
 const char *rt_last_error(void);
 const char *rt_version(void);

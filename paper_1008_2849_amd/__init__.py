@@ -12,7 +12,7 @@ from __future__ import annotations
 __all__ = [
     "Config", "sort_keys", "sort_pairs", "sort_ex", "sort_pairs_batched", "workspace_bytes",
     "digit_histograms", "counting_pass", "copy", "generate", "load_tuning", "tuned_config",
-    "version", "Server", "RtError",
+    "version", "Server", "RtError", "profile_start", "profile_stop",
 ]
 
 

@@ -27,6 +27,17 @@ RT_MAX_DIGIT_BITS = 11
 RT_FLAG_NO_SKIP = 0x1
 RT_FLAG_NT_STORES = 0x2
 
+RT_KIND_FILL = 1
+RT_KIND_HISTOGRAM = 2
+RT_KIND_PLAN = 3
+RT_KIND_COPY_BACK = 4
+RT_KIND_COPY = 5
+RT_KIND_GENERATE = 6
+RT_KIND_SEGMENTED = 7
+RT_KIND_PASS = 16
+RT_KIND_UPSWEEP = 32
+RT_KIND_SCAN = 48
+
 
 class RtConfig(ctypes.Structure):
     _fields_ = [
@@ -82,6 +93,9 @@ SIGNATURES = {
     "rt_server_release": (ctypes.c_int, [vp, u64]),
     "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),
     "rt_server_destroy": (ctypes.c_int, [vp]),
+    "rt_profile_start": (ctypes.c_int, [u32]),
+    "rt_profile_stop": (ctypes.c_int, [ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float), u32,
+                                       ctypes.POINTER(u32)]),
     "rt_load_tuning": (ctypes.c_int, [ctypes.c_char_p]),
     "rt_tuned_config": (ctypes.c_int, [sz, ctypes.c_int, ctypes.POINTER(RtConfig)]),
     "rt_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -199,3 +199,17 @@ def tuned_config(n: int, with_values: bool) -> Config:
 
 def version() -> str:
     return lib().rt_version().decode()
+
+
+def profile_start(max_marks: int = 4096) -> None:
+    """Start recording a HIP event after every kernel the library launches."""
+    check(lib().rt_profile_start(int(max_marks)), "rt_profile_start")
+
+
+def profile_stop(capacity: int = 4096):
+    """Stop recording; returns [(kind, milliseconds)] per launch in order."""
+    kinds = (ctypes.c_uint32 * capacity)()
+    ms = (ctypes.c_float * capacity)()
+    count = ctypes.c_uint32(0)
+    check(lib().rt_profile_stop(kinds, ms, capacity, ctypes.byref(count)), "rt_profile_stop")
+    return [(int(kinds[i]), float(ms[i])) for i in range(count.value)]

@@ -11,10 +11,12 @@
 // classes so that any mix of digit widths can use any shape.
 #define RT_FOR_EACH_SHAPE(X) \
     X(8, 256, 16)            \
-    X(8, 256, 32)            \
     X(8, 512, 16)            \
+    X(8, 1024, 8)            \
+    X(8, 1024, 12)           \
+    X(8, 1024, 16)           \
     X(11, 256, 16)           \
-    X(11, 256, 32)           \
+    X(11, 512, 8)            \
     X(11, 512, 16)
 
 namespace rt {
@@ -36,15 +38,14 @@ struct Layout {
     size_t status_pass[kMaxPasses];
     size_t t1k, t1v, t2k, t2v;
     size_t total;
-    uint32_t tiles;
-    bool wide_status;
+    uint32_t tiles;     // tiles per pass
+    bool wide_status;   // n >= 2^30: 64-bit lookback words and byte offsets
 };
 
 rt_status set_error(rt_status s, const char *fmt, ...);
 const char *last_error();
 bool debug_sync_enabled();
-rt_status finish_call(hipStream_t stream, const char *what, const uint32_t *device_error_word);
-const uint32_t *error_word(const void *ws, const Layout &L);
+rt_status finish_call(hipStream_t stream, const char *what);
 int device_cu_count();
 
 bool shape_supported(int bits_class, int block, int ipt);
@@ -53,6 +54,10 @@ Layout make_layout(size_t n, const Resolved &r, bool direct);
 rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);
 void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
                  bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream);
+
+// Kernel timing marks (see rt_profile_start); cheap no-ops when disabled.
+void prof_begin(hipStream_t stream);
+void prof_mark(hipStream_t stream, uint32_t kind);
 
 // Tuned configuration for n items (from the loaded table, else built in).
 void tuned_config(size_t n, int with_values, rt_config *out);

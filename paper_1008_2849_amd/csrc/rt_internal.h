@@ -14,15 +14,6 @@ constexpr int kMaxPasses = RT_MAX_PASSES;
 constexpr int kMaxBits = RT_MAX_DIGIT_BITS;
 constexpr int kMaxRadix = 1 << kMaxBits;
 
-// Lookback status word: two flag bits on top of the running count.
-// 32-bit words hold counts < 2^30; larger sorts use 64-bit words.
-constexpr uint32_t kFlagAgg = 1u;   // count of this tile alone
-constexpr uint32_t kFlagIncl = 2u;  // count of this tile and all earlier ones
-
-// Device-side error bits (a word in the workspace next to the tile counters).
-constexpr uint32_t kErrLookbackTimeout = 1u;
-constexpr uint32_t kLookbackSpinLimit = 1u << 22;  // fruitless polls (~seconds)
-
 // Source/destination of one executed counting-sort pass.  Written on the
 // device by the planning kernel once the histograms are known, so that pass
 // skipping and the choice of ping-pong buffers need no host round trip.

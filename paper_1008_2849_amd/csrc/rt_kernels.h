@@ -4,17 +4,20 @@
 // of every pass at once; a planning kernel that turns them into each digit's
 // first output slot (exclusive prefix sum), marks passes whose digit is
 // constant as skipped and picks source/destination buffers on the device;
-// then one "onesweep" kernel per pass.  Each onesweep tile ranks its items
-// stably with wave64 ballots, learns the global offset of each digit from
-// the tiles before it by decoupled lookback, gathers its items by digit in
-// LDS and writes every digit run to HBM as a contiguous burst.
+// then one "onesweep" kernel per executed pass.  Each onesweep block takes
+// the next tile of the pass input, ranks its items stably with wave64
+// ballots, publishes its per-digit counts, learns from the tiles before it
+// (decoupled lookback) where each of its digit runs starts, gathers the tile
+// by digit in LDS and writes every digit run to HBM as one burst of
+// consecutive addresses.
 //
 // The counting-sort pass is the naive algorithm of Section 3 of Wassenberg &
 // Sanders (histogram, exclusive prefix sum, scatter with increment); the pass
 // order and stability requirement are Section 4's LSD radix sort.  The LDS
 // staging plays the part of Section 2's software write-combining buffers:
 // output leaves the chip in runs of consecutive addresses instead of one
-// scattered word per item.
+// scattered word per item, and the tiles are large (16K items) so that a
+// digit's run is 256 bytes long on average for uniform keys.
 #include "rt_internal.h"
 
 namespace rt {
@@ -23,25 +26,55 @@ namespace rt {
 // wave64 helpers
 // ---------------------------------------------------------------------------
 
-// Number of set bits of m in lanes below this one.
-__device__ __forceinline__ uint32_t popc_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-}
-
 // Lanes of the wave holding the same BITS-bit digit as this lane: one ballot
 // per digit bit, keeping the lanes that agree with this lane on that bit.
+// The whole wave must be active.  Per bit: the bit sign-extended to 0 or ~0,
+// its ballot, and one three-input logic op per mask half.
 template <int BITS>
-__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
-    uint64_t peers = __builtin_amdgcn_read_exec();
+__device__ __forceinline__ void match_digit(uint32_t d, uint32_t &lo, uint32_t &hi) {
+    int s[BITS];
+    uint64_t set[BITS];
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const uint32_t bit = (d >> b) & 1u;
-        const uint64_t set = __builtin_amdgcn_ballot_w64(bit != 0);
-        const uint64_t flip = 0ull - static_cast<uint64_t>(bit ^ 1u);  // all ones when bit == 0
-        peers &= set ^ flip;
+        s[b] = __builtin_amdgcn_sbfe(static_cast<int>(d), b, 1);  // 0 or -1
+        // Keep s opaque so the ballot compares it directly instead of
+        // re-deriving the bit with extra shifts.
+        asm volatile("" : "+v"(s[b]));
     }
-    return peers;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) set[b] = __builtin_amdgcn_ballot_w64(s[b] != 0);
+    lo = ~0u;
+    hi = ~0u;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        // 0x90 = a & ~(b ^ c): keep the lanes whose bit b equals ours
+        lo = __builtin_amdgcn_bitop3_b32(lo, static_cast<uint32_t>(set[b]), static_cast<uint32_t>(s[b]), 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, static_cast<uint32_t>(set[b] >> 32), static_cast<uint32_t>(s[b]),
+                                         0x90);
+    }
+}
+
+// Global-memory views: address space 1 lets the compiler use global (not
+// flat) instructions, with a uniform 64-bit base and a 32-bit lane offset.
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) char g_char;
+
+// Element i of a global u32 array.  SMALL: i < 2^30, so the byte offset fits
+// in 32 bits.
+template <bool SMALL>
+__device__ __forceinline__ const g_u32 *gelem(const uint32_t *base, size_t i) {
+    // C-style casts: clang turns them into address-space casts
+    if constexpr (SMALL)
+        return (const g_u32 *)((const g_char *)base + static_cast<uint32_t>(i * 4u));
+    else
+        return (const g_u32 *)base + i;
+}
+template <bool SMALL>
+__device__ __forceinline__ g_u32 *gelem(uint32_t *base, size_t i) {
+    if constexpr (SMALL)
+        return (g_u32 *)((g_char *)base + static_cast<uint32_t>(i * 4u));
+    else
+        return (g_u32 *)base + i;
 }
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
@@ -67,8 +100,22 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_
     return before + x - v;
 }
 
+template <bool NT>
+__device__ __forceinline__ void store_g(g_u32 *p, uint32_t v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Sleep roughly `rounds` * 64 clocks (s_sleep takes an immediate).
+__device__ __forceinline__ void backoff(uint32_t rounds) {
+    for (uint32_t i = 0; i < rounds; ++i) __builtin_amdgcn_s_sleep(1);
+}
+
 // ---------------------------------------------------------------------------
-// lookback status words
+// lookback status words: two flag bits over the running count.  32-bit
+// words hold counts < 2^30; larger sorts use 64-bit words.
 // ---------------------------------------------------------------------------
 
 template <typename S>
@@ -90,6 +137,9 @@ struct Status<uint64_t> {
     __device__ static uint32_t count(uint64_t s) { return static_cast<uint32_t>(s); }
 };
 
+constexpr uint32_t kFlagAgg = 1u;   // count of this tile alone
+constexpr uint32_t kFlagIncl = 2u;  // count of this tile and all earlier ones
+
 template <typename S>
 __device__ __forceinline__ S status_load(const S *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -100,12 +150,17 @@ __device__ __forceinline__ void status_store(S *p, S v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool NT>
-__device__ __forceinline__ void store_u32(uint32_t *p, uint32_t v) {
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
+// Adds one to counter h[d] for every active lane with ok set, in LDS.  The
+// lanes that share the first lane's digit are counted with one add, which
+// keeps heavily skewed inputs (most keys with the same digit) from turning
+// into 64-way collisions on one LDS address.  The whole wave must be active.
+__device__ __forceinline__ void wave_count(uint32_t *h, uint32_t d, bool ok) {
+    const uint32_t first = __builtin_amdgcn_readfirstlane(d);
+    const bool same = ok && d == first;
+    const uint64_t same_mask = __builtin_amdgcn_ballot_w64(same);
+    if (ok && !same) atomicAdd(&h[d], 1u);
+    if ((threadIdx.x & 63u) == 0 && same_mask != 0)
+        atomicAdd(&h[first], static_cast<uint32_t>(__popcll(same_mask)));
 }
 
 // ---------------------------------------------------------------------------
@@ -130,51 +185,48 @@ struct HistArgs {
     uint32_t total_bins;
 };
 
-__device__ __forceinline__ void hist_add(uint32_t *s_h, const HistArgs &ha, uint32_t k) {
-#pragma unroll
-    for (int p = 0; p < kMaxPasses; ++p)
-        if (p < static_cast<int>(ha.num_passes))
-            atomicAdd(&s_h[ha.lds_offset[p] + ((k >> ha.shift[p]) & ha.mask[p])], 1u);
-}
-
-// Counts per pass and digit into hist[p * kMaxRadix + d] (which must start at
-// zero); also clears `zero_words` 16-byte words at zero_ptr (the lookback
-// state of the passes that follow).
+// Counts per pass and digit into hist[p * kMaxRadix + d], which must start at
+// zero.  Each wave keeps its own LDS copy of the counters; keys are read in
+// 256-byte wave slots.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict__ keys, uint32_t n,
-                                                     HistArgs ha, uint32_t *__restrict__ hist,
-                                                     uint4 *__restrict__ zero_ptr, size_t zero_words) {
-    extern __shared__ uint32_t s_h[];
+                                                     HistArgs ha, uint32_t *__restrict__ hist) {
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int U = 8;  // slots in flight per lane
+    extern __shared__ uint32_t s_h[];  // WAVES copies of total_bins counters
     const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < ha.total_bins; i += BLOCK) s_h[i] = 0u;
-
-    const size_t gthreads = static_cast<size_t>(gridDim.x) * BLOCK;
-    const size_t gid = static_cast<size_t>(blockIdx.x) * BLOCK + tid;
-    for (size_t i = gid; i < zero_words; i += gthreads) zero_ptr[i] = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    for (uint32_t i = tid; i < WAVES * ha.total_bins; i += BLOCK) s_h[i] = 0u;
     __syncthreads();
+    uint32_t *h = s_h + wave * ha.total_bins;
 
-    // split into an unaligned head, a 16-byte-aligned body and a tail
-    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(keys) >> 2) & 3u);
-    const uint32_t head = mis ? min(4u - mis, n) : 0u;
-    const uint32_t nvec = (n - head) >> 2;
-    const uint32_t tail_start = head + (nvec << 2);
-    if (blockIdx.x == 0 && tid < head) hist_add(s_h, ha, keys[tid]);
-    if (blockIdx.x == 0 && tail_start + tid < n) hist_add(s_h, ha, keys[tail_start + tid]);
-    const uint4 *body = reinterpret_cast<const uint4 *>(keys + head);
-    for (size_t i = gid; i < nvec; i += gthreads) {
-        const uint4 q = body[i];
-        hist_add(s_h, ha, q.x);
-        hist_add(s_h, ha, q.y);
-        hist_add(s_h, ha, q.z);
-        hist_add(s_h, ha, q.w);
+    const size_t wave_span = static_cast<size_t>(64) * U;
+    const size_t stride = static_cast<size_t>(gridDim.x) * WAVES * wave_span;
+    for (size_t base = (static_cast<size_t>(blockIdx.x) * WAVES + wave) * wave_span; base < n; base += stride) {
+        uint32_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + u * 64 + lane;
+            k[u] = i < n ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = base + u * 64 + lane < n;
+#pragma unroll
+            for (int p = 0; p < kMaxPasses; ++p)
+                if (p < static_cast<int>(ha.num_passes))
+                    wave_count(h + ha.lds_offset[p], (k[u] >> ha.shift[p]) & ha.mask[p], ok);
+        }
     }
     __syncthreads();
-    for (uint32_t p = 0; p < ha.num_passes; ++p) {
-        const uint32_t bins = ha.mask[p] + 1u;
-        for (uint32_t d = tid; d < bins; d += BLOCK) {
-            const uint32_t c = s_h[ha.lds_offset[p] + d];
-            if (c) atomicAdd(&hist[p * kMaxRadix + d], c);
-        }
+    for (uint32_t i = tid; i < ha.total_bins; i += BLOCK) {
+        uint32_t c = 0;
+        for (int w = 0; w < WAVES; ++w) c += s_h[w * ha.total_bins + i];
+        if (c == 0) continue;
+        uint32_t p = 0;
+        while (p + 1 < ha.num_passes && i >= ha.lds_offset[p + 1]) ++p;
+        atomicAdd(&hist[p * kMaxRadix + (i - ha.lds_offset[p])], c);
     }
 }
 
@@ -183,14 +235,17 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
 // ---------------------------------------------------------------------------
 
 // One block of 256 threads; thread t covers bins [8t, 8t + 8) of a pass.
+// Also clears the tile counters of the passes.
 __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__restrict__ hist,
                                               uint32_t *__restrict__ base, SortPlan *__restrict__ plan,
                                               uint32_t *__restrict__ tile_counters, uint32_t direct) {
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_constant[kMaxPasses];
     const uint32_t tid = threadIdx.x;
-    if (tid < kMaxPasses) s_constant[tid] = 0u;
-    if (tid <= kMaxPasses) tile_counters[tid] = 0u;  // counters and the error word
+    if (tid < kMaxPasses) {
+        s_constant[tid] = 0u;
+        tile_counters[tid] = 0u;
+    }
     __syncthreads();
     for (uint32_t p = 0; p < a.num_passes; ++p) {
         const uint32_t bins = 1u << a.width[p];
@@ -205,9 +260,8 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__rest
         }
         uint32_t run = block_exclusive_sum<256>(sum, s_wsum);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint32_t d = tid * 8 + i;
-            if (d < bins) base[p * kMaxRadix + d] = run;
+        for (int i = 0; i < 8; ++i) {  // bins past the digit's range start at n
+            base[p * kMaxRadix + tid * 8 + i] = run;
             run += c[i];
         }
         __syncthreads();  // s_wsum is reused by the next pass
@@ -266,14 +320,78 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__rest
 // onesweep counting-sort pass
 // ---------------------------------------------------------------------------
 
-// One tile = BLOCK * IPT consecutive items.  Wave w of the tile owns items
-// [w * 64 * IPT, (w + 1) * 64 * IPT) of it; lane l holds item j * 64 + l of
-// that range in slot j, so slot-by-slot, lane-by-lane processing follows
-// input order, which is what makes the ranking stable.
+// Decoupled lookback for one digit of one tile: the sum of that digit's
+// counts over all earlier tiles.  Earlier tiles publish an aggregate (their
+// own count) and later an inclusive prefix; the walk goes back from the
+// previous tile, adding aggregates, until it reaches an inclusive prefix.
+// The status words of kLookbackBatch earlier tiles are loaded at once.
+//
+// Every earlier tile publishes within microseconds of starting, and a tile
+// only waits on tiles that were claimed (and so started) before it.  The
+// wait is still bounded: after kLookbackSpinLimit fruitless polls the walk
+// raises the error flag and stops, which leaves a wrong result rather than
+// a GPU that never finishes.
+constexpr int kLookbackBatch = 8;
+constexpr uint32_t kLookbackSpinLimit = 1u << 22;
+constexpr uint32_t kErrLookbackTimeout = 1u;
+
+template <typename S>
+__device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status, int32_t tile, uint32_t digit,
+                                                   int radix, uint32_t *__restrict__ error_flag) {
+    using St = Status<S>;
+    uint32_t excl = 0;
+    int32_t at = tile - 1;  // the nearest tile not yet accounted for
+    uint32_t idle = 0, nap = 1;
+    while (at >= 0) {
+        S w[kLookbackBatch];
+#pragma unroll
+        for (int b = 0; b < kLookbackBatch; ++b)
+            w[b] = (at - b >= 0) ? status_load(status + static_cast<size_t>(at - b) * radix + digit) : S(0);
+        bool finished = false, stalled = false;
+        int32_t consumed = 0;
+#pragma unroll
+        for (int b = 0; b < kLookbackBatch; ++b) {
+            if (finished || stalled || at - b < 0) continue;
+            const uint32_t f = St::flag(w[b]);
+            if (f == 0u) {
+                stalled = true;  // not published yet: resume from this tile
+            } else {
+                excl += St::count(w[b]);
+                ++consumed;
+                if (f == kFlagIncl) finished = true;
+            }
+        }
+        if (finished) break;
+        at -= consumed;
+        if (stalled && consumed == 0) {
+            backoff(nap);
+            nap = nap < 16 ? nap * 2 : 16;
+            if (++idle > kLookbackSpinLimit) {
+                atomicOr(error_flag, kErrLookbackTimeout);
+                break;
+            }
+        } else {
+            nap = 1;
+        }
+    }
+    return excl;
+}
+
+// One block per tile of BLOCK * IPT consecutive items, claimed in order from
+// an atomic counter (so a block only ever waits on tiles claimed before it,
+// by blocks that are already running).  Wave w of the tile owns items
+// [w * 64 * IPT, (w + 1) * 64 * IPT) of it and lane l holds item j * 64 + l
+// of that range in slot j, so slot-by-slot, lane-by-lane processing follows
+// input order, which makes the ranking stable.
+//
+// Phases: load keys and values -> rank every item inside its wave (ballot
+// match + per-wave digit counters in LDS) -> per-digit tile counts,
+// published as this tile's aggregate -> tile-local digit offsets -> gather
+// keys and values by digit in LDS -> lookback for the global offset of each
+// digit -> write every digit run to consecutive output addresses.
 template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S>
-__global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass,
-                                                    uint32_t n, const uint32_t *__restrict__ pass_base,
-                                                    S *__restrict__ status,
+__global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
+                                                    const uint32_t *__restrict__ pass_base, S *__restrict__ status,
                                                     uint32_t *__restrict__ tile_counter,
                                                     uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
@@ -282,13 +400,17 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     constexpr int WAVE_ITEMS = 64 * IPT;
     constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;  // digits per owning thread
     constexpr int DT = RADIX / R;                            // owning threads
+    constexpr bool SMALL = sizeof(S) == 4;                    // n < 2^30
     using St = Status<S>;
 
     const PassPlan pp = plan->pass[pass];
     if (!pp.active) return;
 
-    __shared__ uint32_t s_stage[TILE];
-    __shared__ uint32_t s_whist[WAVES * RADIX];
+    __shared__ uint32_t s_stage_k[TILE];
+    __shared__ uint32_t s_stage_v[VALS ? TILE : 1];
+    // per-wave digit counters, then a 64-word scratch row per wave that
+    // absorbs the counter writes of non-leader lanes
+    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
     __shared__ uint32_t s_gbase[RADIX];
     __shared__ uint32_t s_wsum[WAVES];
     __shared__ uint32_t s_tile;
@@ -296,56 +418,59 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
-    if (tid == 0) s_tile = atomicAdd(tile_counter + pass, 1u);
-    for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0u;
-    __syncthreads();
-
-    const uint32_t tile = s_tile;
     const uint32_t shift = pp.shift;
-    const uint32_t mask = (1u << pp.width) - 1u;
+    const uint32_t width = pp.width;
+    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;  // tile index of this lane's slot 0
+    uint32_t *wh = s_whist + wave * RADIX;
+    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
+
+    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;  // this wave's counters
+    if (tid == 0) s_tile = atomicAdd(tile_counter + pass, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
     const size_t tile_base = static_cast<size_t>(tile) * TILE;
     if (tile_base >= n) return;  // only if the tile counter was not cleared
     const uint32_t valid = static_cast<uint32_t>(min(static_cast<size_t>(TILE), n - tile_base));
     const bool full = valid == static_cast<uint32_t>(TILE);
-    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;  // tile index of this lane's slot 0
 
-    // ---- load (coalesced: each slot of a wave is 256 consecutive bytes)
+    // ---- load (each slot of a wave is 256 consecutive bytes)
     uint32_t key[IPT];
     uint32_t val[VALS ? IPT : 1];
-    {
-        const uint32_t *sk = pp.src_k + tile_base + wslot0;
-        const uint32_t *sv = VALS ? pp.src_v + tile_base + wslot0 : nullptr;
-        if (full) {
+    if (full) {
 #pragma unroll
-            for (int j = 0; j < IPT; ++j) key[j] = sk[j * 64];
-            if constexpr (VALS) {
+        for (int j = 0; j < IPT; ++j) key[j] = *gelem<SMALL>(pp.src_k, tile_base + wslot0 + j * 64);
+        if constexpr (VALS) {
 #pragma unroll
-                for (int j = 0; j < IPT; ++j) val[j] = sv[j * 64];
-            }
-        } else {
+            for (int j = 0; j < IPT; ++j) val[j] = *gelem<SMALL>(pp.src_v, tile_base + wslot0 + j * 64);
+        }
+    } else {
 #pragma unroll
-            for (int j = 0; j < IPT; ++j) key[j] = (wslot0 + j * 64 < valid) ? sk[j * 64] : 0u;
-            if constexpr (VALS) {
+        for (int j = 0; j < IPT; ++j)
+            key[j] = (wslot0 + j * 64 < valid) ? *gelem<SMALL>(pp.src_k, tile_base + wslot0 + j * 64) : 0u;
+        if constexpr (VALS) {
 #pragma unroll
-                for (int j = 0; j < IPT; ++j) val[j] = (wslot0 + j * 64 < valid) ? sv[j * 64] : 0u;
-            }
+            for (int j = 0; j < IPT; ++j)
+                val[j] = (wslot0 + j * 64 < valid) ? *gelem<SMALL>(pp.src_v, tile_base + wslot0 + j * 64) : 0u;
         }
     }
 
-    // ---- stable rank inside the wave, per-wave digit counts in LDS
-    // Items past the end of the array take the last digit, so they rank
-    // behind every real item of the tile and are never written.
+    // ---- stable rank inside the wave, per-wave digit counts in LDS.
+    // Items past the end take the last digit, so they rank behind every real
+    // item of the tile and are never written.
     uint32_t rnk[IPT];
-    uint32_t *wh = s_whist + wave * RADIX;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        uint32_t d = (key[j] >> shift) & mask;
+        uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
         if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
-        const uint64_t peers = match_digit<BITS>(d);
-        const uint32_t below = popc_below(peers);
+        uint32_t lo, hi;
+        match_digit<BITS>(d, lo, hi);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
         const uint32_t cnt = wh[d];
         rnk[j] = cnt + below;
-        if (below == 0) wh[d] = cnt + static_cast<uint32_t>(__popcll(peers));
+        // the first lane of each digit advances the counter; the others
+        // write their private scratch word instead
+        uint32_t *dst = below == 0 ? wh + d : scratch;
+        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
         compiler_fence();
     }
     __syncthreads();
@@ -372,108 +497,55 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     }
     const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
     uint32_t dexcl[R];
-    {
+    if (tid < DT) {
         uint32_t run = texcl;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            const uint32_t d = tid * R + r;
             dexcl[r] = run;
-            run += tid < DT ? tcount[r] : 0u;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + d] += run;
+            run += tcount[r];
         }
-    }
-    if (tid < DT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + tid * R + r] += dexcl[r];
     }
     __syncthreads();
 
-    // ---- gather keys by digit in LDS (tile rank = digit start + earlier
-    // waves + rank inside the wave)
+    // ---- gather keys and values by digit in LDS (tile rank = digit start +
+    // earlier waves + rank inside the wave)
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        uint32_t d = (key[j] >> shift) & mask;
+        uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
         if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
         const uint32_t r = wh[d] + rnk[j];
-        rnk[j] = r;
-        s_stage[r] = key[j];
+        s_stage_k[r] = key[j];
+        if constexpr (VALS) s_stage_v[r] = val[j];
     }
 
-    // ---- decoupled lookback: sum the counts of earlier tiles per digit
+    // ---- lookback: the count of each digit in all earlier tiles
     if (tid < DT) {
-        uint32_t excl[R];
-        int32_t at[R];
-        bool done[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            excl[r] = 0;
-            at[r] = static_cast<int32_t>(tile) - 1;
-            done[r] = tile == 0;
-        }
-        bool all_done = tile == 0;
-        uint32_t idle = 0;
-        while (!all_done) {
-            all_done = true;
-            bool progressed = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (done[r]) continue;
-                const S s = status_load(status + static_cast<size_t>(at[r]) * RADIX + tid * R + r);
-                const uint32_t f = St::flag(s);
-                if (f != 0u) {
-                    progressed = true;
-                    excl[r] += St::count(s);
-                    if (f == kFlagIncl)
-                        done[r] = true;
-                    else
-                        --at[r];
-                }
-                all_done = all_done && done[r];
-            }
-            if (!all_done && !progressed) {
-                __builtin_amdgcn_s_sleep(1);
-                // Every earlier tile publishes within microseconds; a wait
-                // this long means broken state, so flag it and stop waiting
-                // rather than hold the GPU.
-                if (++idle > kLookbackSpinLimit) {
-                    atomicOr(error_flag, kErrLookbackTimeout);
-                    break;
-                }
-            }
-        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t d = tid * R + r;
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), d, RADIX, error_flag);
             if (tile != 0)
-                status_store(status + static_cast<size_t>(tile) * RADIX + d,
-                             St::make(kFlagIncl, excl[r] + tcount[r]));
-            s_gbase[d] = pass_base[d] + excl[r] - dexcl[r];
+                status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
+            // LDS slot i of digit d goes to output slot s_gbase[d] + i
+            s_gbase[d] = pass_base[d] + excl - dexcl[r];
         }
     }
     __syncthreads();
 
-    // ---- scatter keys: consecutive LDS slots of one digit go to consecutive
-    // output addresses
-    uint32_t pos[VALS ? IPT : 1];
+    // ---- scatter: consecutive LDS slots of one digit go to consecutive
+    // output addresses.  The clamp to n - 1 costs one op and keeps a logic
+    // error from ever turning into a store outside the array.
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t i = j * BLOCK + tid;
-        const uint32_t k = s_stage[i];
-        const uint32_t p = s_gbase[(k >> shift) & mask] + i;
-        if (VALS) pos[VALS ? j : 0] = p;
-        // p < n holds for every real item; the test keeps a logic error from
-        // ever becoming a stray store
-        if ((full || i < valid) && p < n) store_u32<NT>(pp.dst_k + p, k);
-    }
-    if constexpr (VALS) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) s_stage[rnk[j]] = val[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const uint32_t i = j * BLOCK + tid;
-            if ((full || i < valid) && pos[j] < n) store_u32<NT>(pp.dst_v + pos[j], s_stage[i]);
+        const uint32_t k = s_stage_k[i];
+        const uint32_t p = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, width)] + i, n - 1u);
+        if (full || i < valid) {
+            store_g<NT>(gelem<SMALL>(pp.dst_k, p), k);
+            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), s_stage_v[i]);
         }
     }
 }
@@ -497,12 +569,13 @@ __global__ __launch_bounds__(256) void k_copy_back(const SortPlan *__restrict__ 
     }
 }
 
-// Plain streaming copy of 16-byte words, the bandwidth reference.
+// Plain streaming copy of 16-byte words, the bandwidth reference: one word
+// per thread and one short-lived block per 4 KiB, the form that measured
+// fastest on gfx950 (grid-stride loops over fewer blocks were slower).
 __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                 size_t words) {
-    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
-    for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < words; i += stride)
-        dst[i] = src[i];
+    const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < words) dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(256) void k_copy4(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,

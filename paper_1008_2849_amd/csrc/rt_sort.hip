@@ -5,7 +5,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <vector>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -41,19 +43,12 @@ bool debug_sync_enabled() {
     return on;
 }
 
-rt_status finish_call(hipStream_t stream, const char *what, const uint32_t *device_error_word) {
+rt_status finish_call(hipStream_t stream, const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: launch failed: %s", what, hipGetErrorString(e));
     if (debug_sync_enabled()) {
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-        if (device_error_word != nullptr) {
-            uint32_t word = 0;
-            e = hipMemcpy(&word, device_error_word, sizeof word, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-            if (word & kErrLookbackTimeout)
-                return set_error(RT_ERR_HIP, "%s: a lookback wait timed out on the device", what);
-        }
     }
     return RT_OK;
 }
@@ -144,9 +139,9 @@ Layout make_layout(size_t n, const Resolved &r, bool direct) {
     const size_t sw = L.wide_status ? 8 : 4;
     size_t off = 0;
     L.hist = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.ctr = off;     off += align256(sizeof(uint32_t) * (kMaxPasses + 1));  // tile counters, error word
     L.base = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
     L.plan = off;    off += align256(sizeof(SortPlan));
-    L.ctr = off;     off += align256(sizeof(uint32_t) * kMaxPasses);
     L.status = off;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         L.status_pass[p] = off - L.status;
@@ -215,21 +210,46 @@ rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out) {
 }
 
 // ---------------------------------------------------------------------------
+// kernel timing marks
+// ---------------------------------------------------------------------------
+
+namespace {
+struct Mark {
+    hipEvent_t ev;
+    hipStream_t stream;
+    uint32_t kind;  // 0: start of a call
+};
+std::atomic<bool> g_prof_on{false};
+std::mutex g_prof_mu;
+std::vector<hipEvent_t> g_prof_events;
+std::vector<Mark> g_prof_marks;
+}  // namespace
+
+static void prof_record(hipStream_t stream, uint32_t kind) {
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    const size_t i = g_prof_marks.size();
+    if (i >= g_prof_events.size()) return;
+    if (hipEventRecord(g_prof_events[i], stream) != hipSuccess) return;
+    g_prof_marks.push_back(Mark{g_prof_events[i], stream, kind});
+}
+
+void prof_begin(hipStream_t stream) { prof_record(stream, 0u); }
+void prof_mark(hipStream_t stream, uint32_t kind) { prof_record(stream, kind); }
+
+// ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
 
-const uint32_t *error_word(const void *ws, const Layout &L) {
-    return reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.ctr) + kMaxPasses;
-}
-
 template <int BITS, int BLOCK, int IPT>
-static void launch_onesweep_shape(bool vals, bool nt, bool wide, dim3 grid, hipStream_t stream,
-                                  const SortPlan *plan, int pass, uint32_t n, const uint32_t *base,
-                                  void *status, uint32_t *ctr) {
-#define RT_OS(V, NTV, S)                                                                           \
-    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S>), grid, dim3(BLOCK), 0, stream, plan, \
-                       pass, n, base, static_cast<S *>(status), ctr, ctr + kMaxPasses)
-    if (wide) {
+static void launch_pass_shape(const Layout &L, bool vals, bool nt, hipStream_t stream, const SortPlan *plan,
+                              int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr) {
+    const dim3 grid(L.tiles), block(BLOCK);
+    uint32_t *err = ctr + kMaxPasses;
+#define RT_OS(V, NTV, S)                                                                                     \
+    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S>), grid, block, 0, stream, plan, pass, n, base, \
+                       static_cast<S *>(status), ctr, err)
+    if (L.wide_status) {
         if (vals) { if (nt) RT_OS(true, true, uint64_t); else RT_OS(true, false, uint64_t); }
         else      { if (nt) RT_OS(false, true, uint64_t); else RT_OS(false, false, uint64_t); }
     } else {
@@ -237,15 +257,16 @@ static void launch_onesweep_shape(bool vals, bool nt, bool wide, dim3 grid, hipS
         else      { if (nt) RT_OS(false, true, uint32_t); else RT_OS(false, false, uint32_t); }
     }
 #undef RT_OS
+    prof_mark(stream, RT_KIND_PASS + pass);
 }
 
-static void launch_onesweep(int bits_class, int block, int ipt, bool vals, bool nt, bool wide,
-                            dim3 grid, hipStream_t stream, const SortPlan *plan, int pass, uint32_t n,
-                            const uint32_t *base, void *status, uint32_t *ctr) {
-#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                   \
-    if (bits_class == B && block == BLK && ipt == I) {                                               \
-        launch_onesweep_shape<B, BLK, I>(vals, nt, wide, grid, stream, plan, pass, n, base, status, ctr); \
-        return;                                                                                      \
+static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, bool nt, hipStream_t stream,
+                        const SortPlan *plan, int pass, uint32_t n, const uint32_t *base, void *status,
+                        uint32_t *ctr) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                  \
+    if (bits_class == B && block == BLK && ipt == I) {                                              \
+        launch_pass_shape<B, BLK, I>(L, vals, nt, stream, plan, pass, n, base, status, ctr);       \
+        return;                                                                                     \
     }
     RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
 #undef RT_SHAPE_LAUNCH
@@ -272,29 +293,35 @@ static uint32_t grid_for(size_t items, size_t per_block, uint32_t cap) {
     return static_cast<uint32_t>(g);
 }
 
-void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist,
-                       void *zero_ptr, size_t zero_bytes, hipStream_t stream) {
+void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream) {
     const HistArgs ha = hist_args(r);
     const int cus = device_cu_count();
     hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
                        static_cast<size_t>(r.num_passes) * kMaxRadix);
-    const uint32_t grid = grid_for(n, 256 * 16, static_cast<uint32_t>(cus) * 4);
-    hipLaunchKernelGGL(k_histogram<256>, dim3(grid), dim3(256), ha.total_bins * sizeof(uint32_t), stream,
-                       keys, n, ha, hist, static_cast<uint4 *>(zero_ptr), zero_bytes / 16);
+    prof_mark(stream, RT_KIND_FILL);
+    // LDS: one copy of every pass's counters per wave (4 waves)
+    const uint32_t grid = grid_for(n, 256 * 32, static_cast<uint32_t>(cus) * 8);
+    hipLaunchKernelGGL(k_histogram<256>, dim3(grid), dim3(256), 4 * ha.total_bins * sizeof(uint32_t), stream, keys,
+                       n, ha, hist);
+    prof_mark(stream, RT_KIND_HISTOGRAM);
 }
 
 // The whole sort (direct == false) or one explicit pass (direct == true,
-// user_* read and t1_* written).
-void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L,
-                 char *ws, bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v,
-                 hipStream_t stream) {
+// user_* read and direct_out_* written).
+void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
+                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream) {
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(ws + L.ctr);
     uint32_t *base = reinterpret_cast<uint32_t *>(ws + L.base);
     SortPlan *plan = reinterpret_cast<SortPlan *>(ws + L.plan);
-    uint32_t *ctr = reinterpret_cast<uint32_t *>(ws + L.ctr);
     char *status = ws + L.status;
 
-    launch_histograms(keys, n, r, hist, status, L.status_bytes, stream);
+    prof_begin(stream);
+    // the lookback words of every pass start at zero ("not published")
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(L.status_bytes / 4, 256 * 16, 4096)), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(status), L.status_bytes / 4);
+    prof_mark(stream, RT_KIND_FILL);
+    launch_histograms(keys, n, r, hist, stream);
 
     PlanArgs a{};
     a.num_passes = r.num_passes;
@@ -315,20 +342,19 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
         a.t2_k = L.t2k ? reinterpret_cast<uint32_t *>(ws + L.t2k) : nullptr;
         a.t2_v = (L.t2v && r.with_values) ? reinterpret_cast<uint32_t *>(ws + L.t2v) : nullptr;
     }
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, stream, a, hist, base, plan, ctr,
-                       direct ? 1u : 0u);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, stream, a, hist, base, plan, ctr, direct ? 1u : 0u);
+    prof_mark(stream, RT_KIND_PLAN);
 
-    const dim3 grid(L.tiles);
     const bool nt = (r.flags & RT_FLAG_NT_STORES) != 0;
     for (uint32_t p = 0; p < r.num_passes; ++p)
-        launch_onesweep(bits_class_of(r.width[p]), r.block, r.ipt, r.with_values, nt, L.wide_status, grid,
-                        stream, plan, static_cast<int>(p), n, base + p * kMaxRadix,
-                        status + L.status_pass[p], ctr);
+        launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, nt, stream, plan,
+                    static_cast<int>(p), n, base + p * kMaxRadix, status + L.status_pass[p], ctr);
 
     if (!direct && (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP))) {
         const uint32_t grid_c = grid_for(n, 256 * 8, static_cast<uint32_t>(device_cu_count()) * 8);
         hipLaunchKernelGGL(k_copy_back, dim3(grid_c), dim3(256), 0, stream, plan, a.t1_k, a.t1_v, keys,
                            a.user_v, n);
+        prof_mark(stream, RT_KIND_COPY_BACK);
     }
 }
 
@@ -377,7 +403,7 @@ extern "C" rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const 
     }
     launch_sort(keys, vals, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws), false, nullptr, nullptr,
                 stream);
-    return finish_call(stream, "rt_sort_ex", error_word(ws, L));
+    return finish_call(stream, "rt_sort_ex");
 }
 
 extern "C" rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream) {
@@ -406,8 +432,9 @@ extern "C" rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const r
     Resolved r;
     rt_status s = resolve_config(cfg, n < 2 ? 2 : n, 0, &r);
     if (s != RT_OK) return s;
-    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, nullptr, 0, stream);
-    return finish_call(stream, "rt_digit_histograms", nullptr);
+    prof_begin(stream);
+    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream);
+    return finish_call(stream, "rt_digit_histograms");
 }
 
 extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
@@ -437,7 +464,7 @@ extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, 
         hipError_t e = hipMemcpyAsync(kout, kin, 4, hipMemcpyDeviceToDevice, stream);
         if (e == hipSuccess && vin) e = hipMemcpyAsync(vout, vin, 4, hipMemcpyDeviceToDevice, stream);
         if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_counting_pass: %s", hipGetErrorString(e));
-        return finish_call(stream, "rt_counting_pass", nullptr);
+        return finish_call(stream, "rt_counting_pass");
     }
     rt_config c{};
     rt_config t;
@@ -464,7 +491,7 @@ extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, 
     if (s != RT_OK) return s;
     launch_sort(const_cast<uint32_t *>(kin), const_cast<uint32_t *>(vin), static_cast<uint32_t>(n), r, L,
                 static_cast<char *>(ws), true, kout, vout, stream);
-    return finish_call(stream, "rt_counting_pass", error_word(ws, L));
+    return finish_call(stream, "rt_counting_pass");
 }
 
 extern "C" rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream_t stream) {
@@ -472,17 +499,19 @@ extern "C" rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream
     if (src == nullptr || dst == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_copy: NULL pointer");
     if (bytes & 3u) return set_error(RT_ERR_INVALID_ARG, "rt_copy: bytes must be a multiple of 4");
     const int cus = device_cu_count();
+    prof_begin(stream);
     const bool v16 = !((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes) & 15u);
     if (v16) {
         const size_t words = bytes / 16;
-        hipLaunchKernelGGL(k_copy16, dim3(grid_for(words, 256 * 4, static_cast<uint32_t>(cus) * 16)), dim3(256), 0,
-                           stream, static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), words);
+        hipLaunchKernelGGL(k_copy16, dim3(static_cast<uint32_t>((words + 255) / 256)), dim3(256), 0, stream,
+                           static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), words);
     } else {
         const size_t words = bytes / 4;
         hipLaunchKernelGGL(k_copy4, dim3(grid_for(words, 256 * 4, static_cast<uint32_t>(cus) * 16)), dim3(256), 0,
                            stream, static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), words);
     }
-    return finish_call(stream, "rt_copy", nullptr);
+    prof_mark(stream, RT_KIND_COPY);
+    return finish_call(stream, "rt_copy");
 }
 
 extern "C" rt_status rt_generate(uint32_t *keys, uint32_t *vals, size_t n, const rt_gen_params *params,
@@ -499,8 +528,10 @@ extern "C" rt_status rt_generate(uint32_t *keys, uint32_t *vals, size_t n, const
     memcpy(g.dictionary, params->dictionary, sizeof g.dictionary);
     memcpy(g.thresholds, params->thresholds, sizeof g.thresholds);
     const uint32_t grid = grid_for(n, 256 * 4, static_cast<uint32_t>(device_cu_count()) * 16);
+    prof_begin(stream);
     hipLaunchKernelGGL(k_generate, dim3(grid), dim3(256), 0, stream, keys, vals, static_cast<uint32_t>(n), g);
-    return finish_call(stream, "rt_generate", nullptr);
+    prof_mark(stream, RT_KIND_GENERATE);
+    return finish_call(stream, "rt_generate");
 }
 
 extern "C" const char *rt_status_string(rt_status s) {
@@ -522,3 +553,59 @@ extern "C" const char *rt_status_string(rt_status s) {
 extern "C" const char *rt_last_error(void) { return rt::last_error(); }
 
 extern "C" const char *rt_version(void) { return "rtsort 0.1 (gfx950)"; }
+
+extern "C" rt_status rt_profile_start(uint32_t max_marks) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (hipEvent_t e : g_prof_events) (void)hipEventDestroy(e);
+    g_prof_events.clear();
+    g_prof_marks.clear();
+    g_prof_on.store(false);
+    if (max_marks == 0) return RT_OK;
+    g_prof_events.reserve(max_marks);
+    g_prof_marks.reserve(max_marks);
+    for (uint32_t i = 0; i < max_marks; ++i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) {
+            for (hipEvent_t x : g_prof_events) (void)hipEventDestroy(x);
+            g_prof_events.clear();
+            return set_error(RT_ERR_HIP, "rt_profile_start: hipEventCreate: %s", hipGetErrorString(err));
+        }
+        g_prof_events.push_back(e);
+    }
+    g_prof_on.store(true);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count) {
+    g_prof_on.store(false);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    uint32_t out = 0;
+    rt_status st = RT_OK;
+    for (size_t i = 0; i < g_prof_marks.size(); ++i) {
+        const Mark &m = g_prof_marks[i];
+        if (m.kind == 0) continue;
+        // the previous mark on the same stream ends where this kernel starts
+        size_t j = i;
+        while (j > 0 && g_prof_marks[j - 1].stream != m.stream) --j;
+        if (j == 0) continue;
+        const Mark &prev = g_prof_marks[j - 1];
+        hipError_t e = hipEventSynchronize(m.ev);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, prev.ev, m.ev);
+        if (e != hipSuccess) {
+            st = set_error(RT_ERR_HIP, "rt_profile_stop: %s", hipGetErrorString(e));
+            break;
+        }
+        if (out < capacity) {
+            if (kinds) kinds[out] = m.kind;
+            if (ms) ms[out] = t;
+        }
+        ++out;
+    }
+    if (count) *count = out < capacity ? out : capacity;
+    for (hipEvent_t e : g_prof_events) (void)hipEventDestroy(e);
+    g_prof_events.clear();
+    g_prof_marks.clear();
+    return st;
+}

@@ -134,7 +134,9 @@ void builtin(size_t n, int op, rt_config *out) {
     memset(out, 0, sizeof *out);
     out->num_passes = 4;
     for (int p = 0; p < 4; ++p) out->digit_bits[p] = 8;
-    out->block_threads = 256;
+    // 16K-item tiles: the largest that fits LDS for key/value pairs, and the
+    // fastest measured on gfx950 (longer digit runs, shorter lookback chains)
+    out->block_threads = 1024;
     out->items_per_thread = 16;
     out->flags = 0;
 }

@@ -105,18 +105,18 @@ def test_status_strings(so):
 def test_tuning_table_roundtrip(so, tmp_path):
     good = {"arch": "gfx950", "entries": [
         {"op": "pairs", "min_n": 0, "max_n": 1 << 30, "digit_bits": [11, 11, 10],
-         "block": 256, "ipt": 32, "flags": 2},
+         "block": 512, "ipt": 16, "flags": 2},
         {"op": "keys", "min_n": 0, "max_n": 1 << 40, "digit_bits": [8, 8, 8, 8],
-         "block": 512, "ipt": 16, "flags": 0}]}
+         "block": 1024, "ipt": 8, "flags": 0}]}
     p = tmp_path / "t.json"
     p.write_text(json.dumps(good))
     assert so.rt_load_tuning(str(p).encode()) == _lib.RT_OK
     c = _lib.RtConfig()
     assert so.rt_tuned_config(1 << 20, 1, ctypes.byref(c)) == _lib.RT_OK
     assert [c.digit_bits[i] for i in range(c.num_passes)] == [11, 11, 10]
-    assert (c.block_threads, c.items_per_thread, c.flags) == (256, 32, 2)
+    assert (c.block_threads, c.items_per_thread, c.flags) == (512, 16, 2)
     assert so.rt_tuned_config(1 << 20, 0, ctypes.byref(c)) == _lib.RT_OK
-    assert c.block_threads == 512
+    assert c.block_threads == 1024
     bad = {"entries": [{"op": "pairs", "min_n": 0, "max_n": 10, "digit_bits": [8, 8],
                         "block": 256, "ipt": 16}]}
     p.write_text(json.dumps(bad))
@@ -125,4 +125,4 @@ def test_tuning_table_roundtrip(so, tmp_path):
     assert so.rt_load_tuning(str(p).encode()) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_load_tuning(None) == _lib.RT_OK
     assert so.rt_tuned_config(1 << 20, 1, ctypes.byref(c)) == _lib.RT_OK
-    assert c.num_passes == 4 and c.block_threads == 256
+    assert c.num_passes == 4 and c.block_threads == 1024
