@@ -150,17 +150,20 @@ __device__ __forceinline__ void status_store(S *p, S v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Adds one to counter h[d] for every active lane with ok set, in LDS.  The
-// lanes that share the first lane's digit are counted with one add, which
-// keeps heavily skewed inputs (most keys with the same digit) from turning
-// into 64-way collisions on one LDS address.  The whole wave must be active.
+// Adds one to counter h[d] for every active lane with ok set, in LDS.  When
+// at least half the wave shares the first lane's digit (heavily skewed keys)
+// those lanes are counted with one add, which keeps them from turning into a
+// 64-way collision on one LDS address; otherwise every lane adds its own one.
+// The whole wave must be active.
 __device__ __forceinline__ void wave_count(uint32_t *h, uint32_t d, bool ok) {
     const uint32_t first = __builtin_amdgcn_readfirstlane(d);
-    const bool same = ok && d == first;
-    const uint64_t same_mask = __builtin_amdgcn_ballot_w64(same);
-    if (ok && !same) atomicAdd(&h[d], 1u);
-    if ((threadIdx.x & 63u) == 0 && same_mask != 0)
-        atomicAdd(&h[first], static_cast<uint32_t>(__popcll(same_mask)));
+    const uint64_t same_mask = __builtin_amdgcn_ballot_w64(ok && d == first);
+    if (__popcll(same_mask) >= 32) {  // uniform across the wave
+        if (ok && d != first) atomicAdd(&h[d], 1u);
+        if ((threadIdx.x & 63u) == 0) atomicAdd(&h[first], static_cast<uint32_t>(__popcll(same_mask)));
+    } else if (ok) {
+        atomicAdd(&h[d], 1u);
+    }
 }
 
 // ---------------------------------------------------------------------------

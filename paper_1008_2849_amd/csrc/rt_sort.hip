@@ -114,6 +114,18 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
     if (total != 32) return set_error(RT_ERR_INVALID_ARG, "digit widths sum to %u, not 32", total);
     r.block = static_cast<int>(c.block_threads);
     r.ipt = static_cast<int>(c.items_per_thread);
+    const bool explicit_shape = cfg != nullptr && cfg->block_threads != 0 && cfg->items_per_thread != 0;
+    if (!explicit_shape) {
+        // the tuned tile may be too large for wider digits: use the widest
+        // shape every digit class has
+        bool ok = true;
+        for (uint32_t p = 0; p < r.num_passes; ++p)
+            ok = ok && shape_supported(bits_class_of(r.width[p]), r.block, r.ipt);
+        if (!ok) {
+            r.block = 512;
+            r.ipt = 16;
+        }
+    }
     for (uint32_t p = 0; p < r.num_passes; ++p)
         if (!shape_supported(bits_class_of(r.width[p]), r.block, r.ipt))
             return set_error(RT_ERR_UNSUPPORTED, "no kernel for %d-bit digits with %d threads x %d items",
@@ -473,6 +485,11 @@ extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, 
     c.digit_bits[0] = width;
     c.block_threads = t.block_threads;
     c.items_per_thread = t.items_per_thread;
+    if (!shape_supported(bits_class_of(width), static_cast<int>(c.block_threads),
+                         static_cast<int>(c.items_per_thread))) {
+        c.block_threads = 512;
+        c.items_per_thread = 16;
+    }
     c.flags = RT_FLAG_NO_SKIP;
     // resolve with a placeholder full-width layout, then set the real digit
     Resolved r{};
