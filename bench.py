@@ -65,7 +65,7 @@ def cpu_baseline(keys_h, vals_h, out_k, out_v):
     t0 = time.perf_counter()
     rk, rv = oracle.lsd_sort(keys_h, vals_h)
     dt = time.perf_counter() - t0
-    same = bool(np.array_equal(rk, out_k) and np.array_equal(rv, out_v))
+    same = bool(np.array_equal(rk, out_k) and (out_v is None or np.array_equal(rv, out_v)))
     return dt, same
 
 
@@ -74,7 +74,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--log2n", type=int, default=28, help="problem size (2^28 is the measured workload)")
+    ap.add_argument("--workload", default="pairs_256m_uniform",
+                    help="named synthetic workload (paper_1008_2849_amd.inputs.WORKLOADS)")
+    ap.add_argument("--log2n", type=int, default=0, help="override the workload's size (2^log2n)")
     ap.add_argument("--bits", default="", help="digit widths, e.g. 11,11,10 (default: tuned)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ipt", type=int, default=0)
@@ -92,32 +94,33 @@ def main() -> int:
     import torch
     import paper_1008_2849_amd as rts
     from paper_1008_2849_amd import inputs
-    from paper_1008_2849_amd._lib import (RT_KIND_COPY, RT_KIND_HISTOGRAM, RT_KIND_PASS, RT_KIND_SCAN,
-                                          RT_KIND_UPSWEEP)
+    from paper_1008_2849_amd._lib import RT_KIND_COPY, RT_KIND_HISTOGRAM, RT_KIND_PASS
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
-    n = 1 << args.log2n
+    wl = inputs.WORKLOADS[args.workload]
+    n = (1 << args.log2n) if args.log2n else wl.n
+    vals_on = wl.with_values
     K, W = args.steps, args.warmup
 
-    tuned = rts.tuned_config(n, True)
+    tuned = rts.tuned_config(n, vals_on)
     cfg = rts.Config(tuple(int(x) for x in args.bits.split(",")) if args.bits else tuned.digit_bits,
                      args.block or tuned.block_threads, args.ipt or tuned.items_per_thread,
                      args.flags or tuned.flags)
-    log(f"n=2^{args.log2n} pairs, config {cfg}, steps {K}, warmup {W}")
+    log(f"{wl.name}: n={n} {'pairs' if vals_on else 'keys'}, config {cfg}, steps {K}, warmup {W}")
 
     t = time.perf_counter()
-    keys_h = inputs.uniform_keys(n, inputs.SEED_PAIRS_256M)
-    vals_h = inputs.index_values(n)
+    keys_h, vals_h = inputs.make_workload(wl, n)
     k0 = torch.from_numpy(keys_h.view(np.int32)).to(dev)
-    v0 = torch.from_numpy(vals_h.view(np.int32)).to(dev)
+    v0 = torch.from_numpy(vals_h.view(np.int32)).to(dev) if vals_on else None
     # one private copy of the input per step, all resident before timing
-    slots = [(k0.clone(), v0.clone()) for _ in range(K + W)]
-    ws = torch.empty(rts.workspace_bytes(n, True, cfg), dtype=torch.uint8, device=dev)
+    slots = [(k0.clone(), None if v0 is None else v0.clone()) for _ in range(K + W)]
+    ws = torch.empty(rts.workspace_bytes(n, vals_on, cfg), dtype=torch.uint8, device=dev)
+    item_bytes = 8 if vals_on else 4
     torch.cuda.synchronize()
-    log(f"inputs staged in HBM ({(K + W) * 8 * n / 2**30:.1f} GiB) in {time.perf_counter() - t:.1f}s")
+    log(f"inputs staged in HBM ({(K + W) * item_bytes * n / 2**30:.1f} GiB) in {time.perf_counter() - t:.1f}s")
 
     for i in range(W):
         rts.sort_ex(slots[i][0], slots[i][1], cfg, ws)
@@ -142,18 +145,14 @@ def main() -> int:
                 out.setdefault(kind - base_kind, []).append(ms)
         return {p: float(np.mean(v)) for p, v in sorted(out.items())}
 
-    down = by_kind(RT_KIND_PASS)
-    up = by_kind(RT_KIND_UPSWEEP)
-    scan = by_kind(RT_KIND_SCAN)
+    passes = by_kind(RT_KIND_PASS)
     hist_ms = [ms for kind, ms in marks if kind == RT_KIND_HISTOGRAM]
-    pass_bytes = 16.0 * n  # the pass must read key + value and write key + value
+    pass_bytes = 2.0 * item_bytes * n  # the pass reads and writes every key (and value) once
     per_pass = []
-    for p in sorted(down):
-        total = down[p] + up.get(p, 0.0) + scan.get(p, 0.0)
-        per_pass.append({"pass": p, "ms": round(total, 4), "upsweep_ms": round(up.get(p, 0.0), 4),
-                         "scan_ms": round(scan.get(p, 0.0), 4), "downsweep_ms": round(down[p], 4),
-                         "GB/s": round(pass_bytes / total / 1e6, 1),
-                         "frac_of_peak": round(pass_bytes / total / 1e6 / PEAK_HBM_GBPS, 4)})
+    for p in sorted(passes):
+        per_pass.append({"pass": p, "ms": round(passes[p], 4),
+                         "GB/s": round(pass_bytes / passes[p] / 1e6, 1),
+                         "frac_of_peak": round(pass_bytes / passes[p] / 1e6 / PEAK_HBM_GBPS, 4)})
     all_down = [ms for kind, ms in marks if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
     dom_ms = float(np.mean(all_down)) if all_down else float("nan")
     achieved = pass_bytes / dom_ms / 1e6
@@ -166,19 +165,27 @@ def main() -> int:
     ko, vo = slots[W + K - 1]
     k64 = ko.to(torch.int64) & 0xFFFFFFFF
     props = bool((k64[1:] >= k64[:-1]).all().item())
-    vl = vo.to(torch.int64)
-    props &= bool(((vl >= 0) & (vl < n)).all().item())
-    seen = torch.zeros(n, dtype=torch.bool, device=dev)
-    seen[vl] = True
-    props &= bool(seen.all().item())
-    props &= bool(torch.equal(k0[vl], ko))
-    eq = k64[1:] == k64[:-1]
-    props &= bool((vl[1:][eq] > vl[:-1][eq]).all().item())
-    del seen, k64, vl, eq
+    if vo is not None:
+        vl = vo.to(torch.int64)
+        props &= bool(((vl >= 0) & (vl < n)).all().item())
+        seen = torch.zeros(n, dtype=torch.bool, device=dev)
+        seen[vl] = True
+        props &= bool(seen.all().item())
+        props &= bool(torch.equal(k0[vl], ko))
+        eq = k64[1:] == k64[:-1]
+        props &= bool((vl[1:][eq] > vl[:-1][eq]).all().item())
+        del seen, vl, eq
+    else:  # keys only: the same multiset, by a histogram of all 32 bits' low and high halves
+        src64 = k0.to(torch.int64) & 0xFFFFFFFF
+        for sh in (0, 16):
+            props &= bool(torch.equal(torch.bincount((src64 >> sh) & 0xFFFF, minlength=65536),
+                                      torch.bincount((k64 >> sh) & 0xFFFF, minlength=65536)))
+        props &= bool(torch.equal(src64.sum(), k64.sum()))
+        del src64
+    del k64
 
     # achievable copy bandwidth: 2 GiB read + 2 GiB written
-    src = k0.view(torch.int32)
-    big_src = torch.cat([k0, v0])
+    big_src = torch.empty(1 << 29, dtype=torch.int32, device=dev).fill_(7)
     big_dst = torch.empty_like(big_src)
     rts.copy(big_src, big_dst)
     torch.cuda.synchronize()
@@ -188,7 +195,7 @@ def main() -> int:
     torch.cuda.synchronize()
     cm = [ms for kind, ms in rts.profile_stop(64) if kind == RT_KIND_COPY]
     copy_gbps = 2 * big_src.numel() * 4 / float(np.median(cm)) / 1e6 if cm else None
-    del big_src, big_dst, src
+    del big_src, big_dst
 
     digest = kernel_source_digest()
     traffic = traffic_from_profiles(digest)
@@ -197,11 +204,11 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         out_k = ko.cpu().numpy().view(np.uint32)
-        out_v = vo.cpu().numpy().view(np.uint32)
+        out_v = None if vo is None else vo.cpu().numpy().view(np.uint32)
         log("timing the CPU oracle on the same input (single thread)")
         dt, same = cpu_baseline(keys_h, vals_h, out_k, out_v)
         cpu = {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole workload: 2^{args.log2n} uniform pairs (seed {inputs.SEED_PAIRS_256M}), "
+               "sample": f"the whole workload: {wl.name} at n={n} (seed {wl.seed}), "
                          f"one sort, {dt:.1f} s, host has {os.cpu_count()} logical CPUs",
                "matches_gpu_bit_exact": same}
         log(f"oracle {dt:.1f}s, GPU output {'==' if same else '!='} oracle")
@@ -219,13 +226,13 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"pairs_2^{args.log2n}_uniform", "n": n, "values": "original index",
+        "config": {"workload": wl.name, "n": n, "values": "original index" if vals_on else None,
                    "digit_bits": list(cfg.digit_bits), "block_threads": cfg.block_threads,
                    "items_per_thread": cfg.items_per_thread, "flags": cfg.flags},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": "k_downsweep (scatter of one counting-sort pass)",
+                     "kernel": "k_onesweep (one counting-sort pass: rank, lookback, scatter)",
                      "algorithmic_bytes_per_launch": pass_bytes,
                      "avg_launch_ms": round(dom_ms, 4)},
         "cpu_baseline": cpu,

@@ -56,6 +56,7 @@ typedef enum rt_status {
 /* rt_config.flags */
 #define RT_FLAG_NO_SKIP 0x1u   /* run every pass, even when its digit is constant */
 #define RT_FLAG_NT_STORES 0x2u /* scatter with non-temporal stores */
+#define RT_FLAG_VALIDATE 0x4u  /* batched: wait for the sort and report malformed offsets */
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".
@@ -112,17 +113,41 @@ rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *
 
 /*
  * Sort every segment s = [seg_offsets[s], seg_offsets[s+1]) of keys/vals
- * independently and stably, in one graph-launched sequence.  seg_offsets:
- * device u32[num_segments + 1], nondecreasing.  Items outside
- * [seg_offsets[0], seg_offsets[num_segments]) are not touched; empty
- * segments are fine.  vals may be NULL (keys only).  Malformed offsets are
- * undefined behaviour unless RT_FLAG_VALIDATE-style checking is requested
- * through rt_sort_batched_ex; the plain call does not read offsets on the
- * host.  max_total bounds seg_offsets[num_segments] - seg_offsets[0] (the
- * library sizes its workspace from it; pass the total when known).
+ * independently and stably (Section 4's LSD sort applied to each segment
+ * as to an array of its own; segments are not described by the paper, which
+ * sorts one array).  seg_offsets: device u32[num_segments + 1],
+ * nondecreasing, read only on the device.  Items outside
+ * [seg_offsets[0], seg_offsets[num_segments]) are not touched; empty and
+ * one-item segments are fine.  vals may be NULL (keys only); keys and vals
+ * must not overlap.  max_total bounds seg_offsets[num_segments] -
+ * seg_offsets[0] and sizes the workspace (pass the total when known).
+ * Segments of up to 16384 items are sorted whole in LDS, larger ones by
+ * four 8-bit onesweep passes over 16K-item tiles.
+ *
+ * Errors: argument errors are returned before any device work.  A segment
+ * whose offsets decrease or reach past seg_offsets[0] + max_total is left
+ * unsorted and flagged on the device; the plain call does not wait for the
+ * device, so only RT_FLAG_VALIDATE (or RT_DEBUG_SYNC=1) reports it, as
+ * RT_ERR_INVALID_ARG.  The call is stream-ordered and never writes outside
+ * the segments and the library's workspace.
  */
 rt_status rt_sort_pairs_batched(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
                                 uint32_t num_segments, size_t max_total, hipStream_t stream);
+
+/* Workspace bytes of a batched sort of num_segments segments totalling at
+ * most max_total items (0 when there is nothing to sort). */
+size_t rt_batched_workspace_bytes(uint32_t num_segments, size_t max_total, int with_values);
+
+/*
+ * Explicit form of rt_sort_pairs_batched: flags (RT_FLAG_VALIDATE or 0) and
+ * a caller-owned device workspace of at least rt_batched_workspace_bytes()
+ * bytes, 256-byte aligned (NULL = library cache).  With a caller workspace
+ * and no RT_FLAG_VALIDATE the call only enqueues kernels, so it may be
+ * captured into a HIP graph; concurrent calls must not share a workspace.
+ */
+rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
+                             uint32_t num_segments, size_t max_total, uint32_t flags, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Pieces of the path, exported for parity tests and measurement
@@ -271,10 +296,9 @@ rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
 #define RT_KIND_COPY_BACK 4u
 #define RT_KIND_COPY 5u
 #define RT_KIND_GENERATE 6u
-#define RT_KIND_SEGMENTED 7u
-#define RT_KIND_PASS 16u    /* + pass index: the pass's scatter (downsweep) */
-#define RT_KIND_UPSWEEP 32u /* + pass index: the pass's per-chunk digit counts */
-#define RT_KIND_SCAN 48u    /* + pass index: the pass's per-chunk offsets */
+#define RT_KIND_SEGMENTED 7u /* segmented sort: tile lists of the tiled segments */
+#define RT_KIND_SEG_SMALL 8u /* segmented sort: segments sorted whole in LDS */
+#define RT_KIND_PASS 16u     /* + pass index: one counting-sort pass (onesweep) */
 rt_status rt_profile_start(uint32_t max_marks);
 rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count);
 

@@ -26,6 +26,7 @@ RT_MAX_PASSES = 8
 RT_MAX_DIGIT_BITS = 11
 RT_FLAG_NO_SKIP = 0x1
 RT_FLAG_NT_STORES = 0x2
+RT_FLAG_VALIDATE = 0x4
 
 RT_KIND_FILL = 1
 RT_KIND_HISTOGRAM = 2
@@ -34,9 +35,8 @@ RT_KIND_COPY_BACK = 4
 RT_KIND_COPY = 5
 RT_KIND_GENERATE = 6
 RT_KIND_SEGMENTED = 7
+RT_KIND_SEG_SMALL = 8
 RT_KIND_PASS = 16
-RT_KIND_UPSWEEP = 32
-RT_KIND_SCAN = 48
 
 
 class RtConfig(ctypes.Structure):
@@ -81,6 +81,8 @@ SIGNATURES = {
     "rt_workspace_bytes": (sz, [sz, ctypes.c_int, ctypes.POINTER(RtConfig)]),
     "rt_sort_ex": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
+    "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
+    "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),
     "rt_digit_histograms": (ctypes.c_int, [vp, sz, ctypes.POINTER(RtConfig), vp, vp]),
     "rt_counting_pass": (ctypes.c_int, [vp, vp, vp, vp, sz, u32, u32, vp]),
     "rt_copy": (ctypes.c_int, [vp, vp, sz, vp]),

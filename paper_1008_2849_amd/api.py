@@ -126,7 +126,7 @@ def sort_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, strea
 
 def sort_pairs_batched(keys, vals, offsets, max_total: Optional[int] = None, stream=None) -> None:
     """Sort every segment [offsets[s], offsets[s+1]) independently (stable).
-    vals may be None."""
+    vals may be None; offsets is a device tensor of num_segments + 1 entries."""
     _check_tensor(keys, "keys")
     _check_tensor(vals, "vals")
     _check_tensor(offsets, "offsets")
@@ -135,6 +135,29 @@ def sort_pairs_batched(keys, vals, offsets, max_total: Optional[int] = None, str
     total = keys.numel() if max_total is None else int(max_total)
     check(lib().rt_sort_pairs_batched(_ptr(keys), _ptr(vals), _ptr(offsets), offsets.numel() - 1, total,
                                       _stream(stream)), "rt_sort_pairs_batched")
+
+
+def batched_workspace_bytes(num_segments: int, max_total: int, with_values: bool = True) -> int:
+    return int(lib().rt_batched_workspace_bytes(num_segments, max_total, 1 if with_values else 0))
+
+
+def sort_batched_ex(keys, vals, offsets, max_total: Optional[int] = None, validate: bool = False,
+                    workspace=None, stream=None) -> None:
+    """Batched sort with an optional caller workspace (graph-capturable) and
+    optional validation of the offsets (waits for the device)."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    _check_tensor(offsets, "offsets")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs num_segments + 1 entries")
+    total = keys.numel() if max_total is None else int(max_total)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr = workspace.data_ptr()
+        ws_bytes = workspace.numel() * workspace.element_size()
+    check(lib().rt_sort_batched_ex(_ptr(keys), _ptr(vals), _ptr(offsets), offsets.numel() - 1, total,
+                                   _lib.RT_FLAG_VALIDATE if validate else 0, ws_ptr, ws_bytes, _stream(stream)),
+          "rt_sort_batched_ex")
 
 
 def digit_histograms(keys, cfg: Optional[Config] = None, stream=None):

@@ -1,0 +1,189 @@
+// rt_batched.hip -- host side of the batched segmented sort: workspace
+// layout, launch sequence and the C ABI entry points.  The segment offsets
+// stay on the device: descriptors, size classes and tile maps are all built
+// by kernels, so a call is a fixed sequence of launches (no host sync) that
+// a caller with its own workspace can capture into a HIP graph.
+#include <cstring>
+#include <mutex>
+
+#include "rt_common.h"
+#include "rt_seg_kernels.h"
+
+namespace rt {
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values) {
+    SegLayout L{};
+    L.num_segments = num_segments;
+    L.capacity = capacity;
+    const size_t large_cap = std::min<size_t>(num_segments, capacity / (kSegClassMax[kSegClasses - 1] + 1));
+    L.large_capacity = static_cast<uint32_t>(large_cap);
+    L.max_tiles = static_cast<uint32_t>((capacity + kSegTile - 1) / kSegTile + large_cap);
+    L.wide_status = capacity >= (static_cast<size_t>(1) << 30);
+    const size_t sw = L.wide_status ? 8 : 4;
+    size_t off = 0;
+    L.header = off;     off += align256(sizeof(SegHeader));
+    L.descs = off;      off += align256(sizeof(SegDesc) * num_segments);
+    L.lists = off;      off += align256(sizeof(uint32_t) * (kSegClasses + 1) * static_cast<size_t>(num_segments));
+    L.first_tile = off; off += align256(sizeof(uint32_t) * (large_cap + 1));
+    L.tile_seg = off;   off += align256(sizeof(uint32_t) * L.max_tiles);
+    L.hist = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
+    L.base = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
+    L.status_pass = static_cast<size_t>(L.max_tiles) * kSegRadix * sw;
+    L.status = off;     off += align256(L.status_pass * kSegPasses);
+    L.tk = off;         off += align256(sizeof(uint32_t) * capacity);
+    L.tv = 0;
+    if (with_values) { L.tv = off; off += align256(sizeof(uint32_t) * capacity); }
+    L.total = off;
+    return L;
+}
+
+static uint32_t cap_grid(size_t want, uint32_t cap) {
+    if (want < 1) want = 1;
+    return static_cast<uint32_t>(want < cap ? want : cap);
+}
+
+// Per-segment histograms and prefix sums, whole-in-LDS segments, and the
+// passes over the tiled segments.  The lists and the tiled list's counter
+// are already on the device.
+template <bool VALS, typename S>
+static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint32_t list_stride,
+                                 hipStream_t stream) {
+    const uint32_t cus = static_cast<uint32_t>(device_cu_count());
+    uint32_t *large_list = P.lists + static_cast<size_t>(kSegLarge) * list_stride;
+    hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
+                       L.large_capacity, L.max_tiles);
+    hipLaunchKernelGGL(k_seg_tilemap, dim3(cap_grid((L.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, stream,
+                       P.first_tile, P.header, P.tile_seg);
+    prof_mark(stream, RT_KIND_SEGMENTED);
+    hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
+                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist);
+    prof_mark(stream, RT_KIND_HISTOGRAM);
+    hipLaunchKernelGGL(k_seg_plan, dim3(cap_grid(L.large_capacity, cus * 4)), dim3(256), 0, stream, P.descs,
+                       large_list, P.header, P.hist, P.base);
+    prof_mark(stream, RT_KIND_PLAN);
+    // whole-in-LDS classes
+    hipLaunchKernelGGL((k_seg_small<256, 8, VALS>), dim3(cap_grid(list_stride, cus * 8)), dim3(256), 0, stream,
+                       P.descs, P.lists, P.header, 0);
+    hipLaunchKernelGGL((k_seg_small<512, 16, VALS>), dim3(cap_grid(list_stride, cus * 2)), dim3(512), 0, stream,
+                       P.descs, P.lists + list_stride, P.header, 1);
+    hipLaunchKernelGGL((k_seg_small<1024, 16, VALS>), dim3(cap_grid(list_stride, cus)), dim3(1024), 0, stream,
+                       P.descs, P.lists + 2 * static_cast<size_t>(list_stride), P.header, 2);
+    prof_mark(stream, RT_KIND_SEG_SMALL);
+    for (int p = 0; p < kSegPasses; ++p) {
+        S *status = reinterpret_cast<S *>(reinterpret_cast<char *>(P.status) + p * L.status_pass);
+        hipLaunchKernelGGL((k_seg_onesweep<1024, 16, VALS, S>), dim3(L.max_tiles), dim3(1024), 0, stream, P.descs,
+                           large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status,
+                           P.header_words + offsetof(SegHeader, tile_ctr) / 4 + p,
+                           P.header_words + offsetof(SegHeader, error) / 4);
+        prof_mark(stream, RT_KIND_PASS + p);
+    }
+}
+
+SegPointers seg_pointers(char *ws, const SegLayout &L) {
+    SegPointers P{};
+    P.header = reinterpret_cast<SegHeader *>(ws + L.header);
+    P.header_words = reinterpret_cast<uint32_t *>(ws + L.header);
+    P.descs = reinterpret_cast<SegDesc *>(ws + L.descs);
+    P.lists = reinterpret_cast<uint32_t *>(ws + L.lists);
+    P.first_tile = reinterpret_cast<uint32_t *>(ws + L.first_tile);
+    P.tile_seg = reinterpret_cast<uint32_t *>(ws + L.tile_seg);
+    P.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    P.base = reinterpret_cast<uint32_t *>(ws + L.base);
+    P.status = ws + L.status;
+    P.tk = reinterpret_cast<uint32_t *>(ws + L.tk);
+    P.tv = L.tv ? reinterpret_cast<uint32_t *>(ws + L.tv) : nullptr;
+    return P;
+}
+
+void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
+                    const SegLayout &L, char *ws, hipStream_t stream) {
+    const SegPointers P = seg_pointers(ws, L);
+    const bool vals_on = vals != nullptr;
+    prof_begin(stream);
+    hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, stream, P.header);
+    const size_t hist_words = static_cast<size_t>(kSegPasses) * kSegRadix * L.large_capacity;
+    if (hist_words)
+        hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((hist_words + 4095) / 4096, 1024)), dim3(256), 0, stream,
+                           P.hist, hist_words);
+    const size_t status_words = L.status_pass * kSegPasses / 4;
+    hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((status_words + 4095) / 4096, 4096)), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(P.status), status_words);
+    prof_mark(stream, RT_KIND_FILL);
+    hipLaunchKernelGGL(k_seg_classify, dim3((num_segments + 255) / 256), dim3(256), 0, stream, offsets,
+                       num_segments, keys, vals, P.tk, vals_on ? P.tv : nullptr, L.capacity, L.large_capacity,
+                       P.descs, P.lists, P.header);
+    if (L.wide_status) {
+        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, stream);
+        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, stream);
+    } else {
+        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, stream);
+        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, stream);
+    }
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+static rt_status check_batched(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets, uint32_t num_segments,
+                               size_t max_total, const char *what) {
+    if (max_total >= (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_TOO_LARGE, "%s: max_total = %zu, the limit is 2^32 - 1", what, max_total);
+    if (num_segments == 0 || max_total < 2) return RT_OK;
+    if (seg_offsets == nullptr) return set_error(RT_ERR_INVALID_ARG, "%s: seg_offsets is NULL", what);
+    if (keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "%s: keys is NULL", what);
+    if ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(vals) |
+         reinterpret_cast<uintptr_t>(seg_offsets)) & 3u)
+        return set_error(RT_ERR_INVALID_ARG, "%s: arrays must be 4-byte aligned", what);
+    if (vals != nullptr && keys == vals) return set_error(RT_ERR_INVALID_ARG, "%s: keys and values alias", what);
+    return RT_OK;
+}
+
+extern "C" size_t rt_batched_workspace_bytes(uint32_t num_segments, size_t max_total, int with_values) {
+    if (num_segments == 0 || max_total < 2 || max_total >= (static_cast<size_t>(1) << 32)) return 0;
+    return make_seg_layout(num_segments, max_total, with_values != 0).total;
+}
+
+extern "C" rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
+                                        uint32_t num_segments, size_t max_total, uint32_t flags, void *workspace,
+                                        size_t workspace_bytes, hipStream_t stream) {
+    rt_status s = check_batched(keys, vals, seg_offsets, num_segments, max_total, "rt_sort_batched_ex");
+    if (s != RT_OK || num_segments == 0 || max_total < 2) return s;
+    if (flags & ~static_cast<uint32_t>(RT_FLAG_VALIDATE))
+        return set_error(RT_ERR_INVALID_ARG, "rt_sort_batched_ex: unknown flags 0x%x", flags);
+    const SegLayout L = make_seg_layout(num_segments, max_total, vals != nullptr);
+    void *ws = workspace;
+    if (ws != nullptr) {
+        if (workspace_bytes < L.total)
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_batched_ex: workspace of %zu bytes, %zu needed",
+                             workspace_bytes, L.total);
+        if (reinterpret_cast<uintptr_t>(ws) & 255u)
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_batched_ex: workspace must be 256-byte aligned");
+    } else {
+        s = cached_workspace(L.total, stream, &ws);
+        if (s != RT_OK) return s;
+    }
+    launch_batched(keys, vals, seg_offsets, num_segments, L, static_cast<char *>(ws), stream);
+    s = finish_call(stream, "rt_sort_batched_ex");
+    if (s != RT_OK) return s;
+    if ((flags & RT_FLAG_VALIDATE) || debug_sync_enabled()) {
+        SegHeader h;
+        hipError_t e = hipMemcpyAsync(&h, static_cast<char *>(ws) + L.header, sizeof h, hipMemcpyDeviceToHost,
+                                      stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_sort_batched_ex: %s", hipGetErrorString(e));
+        if (h.error & kSegErrBounds)
+            return set_error(RT_ERR_INVALID_ARG,
+                             "rt_sort_batched_ex: malformed offsets (decreasing, or past max_total); those "
+                             "segments were left unsorted");
+        if (h.error) return set_error(RT_ERR_HIP, "rt_sort_batched_ex: device error word 0x%x", h.error);
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_sort_pairs_batched(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
+                                           uint32_t num_segments, size_t max_total, hipStream_t stream) {
+    return rt_sort_batched_ex(keys, vals, seg_offsets, num_segments, max_total, 0u, nullptr, 0, stream);
+}

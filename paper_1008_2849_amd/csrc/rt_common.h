@@ -55,6 +55,36 @@ rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);
 void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
                  bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream);
 
+// Workspace of a segmented sort (byte offsets) and its device pointers.
+struct SegLayout {
+    uint32_t num_segments;
+    size_t capacity;          // temporaries hold this many items
+    uint32_t large_capacity;  // most segments the tiled path can hold
+    uint32_t max_tiles;
+    bool wide_status;
+    size_t header, descs, lists, first_tile, tile_seg, hist, base, status, status_pass, tk, tv;
+    size_t total;
+};
+
+struct SegPointers {
+    SegHeader *header;
+    uint32_t *header_words;
+    SegDesc *descs;
+    uint32_t *lists;
+    uint32_t *first_tile;
+    uint32_t *tile_seg;
+    uint32_t *hist;
+    uint32_t *base;
+    char *status;
+    uint32_t *tk;
+    uint32_t *tv;
+};
+
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values);
+SegPointers seg_pointers(char *ws, const SegLayout &L);
+void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
+                    const SegLayout &L, char *ws, hipStream_t stream);
+
 // Kernel timing marks (see rt_profile_start); cheap no-ops when disabled.
 void prof_begin(hipStream_t stream);
 void prof_mark(hipStream_t stream, uint32_t kind);

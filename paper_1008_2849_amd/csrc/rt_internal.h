@@ -50,4 +50,36 @@ struct PlanArgs {
     uint32_t *t2_v;
 };
 
+// ---- segmented sort (batched calls and the server)
+
+constexpr int kSegBits = 8;
+constexpr int kSegPasses = 4;
+constexpr int kSegRadix = 1 << kSegBits;
+constexpr int kSegTile = 1024 * 16;  // items per tile of the pass kernels
+constexpr int kSegClasses = 3;       // whole-in-LDS size classes
+// largest segment of each whole-in-LDS class (block threads x items per thread)
+constexpr uint32_t kSegClassMax[kSegClasses] = {256 * 8, 512 * 16, 1024 * 16};
+constexpr int kSegLarge = kSegClasses;  // list index of the tiled segments
+constexpr uint32_t kSegErrBounds = 2u;  // a segment reached past the workspace
+
+// One segment.  The sorted result ends in k/v (the segment's own arrays);
+// tk/tv are temporaries of n elements.  v and tv are NULL for keys only.
+struct SegDesc {
+    uint32_t *k, *v;
+    uint32_t *tk, *tv;
+    uint32_t n;
+    uint32_t pass;  // pass to run when the launch does not fix one
+    uint32_t row;   // row of the per-segment histogram and base tables
+    uint32_t pad;
+};
+
+// Device-side counters of a segmented sort.
+struct SegHeader {
+    uint32_t count[kSegClasses + 1];  // list lengths: whole-in-LDS classes, tiled
+    uint32_t total_tiles;             // tiles of the tiled list
+    uint32_t tile_ctr[kSegPasses + 1];
+    uint32_t error;
+    uint32_t pad[5];
+};
+
 }  // namespace rt

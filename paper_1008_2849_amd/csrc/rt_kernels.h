@@ -150,27 +150,11 @@ __device__ __forceinline__ void status_store(S *p, S v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Adds one to counter h[d] for every active lane with ok set, in LDS.  When
-// at least half the wave shares the first lane's digit (heavily skewed keys)
-// those lanes are counted with one add, which keeps them from turning into a
-// 64-way collision on one LDS address; otherwise every lane adds its own one.
-// The whole wave must be active.
-__device__ __forceinline__ void wave_count(uint32_t *h, uint32_t d, bool ok) {
-    const uint32_t first = __builtin_amdgcn_readfirstlane(d);
-    const uint64_t same_mask = __builtin_amdgcn_ballot_w64(ok && d == first);
-    if (__popcll(same_mask) >= 32) {  // uniform across the wave
-        if (ok && d != first) atomicAdd(&h[d], 1u);
-        if ((threadIdx.x & 63u) == 0) atomicAdd(&h[first], static_cast<uint32_t>(__popcll(same_mask)));
-    } else if (ok) {
-        atomicAdd(&h[d], 1u);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // fill
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_fill_zero(uint32_t *__restrict__ p, size_t words) {
+static __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *__restrict__ p, size_t words) {
     const size_t stride = static_cast<size_t>(gridDim.x) * 256;
     for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < words; i += stride)
         p[i] = 0u;
@@ -189,43 +173,66 @@ struct HistArgs {
 };
 
 // Counts per pass and digit into hist[p * kMaxRadix + d], which must start at
-// zero.  Each wave keeps its own LDS copy of the counters; keys are read in
-// 256-byte wave slots.
-template <int BLOCK>
+// zero.  A block keeps C copies of the counters of all passes in LDS, one
+// per lane class (lane mod C), in rows of total_bins + 1 words: lanes that
+// hit the same digit then add into C different words in C different banks,
+// so skewed keys no longer serialise on one LDS address.  Before counting a
+// wave's batch of 64 * U keys, one test per pass checks whether the whole
+// batch shares that pass's digit (constant bytes, runs of equal keys); such
+// a digit is counted with a single add.  Keys are read in 256-byte slots.
+template <int BLOCK, int C>
 __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict__ keys, uint32_t n,
                                                      HistArgs ha, uint32_t *__restrict__ hist) {
     constexpr int WAVES = BLOCK / 64;
     constexpr int U = 8;  // slots in flight per lane
-    extern __shared__ uint32_t s_h[];  // WAVES copies of total_bins counters
+    extern __shared__ uint32_t s_h[];  // C rows of total_bins + 1 counters
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
-    for (uint32_t i = tid; i < WAVES * ha.total_bins; i += BLOCK) s_h[i] = 0u;
+    const uint32_t row = ha.total_bins + 1u;
+    for (uint32_t i = tid; i < C * row; i += BLOCK) s_h[i] = 0u;
     __syncthreads();
-    uint32_t *h = s_h + wave * ha.total_bins;
+    uint32_t *h = s_h + (lane % C) * row;
 
     const size_t wave_span = static_cast<size_t>(64) * U;
     const size_t stride = static_cast<size_t>(gridDim.x) * WAVES * wave_span;
     for (size_t base = (static_cast<size_t>(blockIdx.x) * WAVES + wave) * wave_span; base < n; base += stride) {
         uint32_t k[U];
+        if (base + wave_span <= n) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t i = base + u * 64 + lane;
-            k[u] = i < n ? keys[i] : 0u;
-        }
+            for (int u = 0; u < U; ++u) k[u] = keys[base + u * 64 + lane];
+            // bits in which some key of the batch differs from lane 0's first
+            const uint32_t k0 = __builtin_amdgcn_readfirstlane(k[0]);
+            uint32_t differ = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = base + u * 64 + lane < n;
+            for (int u = 0; u < U; ++u) differ |= k[u] ^ k0;
 #pragma unroll
-            for (int p = 0; p < kMaxPasses; ++p)
-                if (p < static_cast<int>(ha.num_passes))
-                    wave_count(h + ha.lds_offset[p], (k[u] >> ha.shift[p]) & ha.mask[p], ok);
+            for (int p = 0; p < kMaxPasses; ++p) {
+                if (p >= static_cast<int>(ha.num_passes)) break;
+                uint32_t *hp = h + ha.lds_offset[p];
+                if (__builtin_amdgcn_ballot_w64(((differ >> ha.shift[p]) & ha.mask[p]) != 0u) == 0u) {
+                    if (lane == 0) atomicAdd(&hp[(k0 >> ha.shift[p]) & ha.mask[p]], static_cast<uint32_t>(64 * U));
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) atomicAdd(&hp[(k[u] >> ha.shift[p]) & ha.mask[p]], 1u);
+                }
+            }
+        } else {  // the ragged end of the array
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t i = base + u * 64 + lane;
+                if (i >= n) continue;
+                const uint32_t key = keys[i];
+                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p)
+                    atomicAdd(&h[ha.lds_offset[p] + ((key >> ha.shift[p]) & ha.mask[p])], 1u);
+            }
         }
     }
     __syncthreads();
     for (uint32_t i = tid; i < ha.total_bins; i += BLOCK) {
         uint32_t c = 0;
-        for (int w = 0; w < WAVES; ++w) c += s_h[w * ha.total_bins + i];
+#pragma unroll
+        for (int w = 0; w < C; ++w) c += s_h[w * row + i];
         if (c == 0) continue;
         uint32_t p = 0;
         while (p + 1 < ha.num_passes && i >= ha.lds_offset[p + 1]) ++p;
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
 
 // One block of 256 threads; thread t covers bins [8t, 8t + 8) of a pass.
 // Also clears the tile counters of the passes.
-__global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__restrict__ hist,
+static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__restrict__ hist,
                                               uint32_t *__restrict__ base, SortPlan *__restrict__ plan,
                                               uint32_t *__restrict__ tile_counters, uint32_t direct) {
     __shared__ uint32_t s_wsum[4];
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
 
 // Moves the result of a sort with exactly one executed pass from the
 // temporary back into the caller's arrays.
-__global__ __launch_bounds__(256) void k_copy_back(const SortPlan *__restrict__ plan,
+static __global__ __launch_bounds__(256) void k_copy_back(const SortPlan *__restrict__ plan,
                                                    const uint32_t *__restrict__ tk,
                                                    const uint32_t *__restrict__ tv,
                                                    uint32_t *__restrict__ uk, uint32_t *__restrict__ uv,
@@ -575,13 +582,13 @@ __global__ __launch_bounds__(256) void k_copy_back(const SortPlan *__restrict__ 
 // Plain streaming copy of 16-byte words, the bandwidth reference: one word
 // per thread and one short-lived block per 4 KiB, the form that measured
 // fastest on gfx950 (grid-stride loops over fewer blocks were slower).
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+static __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                 size_t words) {
     const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i < words) dst[i] = src[i];
 }
 
-__global__ __launch_bounds__(256) void k_copy4(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+static __global__ __launch_bounds__(256) void k_copy4(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
                                                size_t words) {
     const size_t stride = static_cast<size_t>(gridDim.x) * 256;
     for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < words; i += stride)
@@ -610,7 +617,7 @@ __device__ __forceinline__ uint64_t splitmix_word(uint64_t state, uint64_t i) {
     return mix64(state + (i + 1ull) * 0x9E3779B97F4A7C15ull);
 }
 
-__global__ __launch_bounds__(256) void k_generate(uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+static __global__ __launch_bounds__(256) void k_generate(uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                   uint32_t n, GenArgs g) {
     const size_t stride = static_cast<size_t>(gridDim.x) * 256;
     for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {

@@ -1,0 +1,521 @@
+// rt_seg_kernels.h -- gfx950 kernels of the segmented (batched) sort.
+//
+// Many independent arrays ("segments": the slices of one batched call, or
+// the requests of the server) are sorted together.  Each segment is
+// described by a SegDesc; a work list picks the segments of a launch.
+//
+// * Segments of at most 16K items are sorted whole inside one block: one
+//   read and one write of HBM, the four 8-bit counting-sort passes running
+//   between LDS and registers.
+// * Larger segments are cut into 16K-item tiles and sorted by per-segment
+//   counting-sort passes in the onesweep form of rt_kernels.h: upfront
+//   per-segment histograms, per-segment exclusive prefix sums, then per pass
+//   one launch covering the tiles of every segment, with each segment's
+//   lookback chain ending at its own first tile.
+//
+// Each pass is Section 3's counting sort (histogram, exclusive prefix sum,
+// stable scatter) and the pass sequence is Section 4's LSD order; a segment
+// is sorted exactly as a single array of its own would be.
+#include "rt_kernels.h"
+
+namespace rt {
+
+// ---------------------------------------------------------------------------
+// set-up of a batched call: descriptors and work lists from the offsets
+// ---------------------------------------------------------------------------
+
+static __global__ __launch_bounds__(64) void k_seg_reset(SegHeader *__restrict__ h) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(h);
+    for (uint32_t i = threadIdx.x; i < sizeof(SegHeader) / 4; i += 64) w[i] = 0u;
+}
+
+// One thread per segment.  Segment s is [off[s], off[s+1]) of keys/vals; its
+// temporaries sit at the same distance from off[0] in tk/tv, which hold
+// `capacity` elements.  A segment with an end before its start, or reaching
+// past off[0] + capacity, is left untouched and raises kSegErrBounds.
+static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ off, uint32_t num_segments,
+                                                      uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
+                                                      size_t capacity, uint32_t large_capacity,
+                                                      SegDesc *__restrict__ descs, uint32_t *__restrict__ lists,
+                                                      SegHeader *__restrict__ h) {
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= num_segments) return;
+    const uint32_t o0 = off[0];
+    const uint32_t a = off[s], b = off[s + 1];
+    if (b < a || a < o0 || static_cast<size_t>(b - o0) > capacity) {
+        atomicOr(&h->error, kSegErrBounds);
+        return;
+    }
+    const uint32_t n = b - a;
+    if (n < 2) return;  // nothing to sort
+    SegDesc d;
+    d.k = keys + a;
+    d.v = vals ? vals + a : nullptr;
+    d.tk = tk + (a - o0);
+    d.tv = tv ? tv + (a - o0) : nullptr;
+    d.n = n;
+    d.pass = 0;
+    d.row = 0;
+    d.pad = 0;
+    int c = kSegLarge;
+#pragma unroll
+    for (int i = kSegClasses - 1; i >= 0; --i)
+        if (n <= kSegClassMax[i]) c = i;
+    const uint32_t at = atomicAdd(&h->count[c], 1u);
+    if (c == kSegLarge) {
+        if (at >= large_capacity) {  // only if capacity does not bound the offsets
+            atomicOr(&h->error, kSegErrBounds);
+            return;
+        }
+        d.row = at;
+    }
+    descs[s] = d;
+    lists[static_cast<size_t>(c) * num_segments + at] = s;
+}
+
+// The tiled list as the server builds it on the host has no counter on the
+// device yet: this sets it.
+static __global__ __launch_bounds__(64) void k_seg_set_count(SegHeader *__restrict__ h, int which, uint32_t count) {
+    if (threadIdx.x == 0) h->count[which] = count;
+}
+
+// One block: first_tile[i] = tiles of list entries before i, and the total.
+// Well-formed offsets never list more than large_capacity segments nor more
+// than max_tiles tiles; overlapping (malformed) ones can, and then the list
+// is cut to what the workspace holds (or emptied) and the error is raised,
+// so that no later kernel indexes past the tables.
+static __global__ __launch_bounds__(1024) void k_seg_tiles(const SegDesc *__restrict__ descs,
+                                                           const uint32_t *__restrict__ list,
+                                                           uint32_t *__restrict__ first_tile, SegHeader *__restrict__ h,
+                                                           uint32_t large_capacity, uint32_t max_tiles) {
+    __shared__ uint32_t s_wsum[16];
+    const uint32_t listed = h->count[kSegLarge];
+    const uint32_t count = min(listed, large_capacity);
+    const uint32_t per = (count + 1023u) / 1024u;
+    const uint32_t lo = min(count, threadIdx.x * per), hi = min(count, lo + per);
+    uint32_t sum = 0;  // at most 256 entries of at most 2^18 tiles: no overflow
+    for (uint32_t i = lo; i < hi; ++i) sum += (descs[list[i]].n + kSegTile - 1) / kSegTile;
+    // saturate, so the block total stays exact up to max_tiles and cannot wrap
+    uint32_t run = block_exclusive_sum<1024>(min(sum, max_tiles + 1u), s_wsum);
+    for (uint32_t i = lo; i < hi; ++i) {
+        first_tile[i] = run;
+        run += (descs[list[i]].n + kSegTile - 1) / kSegTile;
+    }
+    if (threadIdx.x == 1023) {
+        const bool fits = run <= max_tiles;
+        first_tile[count] = run;
+        h->count[kSegLarge] = fits ? count : 0u;
+        h->total_tiles = fits ? run : 0u;
+        if (!fits || listed != count) atomicOr(&h->error, kSegErrBounds);
+    }
+}
+
+// tile_seg[t] = the list entry that tile t belongs to (first_tile is
+// strictly increasing: every listed segment has at least one tile).
+static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__restrict__ first_tile,
+                                                     const SegHeader *__restrict__ h,
+                                                     uint32_t *__restrict__ tile_seg) {
+    const uint32_t count = h->count[kSegLarge];
+    const uint32_t total = h->total_tiles;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256) {
+        uint32_t lo = 0, hi = count - 1;  // the last entry with first_tile <= t
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (first_tile[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        tile_seg[t] = lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// whole segment in one block
+// ---------------------------------------------------------------------------
+
+// Sorts segments of at most BLOCK * IPT items, one per block at a time.  The
+// segment is loaded once, padded with all-ones keys that stay behind every
+// real item (they come last in input order and the sort is stable), taken
+// through the four passes in LDS, and stored once.  Ranking inside a pass is
+// the onesweep ranking: wave-local ballot match plus per-wave digit counters,
+// then digit offsets across the block.
+template <int BLOCK, int IPT, bool VALS>
+__global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__ descs,
+                                                     const uint32_t *__restrict__ list,
+                                                     const SegHeader *__restrict__ h, int which) {
+    constexpr int RADIX = kSegRadix;
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int TILE = BLOCK * IPT;
+    constexpr int WAVE_ITEMS = 64 * IPT;
+    constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;
+    constexpr int DT = RADIX / R;
+    __shared__ uint32_t s_k[TILE];
+    __shared__ uint32_t s_v[VALS ? TILE : 1];
+    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
+    __shared__ uint32_t s_wsum[WAVES];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;
+    uint32_t *wh = s_whist + wave * RADIX;
+    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
+    const uint32_t count = h->count[which];
+
+    for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+        const SegDesc d = descs[list[e]];
+        const uint32_t n = d.n;
+        uint32_t key[IPT];
+        uint32_t val[VALS ? IPT : 1];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = wslot0 + j * 64;
+            key[j] = i < n ? d.k[i] : ~0u;
+            if constexpr (VALS) val[j] = i < n ? d.v[i] : 0u;
+        }
+        for (int p = 0; p < kSegPasses; ++p) {
+            const uint32_t shift = p * kSegBits;
+            for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
+            // (the previous pass finished reading wh before its last barrier)
+            uint32_t rnk[IPT];
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
+                uint32_t lo, hi;
+                match_digit<kSegBits>(dg, lo, hi);
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+                const uint32_t cnt = wh[dg];
+                rnk[j] = cnt + below;
+                uint32_t *dst = below == 0 ? wh + dg : scratch;
+                *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
+                compiler_fence();
+            }
+            __syncthreads();
+            uint32_t tcount[R];
+            uint32_t tsum = 0;
+            if (tid < DT) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t dg = tid * R + r;
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int w = 0; w < WAVES; ++w) {
+                        const uint32_t c = s_whist[w * RADIX + dg];
+                        s_whist[w * RADIX + dg] = run;
+                        run += c;
+                    }
+                    tcount[r] = run;
+                    tsum += run;
+                }
+            }
+            const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
+            if (tid < DT) {
+                uint32_t run = texcl;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t dg = tid * R + r;
+#pragma unroll
+                    for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + dg] += run;
+                    run += tcount[r];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t r = wh[__builtin_amdgcn_ubfe(key[j], shift, kSegBits)] + rnk[j];
+                s_k[r] = key[j];
+                if constexpr (VALS) s_v[r] = val[j];
+            }
+            __syncthreads();
+            if (p + 1 < kSegPasses) {
+#pragma unroll
+                for (int j = 0; j < IPT; ++j) {
+                    key[j] = s_k[wslot0 + j * 64];
+                    if constexpr (VALS) val[j] = s_v[wslot0 + j * 64];
+                }
+                // s_k is rewritten only after the next pass's first barrier
+            }
+        }
+        for (uint32_t i = tid; i < n; i += BLOCK) {
+            d.k[i] = s_k[i];
+            if constexpr (VALS) d.v[i] = s_v[i];
+        }
+        __syncthreads();  // s_k and s_v are reused by the next segment
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tiled segments: per-segment histograms and prefix sums
+// ---------------------------------------------------------------------------
+
+// Counts the digits of all four passes per tiled segment into
+// hist[row][p][d] (zeroed before).  One tile per block iteration, LDS
+// counters with C lane copies as in k_histogram; the input of pass 0 is the
+// segment's own arrays.
+template <int BLOCK, int C>
+__global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restrict__ descs,
+                                                         const uint32_t *__restrict__ list,
+                                                         const uint32_t *__restrict__ first_tile,
+                                                         const uint32_t *__restrict__ tile_seg,
+                                                         const SegHeader *__restrict__ h,
+                                                         uint32_t *__restrict__ hist) {
+    constexpr int BINS = kSegPasses * kSegRadix;
+    constexpr int ROW = BINS + 1;
+    constexpr int PER = kSegTile / BLOCK;
+    __shared__ uint32_t s_h[C * ROW];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    uint32_t *hc = s_h + (lane % C) * ROW;
+    const uint32_t total = h->total_tiles;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        for (uint32_t i = tid; i < C * ROW; i += BLOCK) s_h[i] = 0u;
+        __syncthreads();
+        const uint32_t e = tile_seg[t];
+        const SegDesc d = descs[list[e]];
+        const uint32_t start = (t - first_tile[e]) * kSegTile;
+        const uint32_t valid = min(static_cast<uint32_t>(kSegTile), d.n - start);
+        const uint32_t *src = d.k + start;
+#pragma unroll 8
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = j * BLOCK + tid;
+            if (i < valid) {
+                const uint32_t key = src[i];
+#pragma unroll
+                for (int p = 0; p < kSegPasses; ++p)
+                    atomicAdd(&hc[p * kSegRadix + __builtin_amdgcn_ubfe(key, p * kSegBits, kSegBits)], 1u);
+            }
+        }
+        __syncthreads();
+        uint32_t *out = hist + static_cast<size_t>(d.row) * BINS;
+        for (uint32_t i = tid; i < BINS; i += BLOCK) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < C; ++w) c += s_h[w * ROW + i];
+            if (c) atomicAdd(&out[i], c);
+        }
+        __syncthreads();
+    }
+}
+
+// base[row][p][d] = count of digits below d in pass p of the segment: one
+// block of 256 threads per tiled segment at a time.
+static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restrict__ descs,
+                                                  const uint32_t *__restrict__ list,
+                                                  const SegHeader *__restrict__ h,
+                                                  const uint32_t *__restrict__ hist, uint32_t *__restrict__ base) {
+    __shared__ uint32_t s_wsum[4];
+    const uint32_t count = h->count[kSegLarge];
+    for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+        const size_t row = static_cast<size_t>(descs[list[e]].row) * kSegPasses * kSegRadix;
+        for (int p = 0; p < kSegPasses; ++p) {
+            const uint32_t c = hist[row + p * kSegRadix + threadIdx.x];
+            base[row + p * kSegRadix + threadIdx.x] = block_exclusive_sum<256>(c, s_wsum);
+            __syncthreads();  // s_wsum is reused
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tiled segments: one counting-sort pass over every listed segment
+// ---------------------------------------------------------------------------
+
+// The sum of one digit's counts over tiles [lo, tile) (see lookback_digit).
+template <typename S>
+__device__ __forceinline__ uint32_t seg_lookback_digit(const S *__restrict__ status, int32_t tile, int32_t lo,
+                                                       uint32_t digit, uint32_t *__restrict__ error_flag) {
+    using St = Status<S>;
+    uint32_t excl = 0;
+    int32_t at = tile - 1;
+    uint32_t idle = 0, nap = 1;
+    while (at >= lo) {
+        S w[kLookbackBatch];
+#pragma unroll
+        for (int b = 0; b < kLookbackBatch; ++b)
+            w[b] = (at - b >= lo) ? status_load(status + static_cast<size_t>(at - b) * kSegRadix + digit) : S(0);
+        bool finished = false, stalled = false;
+        int32_t consumed = 0;
+#pragma unroll
+        for (int b = 0; b < kLookbackBatch; ++b) {
+            if (finished || stalled || at - b < lo) continue;
+            const uint32_t f = St::flag(w[b]);
+            if (f == 0u) {
+                stalled = true;
+            } else {
+                excl += St::count(w[b]);
+                ++consumed;
+                if (f == kFlagIncl) finished = true;
+            }
+        }
+        if (finished) break;
+        at -= consumed;
+        if (stalled && consumed == 0) {
+            backoff(nap);
+            nap = nap < 16 ? nap * 2 : 16;
+            if (++idle > kLookbackSpinLimit) {
+                atomicOr(error_flag, kErrLookbackTimeout);
+                break;
+            }
+        } else {
+            nap = 1;
+        }
+    }
+    return excl;
+}
+
+// One block per tile (claimed in order from *tile_counter, as in
+// k_onesweep).  The tile's segment runs pass `pass` (or its own d.pass when
+// pass < 0): even passes read k/v and write tk/tv, odd passes the reverse,
+// so the fourth pass leaves the result in k/v.  Status words: one per tile
+// and digit, zeroed before the launch.
+template <int BLOCK, int IPT, bool VALS, typename S>
+__global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
+                                                        const uint32_t *__restrict__ list,
+                                                        const uint32_t *__restrict__ first_tile,
+                                                        const uint32_t *__restrict__ tile_seg,
+                                                        const SegHeader *__restrict__ h, int pass,
+                                                        const uint32_t *__restrict__ base, S *__restrict__ status,
+                                                        uint32_t *__restrict__ tile_counter,
+                                                        uint32_t *__restrict__ error_flag) {
+    constexpr int RADIX = kSegRadix;
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int TILE = BLOCK * IPT;
+    static_assert(TILE == kSegTile, "tiles of the pass and of the tile map differ");
+    constexpr int WAVE_ITEMS = 64 * IPT;
+    constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;
+    constexpr int DT = RADIX / R;
+    constexpr bool SMALL = sizeof(S) == 4;  // every segment below 2^30 items
+    using St = Status<S>;
+
+    __shared__ uint32_t s_stage_k[TILE];
+    __shared__ uint32_t s_stage_v[VALS ? TILE : 1];
+    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
+    __shared__ uint32_t s_gbase[RADIX];
+    __shared__ uint32_t s_wsum[WAVES];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;
+    uint32_t *wh = s_whist + wave * RADIX;
+    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
+
+    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= h->total_tiles) return;
+    const uint32_t e = tile_seg[tile];
+    const SegDesc d = descs[list[e]];
+    const uint32_t first = first_tile[e];
+    const uint32_t p = pass >= 0 ? static_cast<uint32_t>(pass) : d.pass;
+    const uint32_t shift = p * kSegBits;
+    const uint32_t *src_k = (p & 1u) ? d.tk : d.k;
+    const uint32_t *src_v = (p & 1u) ? d.tv : d.v;
+    uint32_t *dst_k = (p & 1u) ? d.k : d.tk;
+    uint32_t *dst_v = (p & 1u) ? d.v : d.tv;
+    const uint32_t n = d.n;
+    const uint32_t tile_base = (tile - first) * TILE;
+    const uint32_t valid = min(static_cast<uint32_t>(TILE), n - tile_base);
+    const bool full = valid == static_cast<uint32_t>(TILE);
+
+    uint32_t key[IPT];
+    uint32_t val[VALS ? IPT : 1];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t i = wslot0 + j * 64;
+        key[j] = (full || i < valid) ? *gelem<SMALL>(src_k, tile_base + i) : 0u;
+    }
+    if constexpr (VALS) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = wslot0 + j * 64;
+            val[j] = (full || i < valid) ? *gelem<SMALL>(src_v, tile_base + i) : 0u;
+        }
+    }
+
+    uint32_t rnk[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
+        if (!full && wslot0 + j * 64 >= valid) dg = RADIX - 1;
+        uint32_t lo, hi;
+        match_digit<kSegBits>(dg, lo, hi);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        const uint32_t cnt = wh[dg];
+        rnk[j] = cnt + below;
+        uint32_t *dst = below == 0 ? wh + dg : scratch;
+        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
+        compiler_fence();
+    }
+    __syncthreads();
+
+    uint32_t tcount[R];
+    uint32_t tsum = 0;
+    if (tid < DT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t dg = tid * R + r;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = s_whist[w * RADIX + dg];
+                s_whist[w * RADIX + dg] = run;
+                run += c;
+            }
+            tcount[r] = run;
+            tsum += run;
+            status_store(status + static_cast<size_t>(tile) * RADIX + dg,
+                         St::make(tile == first ? kFlagIncl : kFlagAgg, run));
+        }
+    }
+    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
+    uint32_t dexcl[R];
+    if (tid < DT) {
+        uint32_t run = texcl;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t dg = tid * R + r;
+            dexcl[r] = run;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + dg] += run;
+            run += tcount[r];
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
+        if (!full && wslot0 + j * 64 >= valid) dg = RADIX - 1;
+        const uint32_t r = wh[dg] + rnk[j];
+        s_stage_k[r] = key[j];
+        if constexpr (VALS) s_stage_v[r] = val[j];
+    }
+
+    const uint32_t *pbase = base + (static_cast<size_t>(d.row) * kSegPasses + p) * RADIX;
+    if (tid < DT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t dg = tid * R + r;
+            const uint32_t excl = seg_lookback_digit<S>(status, static_cast<int32_t>(tile),
+                                                        static_cast<int32_t>(first), dg, error_flag);
+            if (tile != first)
+                status_store(status + static_cast<size_t>(tile) * RADIX + dg, St::make(kFlagIncl, excl + tcount[r]));
+            s_gbase[dg] = pbase[dg] + excl - dexcl[r];
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t i = j * BLOCK + tid;
+        const uint32_t k = s_stage_k[i];
+        const uint32_t q = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, kSegBits)] + i, n - 1u);
+        if (full || i < valid) {
+            *gelem<SMALL>(dst_k, q) = k;
+            if constexpr (VALS) *gelem<SMALL>(dst_v, q) = s_stage_v[i];
+        }
+    }
+}
+
+}  // namespace rt

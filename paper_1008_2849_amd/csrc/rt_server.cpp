@@ -3,10 +3,6 @@
 
 using namespace rt;
 
-extern "C" rt_status rt_sort_pairs_batched(uint32_t *, uint32_t *, const uint32_t *, uint32_t, size_t,
-                                           hipStream_t) {
-    return set_error(RT_ERR_UNSUPPORTED, "rt_sort_pairs_batched: not built yet");
-}
 extern "C" rt_status rt_server_create(size_t, uint32_t, rt_server **) {
     return set_error(RT_ERR_UNSUPPORTED, "server: not built yet");
 }

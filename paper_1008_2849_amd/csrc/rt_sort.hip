@@ -305,16 +305,39 @@ static uint32_t grid_for(size_t items, size_t per_block, uint32_t cap) {
     return static_cast<uint32_t>(g);
 }
 
+// LDS copies per block for a counter set of `bins` words: as many as fit
+// in 64 KiB (padded rows), at most 16.
+static int hist_copies(uint32_t bins) {
+    int c = 16;
+    while (c > 1 && static_cast<size_t>(c) * (bins + 1) * sizeof(uint32_t) > 72 * 1024) c /= 2;
+    return c;
+}
+
+template <int C>
+static void launch_histogram_copies(const uint32_t *keys, uint32_t n, const HistArgs &ha, uint32_t *hist,
+                                    hipStream_t stream) {
+    constexpr int kBlock = 512;
+    const size_t lds = static_cast<size_t>(C) * (ha.total_bins + 1) * sizeof(uint32_t);
+    static std::once_flag once;  // dynamic LDS above 64 KiB must be allowed
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram<kBlock, C>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    });
+    const uint32_t grid = grid_for(n, kBlock * 8 * 16, static_cast<uint32_t>(device_cu_count()) * 4);
+    hipLaunchKernelGGL((k_histogram<kBlock, C>), dim3(grid), dim3(kBlock), lds, stream, keys, n, ha, hist);
+}
+
 void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream) {
     const HistArgs ha = hist_args(r);
-    const int cus = device_cu_count();
     hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
                        static_cast<size_t>(r.num_passes) * kMaxRadix);
     prof_mark(stream, RT_KIND_FILL);
-    // LDS: one copy of every pass's counters per wave (4 waves)
-    const uint32_t grid = grid_for(n, 256 * 32, static_cast<uint32_t>(cus) * 8);
-    hipLaunchKernelGGL(k_histogram<256>, dim3(grid), dim3(256), 4 * ha.total_bins * sizeof(uint32_t), stream, keys,
-                       n, ha, hist);
+    switch (hist_copies(ha.total_bins)) {
+        case 16: launch_histogram_copies<16>(keys, n, ha, hist, stream); break;
+        case 8: launch_histogram_copies<8>(keys, n, ha, hist, stream); break;
+        case 4: launch_histogram_copies<4>(keys, n, ha, hist, stream); break;
+        default: launch_histogram_copies<2>(keys, n, ha, hist, stream); break;
+    }
     prof_mark(stream, RT_KIND_HISTOGRAM);
 }
 

@@ -126,3 +126,35 @@ def test_tuning_table_roundtrip(so, tmp_path):
     assert so.rt_load_tuning(None) == _lib.RT_OK
     assert so.rt_tuned_config(1 << 20, 1, ctypes.byref(c)) == _lib.RT_OK
     assert c.num_passes == 4 and c.block_threads == 1024
+
+
+def test_batched_argument_errors(so):
+    fake = ctypes.c_void_p(0x10000)
+    off = ctypes.c_void_p(0x90000)
+    assert so.rt_sort_pairs_batched(fake, None, off, 4, 1 << 32, None) == _lib.RT_ERR_TOO_LARGE
+    assert so.rt_sort_pairs_batched(fake, None, None, 4, 1000, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs_batched(None, None, off, 4, 1000, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs_batched(fake, fake, off, 4, 1000, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs_batched(ctypes.c_void_p(0x10002), None, off, 4, 1000, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_batched_ex(fake, None, off, 4, 1000, 0x80, None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    # a caller workspace that is too small or misaligned
+    need = so.rt_batched_workspace_bytes(4, 1000, 0)
+    assert so.rt_sort_batched_ex(fake, None, off, 4, 1000, 0, ctypes.c_void_p(0x100000), need - 1,
+                                 None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_batched_ex(fake, None, off, 4, 1000, 0, ctypes.c_void_p(0x100010), need,
+                                 None) == _lib.RT_ERR_INVALID_ARG
+    # nothing to sort: no device work, even with NULL pointers
+    assert so.rt_sort_pairs_batched(None, None, None, 0, 1000, None) == _lib.RT_OK
+    assert so.rt_sort_pairs_batched(None, None, None, 5, 1, None) == _lib.RT_OK
+
+
+def test_batched_workspace_bytes(so):
+    assert so.rt_batched_workspace_bytes(0, 1000, 1) == 0
+    assert so.rt_batched_workspace_bytes(10, 1, 1) == 0
+    assert so.rt_batched_workspace_bytes(10, 1 << 32, 1) == 0
+    cap = 1 << 27
+    with_v = so.rt_batched_workspace_bytes(4096, cap, 1)
+    keys = so.rt_batched_workspace_bytes(4096, cap, 0)
+    # one temporary per array of the full capacity, plus modest metadata
+    assert with_v - keys >= 4 * cap
+    assert keys >= 4 * cap and keys < 4 * cap + (128 << 20)
