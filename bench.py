@@ -69,6 +69,150 @@ def cpu_baseline(keys_h, vals_h, out_k, out_v):
     return dt, same
 
 
+def split_calls(marks):
+    """Group profile marks into calls: [(total ms, [(kind, ms), ...]), ...]."""
+    calls = []
+    for kind, ms in marks:
+        if kind == 0:
+            calls.append([0.0, []])
+        elif calls:
+            calls[-1][0] += ms
+            calls[-1][1].append((kind, ms))
+    return calls
+
+
+def bench_batched(rts, inputs, dev, K, W, single_gkeys):
+    """The batched workload: 4096 segments of log-uniform sizes totalling
+    2^27 pairs, one sort call per step, each on its own staged copy."""
+    import numpy as np
+    import torch
+    from paper_1008_2849_amd._lib import RT_KIND_PASS
+    sizes = inputs.batched_sizes()
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    k_h = inputs.uniform_keys(n, inputs.SEED_BATCHED)
+    k0 = torch.from_numpy(k_h.view(np.int32)).to(dev)
+    v0 = torch.arange(n, dtype=torch.int32, device=dev)
+    o = torch.from_numpy(off.astype(np.uint32).view(np.int32)).to(dev)
+    slots = [(k0.clone(), v0.clone()) for _ in range(K + W)]
+    ws = torch.empty(rts.batched_workspace_bytes(len(sizes), n, True), dtype=torch.uint8, device=dev)
+    for i in range(W):
+        rts.sort_batched_ex(slots[i][0], slots[i][1], o, n, workspace=ws)
+    torch.cuda.synchronize()
+    rts.profile_start(max_marks=32 * K + 32)
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        rts.sort_batched_ex(slots[i][0], slots[i][1], o, n, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    calls = split_calls(rts.profile_stop(capacity=32 * K + 32))
+    per_call = [c[0] for c in calls]
+    pass_ms = [ms for c in calls for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+    # properties of the last output: within every segment keys ascend, each
+    # key arrives with its own index, indices stay in their segment and in
+    # order among equal keys
+    ko, vo = slots[W + K - 1]
+    seg = torch.repeat_interleave(torch.arange(len(sizes), device=dev),
+                                  torch.from_numpy(sizes.astype(np.int64)).to(dev))
+    vl = vo.to(torch.int64)
+    ok = bool(torch.equal(seg[vl], seg)) and bool(torch.equal(k0[vl], ko))
+    k64 = ko.to(torch.int64) & 0xFFFFFFFF
+    same = seg[1:] == seg[:-1]
+    ok &= bool((k64[1:][same] >= k64[:-1][same]).all().item())
+    eq = same & (k64[1:] == k64[:-1])
+    ok &= bool((vl[1:][eq] > vl[:-1][eq]).all().item())
+    cnt = torch.bincount(vl, minlength=n)
+    ok &= bool((cnt == 1).all().item())
+    del slots, seg, vl, k64, same, eq, cnt
+    gk = n / (wall / K) / 1e9
+    return {"workload": f"batched_{len(sizes)}_segments_loguniform_2^6..2^20_total_{n}", "n": n,
+            "segments": len(sizes), "Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
+            "call_p50_ms": round(float(np.percentile(per_call, 50)), 4),
+            "call_p99_ms": round(float(np.percentile(per_call, 99)), 4),
+            "tiled_pass_ms": round(float(np.mean(pass_ms)), 4) if pass_ms else None,
+            "frac_of_single_array": round(gk / single_gkeys, 4), "parity_properties_ok": ok}
+
+
+def bench_serving(rts, inputs, load, seconds, warm_s, single_gkeys, budget_gib=32):
+    """Poisson arrivals of device-generated requests (sizes 2^U[10,24],
+    distribution uniform / AND-4 / Zipf-16) offered at `load` times the
+    single-array throughput; latency = completion - submission."""
+    import ctypes
+    import queue
+    import threading
+    import numpy as np
+    from paper_1008_2849_amd.api import gen_params_to_c
+    from paper_1008_2849_amd.server import Server
+    mean_n = (2.0 ** 24 - 2.0 ** 10) / (14 * np.log(2.0))
+    rate = load * single_gkeys * 1e9 / mean_n  # requests per second
+    count = int(rate * (seconds + warm_s) * 1.05) + 16
+    seed = inputs.SEED_SERVING
+    arrivals = inputs.poisson_arrivals(rate, count, seed)
+    sizes = inputs.serving_request_sizes(count, seed)
+    dists = inputs.serving_request_dists(count, seed)
+    # request i draws its keys from stream i of the serving seed
+    states = inputs.splitmix64_words(seed, 0, count)
+    templates = [gen_params_to_c(inputs.counter_params(d, seed, 0)) for d in range(3)]
+    params = []
+    for i in range(count):
+        g = type(templates[0])()
+        ctypes.memmove(ctypes.addressof(g), ctypes.addressof(templates[int(dists[i])]), ctypes.sizeof(g))
+        g.state = int(states[i])
+        params.append(g)
+    srv = Server(hbm_budget_bytes=budget_gib << 30, max_active=4096)
+    tickets = queue.Queue()
+    lat = {}
+    failures = []
+
+    def collect():
+        while True:
+            item = tickets.get()
+            if item is None:
+                return
+            i, t = item
+            try:
+                lat[i] = srv.wait(t)
+                srv.release(t)
+            except Exception as e:  # reported in the result line
+                failures.append(repr(e))
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    end = seconds + warm_s
+    i = 0
+    while i < count:
+        now = time.perf_counter() - t0
+        if now > end:
+            break
+        while i < count and arrivals[i] <= now:
+            tickets.put((i, srv.submit_generated(params[i], int(sizes[i]))))
+            i += 1
+        if i < count:
+            gap = arrivals[i] - (time.perf_counter() - t0)
+            if gap > 2e-4:
+                time.sleep(gap - 1e-4)
+    submitted = i
+    tickets.put(None)
+    th.join()
+    wall = time.perf_counter() - t0
+    p50_all, p99_all, gk_srv, done, peak = srv.stats()
+    srv.close()
+    meas = [j for j in range(submitted) if arrivals[j] >= warm_s and j in lat]
+    lm = np.array([lat[j] for j in meas]) / 1e3
+    items = float(np.sum(sizes[meas])) if meas else 0.0
+    span = (max(arrivals[j] + lat[j] / 1e6 for j in meas) - warm_s) if meas else 1.0
+    return {"load": load, "offered_Gkeys/s": round(load * single_gkeys, 3),
+            "achieved_Gkeys/s": round(items / span / 1e9, 3) if meas else None,
+            "p50_ms": round(float(np.percentile(lm, 50)), 3) if meas else None,
+            "p99_ms": round(float(np.percentile(lm, 99)), 3) if meas else None,
+            "requests_measured": len(meas), "requests_submitted": submitted,
+            "seconds": seconds, "warmup_s": warm_s, "budget_GiB": budget_gib,
+            "peak_budgeted_GiB": round(peak / 2**30, 3), "failures": failures[:3],
+            "wall_s": round(wall, 2)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +226,10 @@ def main() -> int:
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-loads", default="0.7", help="comma list of offered loads (fraction of "
+                    "single-array throughput); empty to skip serving")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -213,6 +361,20 @@ def main() -> int:
                "matches_gpu_bit_exact": same}
         log(f"oracle {dt:.1f}s, GPU output {'==' if same else '!='} oracle")
 
+    batched = None
+    if not args.no_batched and args.workload == "pairs_256m_uniform":
+        log("batched workload")
+        batched = bench_batched(rts, inputs, dev, K, W, gkeys)
+        log(f"batched: {batched}")
+    serving = []
+    if args.serve_loads and args.workload == "pairs_256m_uniform":
+        del slots
+        torch.cuda.empty_cache()
+        for load in (float(x) for x in args.serve_loads.split(",")):
+            log(f"serving at load {load}")
+            serving.append(bench_serving(rts, inputs, load, args.serve_seconds, 1.0, gkeys))
+            log(f"serving: {serving[-1]}")
+
     line = {
         "metric": METRIC,
         "value": round(gkeys, 3),
@@ -241,10 +403,15 @@ def main() -> int:
         "copy_peak_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
         "parity_properties_ok": props,
+        "batched": batched,
+        "serving": serving,
         "kernel_source_digest": digest,
     }
     print(json.dumps(line), flush=True)
-    return 0 if props and (cpu is None or cpu["matches_gpu_bit_exact"]) else 3
+    ok = props and (cpu is None or cpu["matches_gpu_bit_exact"])
+    ok = ok and (batched is None or batched["parity_properties_ok"])
+    ok = ok and all(not s["failures"] for s in serving)
+    return 0 if ok else 3
 
 
 if __name__ == "__main__":

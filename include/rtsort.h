@@ -288,7 +288,9 @@ rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
  * events are recorded; later launches go unrecorded.  rt_profile_stop waits
  * for the events, writes up to `capacity` (kind, milliseconds) pairs into the
  * host arrays kinds/ms in launch order, stores their number in *count and
- * frees the events.  Kinds: RT_KIND_* below.
+ * frees the events.  Kinds: RT_KIND_* below; kind 0 opens each call and
+ * carries the idle time since the previous mark on its stream (0 for the
+ * first).
  */
 #define RT_KIND_FILL 1u
 #define RT_KIND_HISTOGRAM 2u

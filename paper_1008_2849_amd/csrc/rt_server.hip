@@ -1,0 +1,677 @@
+// rt_server.hip -- the serving loop: requests to sort arrive one by one, are
+// admitted under a device-memory budget, and progress together in steps.
+//
+// Continuous batching at pass granularity: every step runs, for every
+// admitted request, one counting-sort pass over its tiles (requests of more
+// than 16K items) or its whole sort in LDS (smaller ones), all in the same
+// few launches of the segmented kernels.  A request admitted between two
+// steps joins the next one: its digit histograms and prefix sums are built
+// at the start of that step and its first pass runs in it.  A request of
+// more than 16K items is done after four steps, a smaller one after one.
+//
+// Memory: one arena of hbm_budget_bytes, carved first-fit (256-byte
+// granules) into each request's temporaries (and, for generated requests,
+// its input/result arrays).  Fixed metadata besides the arena: per-request
+// histogram and prefix-sum rows, descriptors, work lists and the lookback
+// words of one step.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "rt_common.h"
+#include "rt_seg_kernels.h"
+
+namespace rt {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_us() {
+    return std::chrono::duration<double, std::micro>(Clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t kGranule = 256;
+constexpr size_t kMaxRequestItems = (static_cast<size_t>(1) << 30) - 1;  // 32-bit lookback words
+
+size_t round_up(size_t x) { return (x + kGranule - 1) & ~(kGranule - 1); }
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+   public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = round_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = round_up(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+enum State { kQueued, kActive, kDone };
+
+struct Request {
+    uint64_t id = 0;
+    size_t n = 0;
+    bool generated = false;
+    bool with_values = false;
+    rt_gen_params gen{};
+    uint32_t *k = nullptr, *v = nullptr;    // input, then the sorted result
+    uint32_t *tk = nullptr, *tv = nullptr;  // temporaries
+    size_t data_off = 0, data_bytes = 0;    // arena: generated input/result
+    size_t tmp_off = 0, tmp_bytes = 0;      // arena: temporaries
+    State state = kQueued;
+    rt_status status = RT_OK;
+    std::string error;  // detail of a failed request
+    uint32_t pass = 0;  // next pass (tiled requests)
+    uint32_t row = 0;   // histogram / prefix-sum row
+    bool fresh = true;  // histograms not built yet
+    double t_submit = 0, t_done = 0;
+};
+
+bool is_small(const Request &r) { return r.n <= kSegClassMax[kSegClasses - 1]; }
+
+// Device metadata of one step: [header | descs | lists | first_tile |
+// tile_seg] for the pass work, a second header/list/first_tile/tile_seg set
+// for the histogram work of fresh requests, the per-request rows and the
+// lookback words.  The leading "step block" (headers, descs, lists) is
+// uploaded from pinned host memory once per step.
+struct Meta {
+    size_t hdr_pass, hdr_hist, descs, lists_pass, list_hist, block_bytes;
+    size_t first_pass, first_hist, seg_pass, seg_hist, hist, base, status, total;
+    uint32_t max_tiles;
+};
+
+Meta make_meta(uint32_t max_active, size_t arena_bytes) {
+    Meta m{};
+    auto a = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    // A tiled request (n > 16K items) holds at least 4n bytes of arena and
+    // has ceil(n / 16K) <= n / 16K + 1 <= 2n / 16K tiles, so a step has at
+    // most min(arena / 32K, arena / 64K + max_active) tiles.
+    const size_t by_size = arena_bytes / (sizeof(uint32_t) * kSegTile / 2);
+    const size_t by_count = arena_bytes / (sizeof(uint32_t) * kSegTile) + max_active;
+    m.max_tiles = static_cast<uint32_t>(std::min(by_size, by_count) + 1);
+    size_t off = 0;
+    m.hdr_pass = off;   off += a(sizeof(SegHeader));
+    m.hdr_hist = off;   off += a(sizeof(SegHeader));
+    m.descs = off;      off += a(sizeof(SegDesc) * max_active);
+    m.lists_pass = off; off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
+    m.list_hist = off;  off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
+    m.block_bytes = off;
+    m.first_pass = off; off += a(sizeof(uint32_t) * (max_active + 1));
+    m.first_hist = off; off += a(sizeof(uint32_t) * (max_active + 1));
+    m.seg_pass = off;   off += a(sizeof(uint32_t) * m.max_tiles);
+    m.seg_hist = off;   off += a(sizeof(uint32_t) * m.max_tiles);
+    m.hist = off;       off += a(sizeof(uint32_t) * kSegPasses * kSegRadix * max_active);
+    m.base = off;       off += a(sizeof(uint32_t) * kSegPasses * kSegRadix * max_active);
+    m.status = off;     off += a(sizeof(uint32_t) * kSegRadix * static_cast<size_t>(m.max_tiles));
+    m.total = off;
+    return m;
+}
+
+// Zeroes the histogram rows of the listed (fresh) requests.
+__global__ __launch_bounds__(256) void k_srv_clear_rows(const SegDesc *__restrict__ descs,
+                                                        const uint32_t *__restrict__ list,
+                                                        const SegHeader *__restrict__ h, uint32_t *__restrict__ hist) {
+    const uint32_t count = h->count[kSegLarge];
+    for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+        uint32_t *row = hist + static_cast<size_t>(descs[list[e]].row) * kSegPasses * kSegRadix;
+        for (uint32_t i = threadIdx.x; i < kSegPasses * kSegRadix; i += 256) row[i] = 0u;
+    }
+}
+
+}  // namespace
+}  // namespace rt
+
+using namespace rt;
+
+struct rt_server {
+    int device = 0;
+    hipStream_t stream = nullptr;   // steps
+    hipStream_t io = nullptr;       // generation is on `stream`; fetch copies here
+    hipEvent_t step_done = nullptr;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    Arena alloc;
+    size_t used = 0, peak = 0;
+    uint32_t max_active = 0;
+    Meta meta{};
+    char *dmeta = nullptr;
+    char *hblock = nullptr;  // pinned staging of the step block
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
+    std::vector<uint32_t> free_rows;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread thr;
+
+    std::vector<double> latencies;
+    double first_submit = -1, last_done = 0;
+    uint64_t items_done = 0;
+    uint64_t steps = 0;
+};
+
+namespace {
+
+size_t footprint(const Request &r) {
+    const size_t arr = round_up(r.n * sizeof(uint32_t));
+    const size_t per = r.with_values ? 2 : 1;
+    return (r.generated ? per * arr : 0) + (is_small(r) ? 0 : per * arr);
+}
+
+// Admit queued requests in arrival order while memory and slots last.
+// Returns the requests admitted (mu held by the caller).
+std::vector<Request *> admit(rt_server *s) {
+    std::vector<Request *> fresh;
+    while (!s->queue.empty() && s->active.size() < s->max_active) {
+        Request *r = s->queue.front();
+        const size_t arr = round_up(r->n * sizeof(uint32_t));
+        const size_t per = r->with_values ? 2 : 1;
+        size_t data_off = 0, tmp_off = 0;
+        const size_t data_bytes = r->generated ? per * arr : 0;
+        const size_t tmp_bytes = is_small(*r) ? 0 : per * arr;
+        if (data_bytes && !s->alloc.alloc(data_bytes, &data_off)) break;
+        if (tmp_bytes && !s->alloc.alloc(tmp_bytes, &tmp_off)) {
+            if (data_bytes) s->alloc.release(data_off, data_bytes);
+            break;
+        }
+        s->queue.pop_front();
+        r->data_off = data_off;
+        r->data_bytes = data_bytes;
+        r->tmp_off = tmp_off;
+        r->tmp_bytes = tmp_bytes;
+        if (r->generated) {
+            r->k = reinterpret_cast<uint32_t *>(s->arena + data_off);
+            r->v = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + data_off + arr) : nullptr;
+        }
+        if (tmp_bytes) {
+            r->tk = reinterpret_cast<uint32_t *>(s->arena + tmp_off);
+            r->tv = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + tmp_off + arr) : nullptr;
+        }
+        s->used += data_bytes + tmp_bytes;
+        s->peak = std::max(s->peak, s->used);
+        r->row = s->free_rows.back();
+        s->free_rows.pop_back();
+        r->state = kActive;
+        r->pass = 0;
+        r->fresh = true;
+        s->active.push_back(r);
+        fresh.push_back(r);
+    }
+    return fresh;
+}
+
+void fail_active(rt_server *s, rt_status st) {
+    const std::string why = last_error();  // set on this (the scheduler's) thread
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = now_us();
+    for (Request *r : s->active) {
+        r->state = kDone;
+        r->status = st;
+        r->error = why;
+        r->t_done = t;
+        if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
+        s->used -= r->tmp_bytes;
+        r->tmp_bytes = 0;
+        s->free_rows.push_back(r->row);
+    }
+    s->active.clear();
+    s->cv_done.notify_all();
+}
+
+// One step: histograms of fresh tiled requests, one pass of every tiled
+// request, the whole sort of every fresh small request.
+rt_status run_step(rt_server *s, const std::vector<Request *> &fresh) {
+    const Meta &m = s->meta;
+    hipStream_t st = s->stream;
+    // generate the inputs of fresh generated requests
+    for (Request *r : fresh) {
+        if (!r->generated) continue;
+        rt_status g = rt_generate(r->k, r->v, r->n, &r->gen, 0u, st);
+        if (g != RT_OK) return g;
+    }
+    // step block on the host
+    char *hb = s->hblock;
+    memset(hb, 0, m.block_bytes);
+    SegHeader *hp = reinterpret_cast<SegHeader *>(hb + m.hdr_pass);
+    SegHeader *hh = reinterpret_cast<SegHeader *>(hb + m.hdr_hist);
+    SegDesc *descs = reinterpret_cast<SegDesc *>(hb + m.descs);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(hb + m.lists_pass);
+    uint32_t *hlist = reinterpret_cast<uint32_t *>(hb + m.list_hist) + static_cast<size_t>(kSegLarge) * s->max_active;
+    const uint32_t stride = s->max_active;
+    size_t tiles = 0;
+    bool any_small = false;
+    for (size_t i = 0; i < s->active.size(); ++i) {
+        Request *r = s->active[i];
+        SegDesc &d = descs[i];
+        d.k = r->k;
+        d.v = r->with_values ? r->v : nullptr;
+        d.tk = r->tk;
+        d.tv = r->with_values ? r->tv : nullptr;
+        d.n = static_cast<uint32_t>(r->n);
+        d.pass = r->pass;
+        d.row = r->row;
+        if (r->n < 2) continue;
+        if (is_small(*r)) {
+            if (!r->fresh) continue;
+            int c = kSegClasses - 1;
+            for (int q = kSegClasses - 1; q >= 0; --q)
+                if (r->n <= kSegClassMax[q]) c = q;
+            lists[static_cast<size_t>(c) * stride + hp->count[c]++] = static_cast<uint32_t>(i);
+            any_small = true;
+        } else {
+            lists[static_cast<size_t>(kSegLarge) * stride + hp->count[kSegLarge]++] = static_cast<uint32_t>(i);
+            tiles += (r->n + kSegTile - 1) / kSegTile;
+            if (r->fresh) hlist[hh->count[kSegLarge]++] = static_cast<uint32_t>(i);
+        }
+    }
+    if (tiles > m.max_tiles) return set_error(RT_ERR_HIP, "server: step of %zu tiles exceeds %u", tiles, m.max_tiles);
+    hipError_t e = hipMemcpyAsync(s->dmeta, hb, m.block_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: step upload: %s", hipGetErrorString(e));
+
+    char *dm = s->dmeta;
+    SegHeader *d_hp = reinterpret_cast<SegHeader *>(dm + m.hdr_pass);
+    SegHeader *d_hh = reinterpret_cast<SegHeader *>(dm + m.hdr_hist);
+    const SegDesc *d_descs = reinterpret_cast<const SegDesc *>(dm + m.descs);
+    uint32_t *d_lists = reinterpret_cast<uint32_t *>(dm + m.lists_pass);
+    uint32_t *d_hlist = reinterpret_cast<uint32_t *>(dm + m.list_hist) + static_cast<size_t>(kSegLarge) * stride;
+    uint32_t *d_plist = d_lists + static_cast<size_t>(kSegLarge) * stride;
+    uint32_t *d_first_p = reinterpret_cast<uint32_t *>(dm + m.first_pass);
+    uint32_t *d_first_h = reinterpret_cast<uint32_t *>(dm + m.first_hist);
+    uint32_t *d_seg_p = reinterpret_cast<uint32_t *>(dm + m.seg_pass);
+    uint32_t *d_seg_h = reinterpret_cast<uint32_t *>(dm + m.seg_hist);
+    uint32_t *d_hist = reinterpret_cast<uint32_t *>(dm + m.hist);
+    uint32_t *d_base = reinterpret_cast<uint32_t *>(dm + m.base);
+    uint32_t *d_status = reinterpret_cast<uint32_t *>(dm + m.status);
+    const uint32_t cus = static_cast<uint32_t>(device_cu_count());
+    auto grid = [](size_t want, uint32_t cap) { return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(want, cap))); };
+
+    if (hh->count[kSegLarge]) {  // histograms and prefix sums of fresh tiled requests
+        const uint32_t fresh_n = hh->count[kSegLarge];
+        hipLaunchKernelGGL(k_srv_clear_rows, dim3(grid(fresh_n, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
+                           d_hist);
+        hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_hlist, d_first_h, d_hh, stride,
+                           m.max_tiles);
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((m.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
+                           d_hh, d_seg_h);
+        hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(tiles, cus * 2)), dim3(512), 0, st, d_descs, d_hlist,
+                           d_first_h, d_seg_h, d_hh, d_hist);
+        hipLaunchKernelGGL(k_seg_plan, dim3(grid(fresh_n, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh, d_hist,
+                           d_base);
+    }
+    if (hp->count[kSegLarge]) {  // one pass of every tiled request
+        hipLaunchKernelGGL(k_fill_zero, dim3(grid((tiles * kSegRadix + 4095) / 4096, 4096)), dim3(256), 0, st,
+                           d_status, tiles * kSegRadix);
+        hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_hp, stride,
+                           m.max_tiles);
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p, d_hp,
+                           d_seg_p);
+        uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, tile_ctr) / 4;
+        uint32_t *err = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, error) / 4;
+        bool vals = false;
+        for (Request *r : s->active) vals = vals || r->with_values;
+        // keys-only requests inside a mixed step: their descriptors carry
+        // no value arrays, so the value kernel would dereference NULL; such
+        // steps run the keys-only kernel for them through a second launch
+        // over the same list would complicate the tile map, so a server is
+        // either all-pairs or all-keys (enforced at submit).
+        if (vals)
+            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(tiles)),
+                               dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
+                               ctr, err);
+        else
+            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(tiles)),
+                               dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
+                               ctr, err);
+    }
+    if (any_small) {
+        bool vals = false;
+        for (Request *r : s->active) vals = vals || r->with_values;
+        const size_t n0 = hp->count[0], n1 = hp->count[1], n2 = hp->count[2];
+        if (vals) {
+            if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
+            if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, d_lists + stride, d_hp, 1);
+            if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, d_lists + 2 * static_cast<size_t>(stride), d_hp, 2);
+        } else {
+            if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
+            if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, d_lists + stride, d_hp, 1);
+            if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, d_lists + 2 * static_cast<size_t>(stride), d_hp, 2);
+        }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: launch: %s", hipGetErrorString(e));
+    // the error words of both headers come back with the step
+    e = hipMemcpyAsync(hb + m.hdr_pass, dm + m.hdr_pass, 2 * ((sizeof(SegHeader) + 255) & ~size_t(255)),
+                       hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(s->step_done, st);
+    if (e == hipSuccess) e = hipEventSynchronize(s->step_done);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: step: %s", hipGetErrorString(e));
+    if (hp->error | hh->error)
+        return set_error(RT_ERR_HIP, "server: device error word 0x%x", hp->error | hh->error);
+    return RT_OK;
+}
+
+void scheduler(rt_server *s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::vector<Request *> fresh;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop) return;
+            fresh = admit(s);
+            if (s->active.empty()) {  // the head of the queue waits for memory
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
+            }
+        }
+        const rt_status st = run_step(s, fresh);
+        if (st != RT_OK) {
+            (void)hipStreamSynchronize(s->stream);  // nothing may still use what is freed
+            fail_active(s, st);
+            continue;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        ++s->steps;
+        const double t = now_us();
+        std::vector<Request *> still;
+        for (Request *r : s->active) {
+            r->fresh = false;
+            const bool finished = r->n < 2 || is_small(*r) || r->pass + 1 == kSegPasses;
+            if (!finished) {
+                ++r->pass;
+                still.push_back(r);
+                continue;
+            }
+            r->state = kDone;
+            r->t_done = t;
+            if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
+            s->used -= r->tmp_bytes;
+            r->tmp_bytes = 0;
+            s->free_rows.push_back(r->row);
+            s->latencies.push_back(t - r->t_submit);
+            s->items_done += r->n;
+            s->last_done = t;
+        }
+        s->active.swap(still);
+        s->cv_done.notify_all();
+    }
+}
+
+rt_status enqueue(rt_server *s, std::unique_ptr<Request> r, uint64_t *ticket) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return set_error(RT_ERR_CANCELLED, "server: stopping");
+    // one value layout per server (the step kernels are instantiated for it)
+    for (auto &kv : s->all) {
+        if (kv.second->with_values != r->with_values)
+            return set_error(RT_ERR_INVALID_ARG, "server: mixing keys-only and key/value requests is not supported");
+        break;
+    }
+    r->id = s->next_id++;
+    r->t_submit = now_us();
+    if (s->first_submit < 0) s->first_submit = r->t_submit;
+    *ticket = r->id;
+    s->queue.push_back(r.get());
+    s->all[r->id] = std::move(r);
+    s->cv_work.notify_one();
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_active, rt_server **out) {
+    if (out == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_create: out is NULL");
+    *out = nullptr;
+    if (max_active == 0 || max_active > (1u << 20))
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_create: max_active %u outside 1..2^20", max_active);
+    if (hbm_budget_bytes < (1u << 20))
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_create: budget below 1 MiB");
+    std::unique_ptr<rt_server> s(new rt_server());
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_server_create: %s", hipGetErrorString(e));
+    s->arena_bytes = round_up(hbm_budget_bytes);
+    s->max_active = max_active;
+    s->meta = make_meta(max_active, s->arena_bytes);
+    e = hipMalloc(reinterpret_cast<void **>(&s->arena), s->arena_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RT_ERR_OUT_OF_MEMORY, "rt_server_create: arena of %zu bytes: %s", s->arena_bytes,
+                         hipGetErrorString(e));
+    }
+    e = hipMalloc(reinterpret_cast<void **>(&s->dmeta), s->meta.total);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->hblock), s->meta.block_bytes + 2 * 256);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->dmeta) (void)hipFree(s->dmeta);
+        if (s->hblock) (void)hipHostFree(s->hblock);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->io) (void)hipStreamDestroy(s->io);
+        (void)hipFree(s->arena);
+        return set_error(RT_ERR_OUT_OF_MEMORY, "rt_server_create: metadata: %s", hipGetErrorString(e));
+    }
+    s->alloc.reset(s->arena_bytes);
+    s->free_rows.reserve(max_active);
+    for (uint32_t i = max_active; i-- > 0;) s->free_rows.push_back(i);
+    rt_server *raw = s.release();
+    raw->thr = std::thread(scheduler, raw);
+    *out = raw;
+    return RT_OK;
+}
+
+static rt_status check_request_size(rt_server *s, size_t n, bool generated, bool with_values, const char *what) {
+    if (n > kMaxRequestItems) return set_error(RT_ERR_TOO_LARGE, "%s: n = %zu, the server limit is 2^30 - 1", what, n);
+    Request probe;
+    probe.n = n;
+    probe.generated = generated;
+    probe.with_values = with_values;
+    if (footprint(probe) > s->arena_bytes)
+        return set_error(RT_ERR_BUDGET, "%s: %zu bytes needed, the budget is %zu", what, footprint(probe),
+                         s->arena_bytes);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_server_submit(rt_server *s, uint32_t *keys, uint32_t *vals, size_t n, uint64_t *ticket) {
+    if (s == nullptr || ticket == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: NULL argument");
+    if (n > 0 && keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: keys is NULL");
+    if ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(vals)) & 3u)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: arrays must be 4-byte aligned");
+    if (vals != nullptr && n > 0) {
+        const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), v0 = reinterpret_cast<uintptr_t>(vals);
+        const uintptr_t bytes = n * sizeof(uint32_t);
+        if (k0 < v0 + bytes && v0 < k0 + bytes) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: keys and values overlap");
+    }
+    rt_status st = check_request_size(s, n, false, vals != nullptr, "rt_server_submit");
+    if (st != RT_OK) return st;
+    std::unique_ptr<Request> r(new Request());
+    r->n = n;
+    r->k = keys;
+    r->v = vals;
+    r->with_values = vals != nullptr;
+    return enqueue(s, std::move(r), ticket);
+}
+
+extern "C" rt_status rt_server_submit_generated(rt_server *s, const rt_gen_params *params, size_t n,
+                                                uint64_t *ticket) {
+    if (s == nullptr || params == nullptr || ticket == nullptr)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit_generated: NULL argument");
+    if (params->dist > RT_DIST_ZIPF16)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit_generated: unknown dist %u", params->dist);
+    rt_status st = check_request_size(s, n, true, true, "rt_server_submit_generated");
+    if (st != RT_OK) return st;
+    std::unique_ptr<Request> r(new Request());
+    r->n = n;
+    r->generated = true;
+    r->with_values = true;
+    r->gen = *params;
+    return enqueue(s, std::move(r), ticket);
+}
+
+extern "C" rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us) {
+    if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_wait: server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->all.find(ticket) == s->all.end())
+        return set_error(RT_ERR_NOT_FOUND, "rt_server_wait: no request %llu", (unsigned long long)ticket);
+    // look the request up afresh: the table may rehash, and another waiter
+    // on the same ticket may have taken it, while this one sleeps
+    auto done = [&] {
+        auto f = s->all.find(ticket);
+        return f == s->all.end() || f->second->state == kDone;
+    };
+    if (timeout_us < 0) {
+        s->cv_done.wait(lk, done);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+        return set_error(RT_ERR_TIMEOUT, "rt_server_wait: request %llu still running", (unsigned long long)ticket);
+    }
+    auto it = s->all.find(ticket);
+    if (it == s->all.end())
+        return set_error(RT_ERR_NOT_FOUND, "rt_server_wait: request %llu was collected by another wait",
+                         (unsigned long long)ticket);
+    Request *r = it->second.get();
+    if (latency_us) *latency_us = r->t_done - r->t_submit;
+    const rt_status st = r->status;
+    const std::string why = r->error;
+    if (!r->generated) s->all.erase(it);  // nothing is left to fetch
+    if (st != RT_OK)
+        return set_error(st, "rt_server_wait: request %llu failed: %s", (unsigned long long)ticket, why.c_str());
+    return RT_OK;
+}
+
+static rt_status drop_generated(rt_server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it) {
+    Request *r = it->second.get();
+    if (r->data_bytes) {
+        s->alloc.release(r->data_off, r->data_bytes);
+        s->used -= r->data_bytes;
+    }
+    s->all.erase(it);
+    s->cv_work.notify_one();  // memory came free
+    return RT_OK;
+}
+
+extern "C" rt_status rt_server_fetch(rt_server *s, uint64_t ticket, uint32_t *out_keys, uint32_t *out_vals) {
+    if (s == nullptr || out_keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_fetch: NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end() || !it->second->generated)
+        return set_error(RT_ERR_NOT_FOUND, "rt_server_fetch: no generated request %llu", (unsigned long long)ticket);
+    Request *r = it->second.get();
+    if (r->state != kDone) return set_error(RT_ERR_INVALID_ARG, "rt_server_fetch: request %llu not finished", (unsigned long long)ticket);
+    if (r->status != RT_OK) return set_error(r->status, "rt_server_fetch: request %llu failed", (unsigned long long)ticket);
+    const size_t bytes = r->n * sizeof(uint32_t);
+    hipError_t e = hipSuccess;
+    if (bytes) {
+        e = hipMemcpyAsync(out_keys, r->k, bytes, hipMemcpyDeviceToDevice, s->io);
+        if (e == hipSuccess && out_vals) e = hipMemcpyAsync(out_vals, r->v, bytes, hipMemcpyDeviceToDevice, s->io);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->io);
+    }
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_server_fetch: %s", hipGetErrorString(e));
+    return drop_generated(s, it);
+}
+
+extern "C" rt_status rt_server_release(rt_server *s, uint64_t ticket) {
+    if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_release: server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(RT_ERR_NOT_FOUND, "rt_server_release: no request %llu", (unsigned long long)ticket);
+    if (it->second->state != kDone)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_release: request %llu not finished", (unsigned long long)ticket);
+    return drop_generated(s, it);
+}
+
+extern "C" rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
+                                     uint64_t *completed, size_t *peak_bytes) {
+    if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_stats: server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> l = s->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        size_t i = static_cast<size_t>(q * static_cast<double>(l.size() - 1) + 0.5);
+        return l[std::min(i, l.size() - 1)];
+    };
+    if (p50_us) *p50_us = pct(0.50);
+    if (p99_us) *p99_us = pct(0.99);
+    if (gkeys_per_s) {
+        const double span = s->last_done - s->first_submit;
+        *gkeys_per_s = (span > 0 && s->items_done) ? static_cast<double>(s->items_done) / span / 1e3 : 0.0;
+    }
+    if (completed) *completed = l.size();
+    if (peak_bytes) *peak_bytes = s->peak;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_server_destroy(rt_server *s) {
+    if (s == nullptr) return RT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->thr.joinable()) s->thr.join();
+    (void)hipStreamSynchronize(s->stream);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const double t = now_us();
+        for (auto &kv : s->all) {
+            Request *r = kv.second.get();
+            if (r->state != kDone) {
+                r->state = kDone;
+                r->status = RT_ERR_CANCELLED;
+                r->t_done = t;
+            }
+        }
+        s->cv_done.notify_all();
+    }
+    (void)hipEventDestroy(s->step_done);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->io);
+    (void)hipHostFree(s->hblock);
+    (void)hipFree(s->dmeta);
+    (void)hipFree(s->arena);
+    delete s;
+    return RT_OK;
+}

@@ -624,15 +624,13 @@ extern "C" rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capaci
     rt_status st = RT_OK;
     for (size_t i = 0; i < g_prof_marks.size(); ++i) {
         const Mark &m = g_prof_marks[i];
-        if (m.kind == 0) continue;
         // the previous mark on the same stream ends where this kernel starts
+        // (for a call-start mark: the idle gap since the previous call)
         size_t j = i;
         while (j > 0 && g_prof_marks[j - 1].stream != m.stream) --j;
-        if (j == 0) continue;
-        const Mark &prev = g_prof_marks[j - 1];
         hipError_t e = hipEventSynchronize(m.ev);
         float t = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, prev.ev, m.ev);
+        if (e == hipSuccess && j > 0) e = hipEventElapsedTime(&t, g_prof_marks[j - 1].ev, m.ev);
         if (e != hipSuccess) {
             st = set_error(RT_ERR_HIP, "rt_profile_stop: %s", hipGetErrorString(e));
             break;

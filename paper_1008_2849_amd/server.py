@@ -1,0 +1,86 @@
+"""Python handle of the library's serving loop (rt_server_* in rtsort.h).
+
+Every step of the loop runs in the library's scheduler thread and HIP
+kernels; this class only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+from . import _lib
+from ._lib import RtGenParams, check, lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Server:
+    """Sorts requests submitted one by one; see rt_server_create."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4096):
+        h = ctypes.c_void_p()
+        check(lib().rt_server_create(int(hbm_budget_bytes), int(max_active), ctypes.byref(h)), "rt_server_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("server is closed")
+        return self._h
+
+    def submit(self, keys, vals=None) -> int:
+        """Sort device tensors keys (and vals) in place; returns a ticket.
+        The tensors must stay alive and untouched until wait() returns."""
+        for t, name in ((keys, "keys"), (vals, "vals")):
+            if t is not None and (not t.is_cuda or t.element_size() != 4 or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous 4-byte device tensor")
+        ticket = ctypes.c_uint64()
+        check(lib().rt_server_submit(self.handle, _ptr(keys), _ptr(vals), keys.numel(), ctypes.byref(ticket)),
+              "rt_server_submit")
+        return ticket.value
+
+    def submit_generated(self, params: RtGenParams, n: int) -> int:
+        """A request whose input the server generates on the device."""
+        ticket = ctypes.c_uint64()
+        check(lib().rt_server_submit_generated(self.handle, ctypes.byref(params), int(n), ctypes.byref(ticket)),
+              "rt_server_submit_generated")
+        return ticket.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> float:
+        """Block until the request is done; returns its latency in us."""
+        lat = ctypes.c_double()
+        check(lib().rt_server_wait(self.handle, int(ticket), int(timeout_us), ctypes.byref(lat)), "rt_server_wait")
+        return lat.value
+
+    def fetch(self, ticket: int, out_keys, out_vals=None) -> None:
+        check(lib().rt_server_fetch(self.handle, int(ticket), _ptr(out_keys), _ptr(out_vals)), "rt_server_fetch")
+
+    def release(self, ticket: int) -> None:
+        check(lib().rt_server_release(self.handle, int(ticket)), "rt_server_release")
+
+    def stats(self) -> Tuple[float, float, float, int, int]:
+        """(p50 us, p99 us, Gkeys/s, completed requests, peak budgeted bytes)."""
+        p50, p99, gk = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        done, peak = ctypes.c_uint64(), ctypes.c_size_t()
+        check(lib().rt_server_stats(self.handle, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(gk),
+                                    ctypes.byref(done), ctypes.byref(peak)), "rt_server_stats")
+        return p50.value, p99.value, gk.value, done.value, peak.value
+
+    def close(self) -> None:
+        if self._h is not None:
+            check(lib().rt_server_destroy(self._h), "rt_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

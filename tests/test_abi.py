@@ -158,3 +158,18 @@ def test_batched_workspace_bytes(so):
     # one temporary per array of the full capacity, plus modest metadata
     assert with_v - keys >= 4 * cap
     assert keys >= 4 * cap and keys < 4 * cap + (128 << 20)
+
+
+def test_server_argument_errors(so):
+    out = ctypes.c_void_p()
+    assert so.rt_server_create(1 << 30, 0, ctypes.byref(out)) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_create(1000, 8, ctypes.byref(out)) == _lib.RT_ERR_INVALID_ARG  # budget below 1 MiB
+    assert so.rt_server_create(1 << 30, 8, None) == _lib.RT_ERR_INVALID_ARG
+    t = ctypes.c_uint64()
+    assert so.rt_server_submit(None, None, None, 0, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_submit_generated(None, None, 10, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_wait(None, 1, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_fetch(None, 1, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_release(None, 1) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_stats(None, None, None, None, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_destroy(None) == _lib.RT_OK

@@ -1,0 +1,102 @@
+"""The serving loop: every request comes back sorted exactly as the oracle
+sorts it alone, whatever else shares its steps (tolerance 0: the sort is
+exact).  Requests are device-generated from the counter-based generator,
+which the host re-derives for the oracle, or caller-owned device arrays.
+Sizes straddle the whole-in-LDS limit (16384) and the tile size; the
+budget is small enough that admission has to wait for memory."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1008_2849_amd import inputs
+from paper_1008_2849_amd.api import gen_params_to_c
+from paper_1008_2849_amd.server import Server
+from paper_1008_2849_amd._lib import RtError, RT_ERR_BUDGET, RT_ERR_NOT_FOUND
+from gpu_util import announce, sync, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 100, 2048, 2049, 8192, 8193, 16384, 16385, 16384 * 2 + 5, 100_000, 300_001]
+
+
+def _generated_case(srv, rid, n, dist):
+    p = inputs.counter_params(dist, inputs.SEED_SERVING, rid)
+    return srv.submit_generated(gen_params_to_c(p), n), p
+
+
+def test_generated_mix_matches_oracle_alone():
+    import torch
+    rng = np.random.default_rng(5)
+    sizes = list(SIZES) * 3
+    rng.shuffle(sizes)
+    announce(f"server generated mix of {len(sizes)} requests")
+    with Server(hbm_budget_bytes=64 << 20, max_active=64) as srv:
+        pending = []
+        for rid, n in enumerate(sizes):
+            dist = rid % 3
+            t, p = _generated_case(srv, rid, n, dist)
+            pending.append((t, p, n))
+        for t, p, n in pending:
+            lat = srv.wait(t)
+            assert lat >= 0
+            k = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+            v = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+            srv.fetch(t, k, v)
+            sync()
+            keys = inputs.counter_keys(p, n)
+            wk, wv = oracle.lsd_sort(keys, np.arange(n, dtype=np.uint32))
+            assert np.array_equal(to_host(k)[:n], wk), (n, p.dist)
+            assert np.array_equal(to_host(v)[:n], wv), (n, p.dist)
+        p50, p99, gk, done, peak = srv.stats()
+        assert done == len(sizes) and p99 >= p50 > 0 and gk > 0
+        assert 0 < peak <= 64 << 20
+
+
+def test_caller_arrays_sorted_in_place():
+    rng = np.random.default_rng(6)
+    announce("server caller-owned arrays")
+    with Server(hbm_budget_bytes=32 << 20, max_active=16) as srv:
+        cases = []
+        for i, n in enumerate([5, 16384, 16385, 70_000, 1000, 250_000]):
+            keys = inputs.and_keys(n, 4, 40 + i) if i % 2 else inputs.uniform_keys(n, 40 + i)
+            vals = inputs.index_values(n)
+            kd, vd = to_dev(keys), to_dev(vals)
+            cases.append((srv.submit(kd, vd), keys, vals, kd, vd))
+        for t, keys, vals, kd, vd in cases:
+            srv.wait(t)
+            wk, wv = oracle.lsd_sort(keys, vals)
+            assert np.array_equal(to_host(kd), wk) and np.array_equal(to_host(vd), wv)
+        with pytest.raises(RtError) as e:
+            srv.wait(cases[0][0])  # collected by the first wait
+        assert e.value.status == RT_ERR_NOT_FOUND
+
+
+def test_budget_admission_waits_and_rejects():
+    import torch
+    announce("server budget")
+    n = 300_000  # generated, pairs: 4 arrays of 1.2 MB
+    with Server(hbm_budget_bytes=6 << 20, max_active=8) as srv:
+        with pytest.raises(RtError) as e:
+            srv.submit_generated(gen_params_to_c(inputs.counter_params(0, 1, 0)), 1 << 20)
+        assert e.value.status == RT_ERR_BUDGET
+        ts = [(_generated_case(srv, i, n, 0)) for i in range(4)]
+        for t, p in ts:
+            srv.wait(t)
+            k = torch.empty(n, dtype=torch.int32, device="cuda")
+            srv.fetch(t, k, None)
+            sync()
+            assert np.array_equal(to_host(k), np.sort(inputs.counter_keys(p, n)))
+        assert srv.stats()[4] <= 6 << 20
+
+
+def test_keys_only_server():
+    announce("server keys only")
+    with Server(hbm_budget_bytes=16 << 20, max_active=8) as srv:
+        cases = []
+        for i, n in enumerate([3, 9000, 40_000]):
+            keys = inputs.uniform_keys(n, 60 + i)
+            kd = to_dev(keys)
+            cases.append((srv.submit(kd), keys, kd))
+        for t, keys, kd in cases:
+            srv.wait(t)
+            assert np.array_equal(to_host(kd), np.sort(keys))
