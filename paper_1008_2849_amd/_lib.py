@@ -122,8 +122,22 @@ def lib() -> ctypes.CDLL:
                 f = getattr(so, name)
                 f.restype = res
                 f.argtypes = args
+            _load_default_tuning(so)
             _lib = so
     return _lib
+
+
+TUNING_PATH = os.path.join(HERE, "tuning", "gfx950.json")
+
+
+def _load_default_tuning(so) -> None:
+    """The autotuner's table for this GPU (RT_TUNING_FILE overrides the
+    path; an empty value keeps the built-in defaults)."""
+    path = os.environ.get("RT_TUNING_FILE", TUNING_PATH)
+    if path and os.path.exists(path):
+        status = so.rt_load_tuning(path.encode())
+        if status != RT_OK:
+            raise RuntimeError(f"tuning table {path}: {so.rt_last_error().decode(errors='replace')}")
 
 
 def check(status: int, where: str) -> None:
