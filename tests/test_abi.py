@@ -173,3 +173,19 @@ def test_server_argument_errors(so):
     assert so.rt_server_release(None, 1) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_stats(None, None, None, None, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_destroy(None) == _lib.RT_OK
+
+
+def test_committed_tuning_table_loads(so):
+    """The autotuner's table for gfx950 parses, and every entry names a
+    compiled configuration (the library validates each on load)."""
+    path = os.path.join(ROOT, "paper_1008_2849_amd", "tuning", "gfx950.json")
+    table = json.load(open(path))
+    assert table["arch"] == "gfx950" and table["entries"]
+    assert so.rt_load_tuning(path.encode()) == _lib.RT_OK
+    c = _lib.RtConfig()
+    for e in table["entries"]:
+        n = max(2, e["min_n"])
+        assert so.rt_tuned_config(n, 1 if e["op"] == "pairs" else 0, ctypes.byref(c)) == _lib.RT_OK
+        assert [c.digit_bits[i] for i in range(c.num_passes)] == e["digit_bits"]
+        assert (c.block_threads, c.items_per_thread, c.flags) == (e["block"], e["ipt"], e["flags"])
+    assert so.rt_load_tuning(None) == _lib.RT_OK
