@@ -248,9 +248,12 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
 // ---------------------------------------------------------------------------
 
 // Counts the digits of all four passes per tiled segment into
-// hist[row][p][d] (zeroed before).  One tile per block iteration, LDS
-// counters with C lane copies as in k_histogram; the input of pass 0 is the
-// segment's own arrays.
+// hist[row][p][d] (zeroed before).  Block b walks a contiguous range of
+// tiles, so its counters stay in LDS across the tiles of one segment and
+// are flushed to HBM (atomics) only when the segment changes.  Counting is
+// as in k_histogram: C lane-class copies of the counters in padded LDS rows,
+// and a wave batch whose keys share a pass's digit is counted with one add.
+// The input of pass 0 is the segment's own arrays.
 template <int BLOCK, int C>
 __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restrict__ descs,
                                                          const uint32_t *__restrict__ list,
@@ -260,40 +263,79 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
                                                          uint32_t *__restrict__ hist) {
     constexpr int BINS = kSegPasses * kSegRadix;
     constexpr int ROW = BINS + 1;
-    constexpr int PER = kSegTile / BLOCK;
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int U = 8;
+    constexpr uint32_t SPAN = 64 * U;  // keys per wave batch
     __shared__ uint32_t s_h[C * ROW];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
     uint32_t *hc = s_h + (lane % C) * ROW;
+    for (uint32_t i = tid; i < C * ROW; i += BLOCK) s_h[i] = 0u;
     const uint32_t total = h->total_tiles;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        for (uint32_t i = tid; i < C * ROW; i += BLOCK) s_h[i] = 0u;
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t t_begin = min(total, blockIdx.x * per);
+    const uint32_t t_end = min(total, t_begin + per);
+    // adds the LDS counters into the segment's row and clears them
+    auto flush = [&](uint32_t e) {
         __syncthreads();
+        uint32_t *out = hist + static_cast<size_t>(descs[list[e]].row) * BINS;
+        for (uint32_t i = tid; i < BINS; i += BLOCK) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < C; ++w) {
+                c += s_h[w * ROW + i];
+                s_h[w * ROW + i] = 0u;
+            }
+            if (c) atomicAdd(&out[i], c);
+        }
+        __syncthreads();
+    };
+    __syncthreads();
+    uint32_t cur = ~0u;  // list entry whose counts are in LDS (uniform)
+    for (uint32_t t = t_begin; t < t_end; ++t) {
         const uint32_t e = tile_seg[t];
+        if (e != cur) {
+            if (cur != ~0u) flush(cur);
+            cur = e;
+        }
         const SegDesc d = descs[list[e]];
         const uint32_t start = (t - first_tile[e]) * kSegTile;
         const uint32_t valid = min(static_cast<uint32_t>(kSegTile), d.n - start);
         const uint32_t *src = d.k + start;
-#pragma unroll 8
-        for (int j = 0; j < PER; ++j) {
-            const uint32_t i = j * BLOCK + tid;
-            if (i < valid) {
-                const uint32_t key = src[i];
+        for (uint32_t base = wave * SPAN; base < valid; base += WAVES * SPAN) {
+            uint32_t k[U];
+            if (base + SPAN <= valid) {
 #pragma unroll
-                for (int p = 0; p < kSegPasses; ++p)
-                    atomicAdd(&hc[p * kSegRadix + __builtin_amdgcn_ubfe(key, p * kSegBits, kSegBits)], 1u);
+                for (int u = 0; u < U; ++u) k[u] = src[base + u * 64 + lane];
+                const uint32_t k0 = __builtin_amdgcn_readfirstlane(k[0]);
+                uint32_t differ = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) differ |= k[u] ^ k0;
+#pragma unroll
+                for (int p = 0; p < kSegPasses; ++p) {
+                    uint32_t *hp = hc + p * kSegRadix;
+                    if (__builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(differ, p * kSegBits, kSegBits) != 0u) == 0u) {
+                        if (lane == 0) atomicAdd(&hp[__builtin_amdgcn_ubfe(k0, p * kSegBits, kSegBits)], SPAN);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[__builtin_amdgcn_ubfe(k[u], p * kSegBits, kSegBits)], 1u);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t i = base + u * 64 + lane;
+                    if (i >= valid) continue;
+                    const uint32_t key = src[i];
+#pragma unroll
+                    for (int p = 0; p < kSegPasses; ++p)
+                        atomicAdd(&hc[p * kSegRadix + __builtin_amdgcn_ubfe(key, p * kSegBits, kSegBits)], 1u);
+                }
             }
         }
-        __syncthreads();
-        uint32_t *out = hist + static_cast<size_t>(d.row) * BINS;
-        for (uint32_t i = tid; i < BINS; i += BLOCK) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int w = 0; w < C; ++w) c += s_h[w * ROW + i];
-            if (c) atomicAdd(&out[i], c);
-        }
-        __syncthreads();
     }
+    if (cur != ~0u) flush(cur);
 }
 
 // base[row][p][d] = count of digits below d in pass p of the segment: one
