@@ -227,7 +227,7 @@ def main() -> int:
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serve-loads", default="0.7", help="comma list of offered loads (fraction of "
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="comma list of offered loads (fraction of "
                     "single-array throughput); empty to skip serving")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()

@@ -617,25 +617,26 @@ __device__ __forceinline__ uint64_t splitmix_word(uint64_t state, uint64_t i) {
     return mix64(state + (i + 1ull) * 0x9E3779B97F4A7C15ull);
 }
 
+// Key i of a generated stream (the definition rt_generate documents).
+__device__ __forceinline__ uint32_t generate_key(const GenArgs &g, size_t i) {
+    if (g.dist == RT_DIST_UNIFORM) return static_cast<uint32_t>(splitmix_word(g.state, i));
+    if (g.dist == RT_DIST_AND4) {
+        const uint64_t a = splitmix_word(g.state, 2 * i);
+        const uint64_t b = splitmix_word(g.state, 2 * i + 1);
+        return static_cast<uint32_t>(a) & static_cast<uint32_t>(a >> 32) & static_cast<uint32_t>(b) &
+               static_cast<uint32_t>(b >> 32);
+    }
+    const uint64_t u = splitmix_word(g.state, i) >> 32;
+    uint32_t r = 0;
+    while (r < 15 && u >= g.thresholds[r]) ++r;
+    return g.dictionary[r];
+}
+
 static __global__ __launch_bounds__(256) void k_generate(uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                   uint32_t n, GenArgs g) {
     const size_t stride = static_cast<size_t>(gridDim.x) * 256;
     for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
-        uint32_t k;
-        if (g.dist == RT_DIST_UNIFORM) {
-            k = static_cast<uint32_t>(splitmix_word(g.state, i));
-        } else if (g.dist == RT_DIST_AND4) {
-            const uint64_t a = splitmix_word(g.state, 2 * i);
-            const uint64_t b = splitmix_word(g.state, 2 * i + 1);
-            k = static_cast<uint32_t>(a) & static_cast<uint32_t>(a >> 32) & static_cast<uint32_t>(b) &
-                static_cast<uint32_t>(b >> 32);
-        } else {
-            const uint64_t u = splitmix_word(g.state, i) >> 32;
-            uint32_t r = 0;
-            while (r < 15 && u >= g.thresholds[r]) ++r;
-            k = g.dictionary[r];
-        }
-        keys[i] = k;
+        keys[i] = generate_key(g, i);
         if (vals) vals[i] = g.value_base + static_cast<uint32_t>(i);
     }
 }

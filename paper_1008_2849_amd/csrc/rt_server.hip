@@ -5,9 +5,17 @@
 // admitted request, one counting-sort pass over its tiles (requests of more
 // than 16K items) or its whole sort in LDS (smaller ones), all in the same
 // few launches of the segmented kernels.  A request admitted between two
-// steps joins the next one: its digit histograms and prefix sums are built
-// at the start of that step and its first pass runs in it.  A request of
-// more than 16K items is done after four steps, a smaller one after one.
+// steps joins the next one: its input is generated (for generated
+// requests), its digit histograms and prefix sums are built at the start of
+// that step, and its first pass runs in it.  A request of more than 16K
+// items is done after four steps, a smaller one after one.
+//
+// The scheduler thread builds a step on the host (descriptors, work lists),
+// uploads it from pinned memory, enqueues its kernels on the server's
+// stream and records an event; a request is reported done when the event
+// of its last step has fired.  Up to `depth` steps may be in flight
+// (RT_SERVER_DEPTH, default 1: requests that arrive during a step then join
+// the very next one, which measured best for latency and throughput).
 //
 // Memory: one arena of hbm_budget_bytes, carved first-fit (256-byte
 // granules) into each request's temporaries (and, for generated requests,
@@ -17,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -109,13 +118,22 @@ struct Request {
 
 bool is_small(const Request &r) { return r.n <= kSegClassMax[kSegClasses - 1]; }
 
+// One generated request of a step: its arrays and stream parameters.
+struct GenDesc {
+    uint32_t *k, *v;
+    uint32_t n;
+    uint32_t first_chunk;  // chunks of the step's generated requests before this one
+    GenArgs g;
+};
+constexpr uint32_t kGenChunk = 4096;  // items per generating block
+
 // Device metadata of one step: [header | descs | lists | first_tile |
 // tile_seg] for the pass work, a second header/list/first_tile/tile_seg set
 // for the histogram work of fresh requests, the per-request rows and the
 // lookback words.  The leading "step block" (headers, descs, lists) is
 // uploaded from pinned host memory once per step.
 struct Meta {
-    size_t hdr_pass, hdr_hist, descs, lists_pass, list_hist, block_bytes;
+    size_t hdr_pass, hdr_hist, descs, lists_pass, list_hist, block_bytes, gen;
     size_t first_pass, first_hist, seg_pass, seg_hist, hist, base, status, total;
     uint32_t max_tiles;
 };
@@ -136,6 +154,7 @@ Meta make_meta(uint32_t max_active, size_t arena_bytes) {
     m.lists_pass = off; off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
     m.list_hist = off;  off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
     m.block_bytes = off;
+    m.gen = off;        off += a(sizeof(GenDesc) * max_active);
     m.first_pass = off; off += a(sizeof(uint32_t) * (max_active + 1));
     m.first_hist = off; off += a(sizeof(uint32_t) * (max_active + 1));
     m.seg_pass = off;   off += a(sizeof(uint32_t) * m.max_tiles);
@@ -145,6 +164,25 @@ Meta make_meta(uint32_t max_active, size_t arena_bytes) {
     m.status = off;     off += a(sizeof(uint32_t) * kSegRadix * static_cast<size_t>(m.max_tiles));
     m.total = off;
     return m;
+}
+
+// Fills the inputs of every generated request of a step.  The requests'
+// items are cut into chunks of kGenChunk, numbered across the requests in
+// order; block b fills chunk b (found by binary search over first_chunk).
+__global__ __launch_bounds__(256) void k_srv_generate(const GenDesc *__restrict__ gd, uint32_t count) {
+    uint32_t lo = 0, hi = count - 1;  // the last request with first_chunk <= b
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (gd[mid].first_chunk <= blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const GenDesc &d = gd[lo];
+    const uint32_t begin = (blockIdx.x - d.first_chunk) * kGenChunk;
+    const uint32_t end = min(d.n, begin + kGenChunk);
+    for (uint32_t i = begin + threadIdx.x; i < end; i += 256) {
+        d.k[i] = generate_key(d.g, i);
+        if (d.v) d.v[i] = i;
+    }
 }
 
 // Zeroes the histogram rows of the listed (fresh) requests.
@@ -163,11 +201,22 @@ __global__ __launch_bounds__(256) void k_srv_clear_rows(const SegDesc *__restric
 
 using namespace rt;
 
+constexpr int kRing = 8;  // most steps in flight (ring slots)
+
+// Host side of one step in flight: its pinned staging (step block, then the
+// generated-request descriptors, then the header words read back), the
+// event that marks its end, and the requests it touched / finishes.
+struct StepSlot {
+    char *host = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Request *> members;
+    std::vector<Request *> finishing;
+};
+
 struct rt_server {
     int device = 0;
-    hipStream_t stream = nullptr;   // steps
-    hipStream_t io = nullptr;       // generation is on `stream`; fetch copies here
-    hipEvent_t step_done = nullptr;
+    hipStream_t stream = nullptr;  // every step, in order
+    hipStream_t io = nullptr;      // fetch copies
     char *arena = nullptr;
     size_t arena_bytes = 0;
     Arena alloc;
@@ -175,7 +224,10 @@ struct rt_server {
     uint32_t max_active = 0;
     Meta meta{};
     char *dmeta = nullptr;
-    char *hblock = nullptr;  // pinned staging of the step block
+    StepSlot ring[kRing];
+    int depth = 1;       // steps in flight at most (1..kRing); 1 measured best
+    int ring_head = 0;   // oldest step in flight
+    int ring_count = 0;  // steps in flight
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -199,6 +251,10 @@ size_t footprint(const Request &r) {
     const size_t arr = round_up(r.n * sizeof(uint32_t));
     const size_t per = r.with_values ? 2 : 1;
     return (r.generated ? per * arr : 0) + (is_small(r) ? 0 : per * arr);
+}
+
+size_t slot_bytes(const Meta &m, uint32_t max_active) {
+    return m.block_bytes + sizeof(GenDesc) * max_active + 2 * 256;
 }
 
 // Admit queued requests in arrival order while memory and slots last.
@@ -243,48 +299,36 @@ std::vector<Request *> admit(rt_server *s) {
     return fresh;
 }
 
-void fail_active(rt_server *s, rt_status st) {
-    const std::string why = last_error();  // set on this (the scheduler's) thread
-    std::lock_guard<std::mutex> lk(s->mu);
-    const double t = now_us();
-    for (Request *r : s->active) {
-        r->state = kDone;
-        r->status = st;
-        r->error = why;
-        r->t_done = t;
-        if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
-        s->used -= r->tmp_bytes;
-        r->tmp_bytes = 0;
-        s->free_rows.push_back(r->row);
-    }
-    s->active.clear();
-    s->cv_done.notify_all();
-}
+// Builds the next step in ring slot `slot` from the active requests (mu
+// held): descriptors and work lists on the host, then the bookkeeping that
+// does not depend on the device finishing -- every request advances one
+// pass, and the temporaries and rows of the requests this step finishes go
+// back to the pools at once (later steps run after this one on the same
+// stream, so reusing them is ordered behind its kernels).
+struct StepPlan {
+    size_t tiles = 0;
+    uint32_t fresh_tiled = 0, tiled = 0, small[kSegClasses] = {0, 0, 0}, gen = 0, gen_chunks = 0;
+    bool vals = false;
+};
 
-// One step: histograms of fresh tiled requests, one pass of every tiled
-// request, the whole sort of every fresh small request.
-rt_status run_step(rt_server *s, const std::vector<Request *> &fresh) {
+StepPlan build_step(rt_server *s, StepSlot &slot) {
     const Meta &m = s->meta;
-    hipStream_t st = s->stream;
-    // generate the inputs of fresh generated requests
-    for (Request *r : fresh) {
-        if (!r->generated) continue;
-        rt_status g = rt_generate(r->k, r->v, r->n, &r->gen, 0u, st);
-        if (g != RT_OK) return g;
-    }
-    // step block on the host
-    char *hb = s->hblock;
+    StepPlan P;
+    char *hb = slot.host;
     memset(hb, 0, m.block_bytes);
     SegHeader *hp = reinterpret_cast<SegHeader *>(hb + m.hdr_pass);
     SegHeader *hh = reinterpret_cast<SegHeader *>(hb + m.hdr_hist);
     SegDesc *descs = reinterpret_cast<SegDesc *>(hb + m.descs);
     uint32_t *lists = reinterpret_cast<uint32_t *>(hb + m.lists_pass);
     uint32_t *hlist = reinterpret_cast<uint32_t *>(hb + m.list_hist) + static_cast<size_t>(kSegLarge) * s->max_active;
+    GenDesc *gen = reinterpret_cast<GenDesc *>(hb + m.block_bytes);
     const uint32_t stride = s->max_active;
-    size_t tiles = 0;
-    bool any_small = false;
+    slot.members.assign(s->active.begin(), s->active.end());
+    slot.finishing.clear();
+    std::vector<Request *> still;
     for (size_t i = 0; i < s->active.size(); ++i) {
         Request *r = s->active[i];
+        P.vals = P.vals || r->with_values;
         SegDesc &d = descs[i];
         d.k = r->k;
         d.v = r->with_values ? r->v : nullptr;
@@ -293,25 +337,69 @@ rt_status run_step(rt_server *s, const std::vector<Request *> &fresh) {
         d.n = static_cast<uint32_t>(r->n);
         d.pass = r->pass;
         d.row = r->row;
-        if (r->n < 2) continue;
-        if (is_small(*r)) {
-            if (!r->fresh) continue;
+        if (r->fresh && r->generated && r->n > 0) {
+            GenDesc &g = gen[P.gen++];
+            g.k = r->k;
+            g.v = r->with_values ? r->v : nullptr;
+            g.n = static_cast<uint32_t>(r->n);
+            g.first_chunk = P.gen_chunks;
+            P.gen_chunks += static_cast<uint32_t>((r->n + kGenChunk - 1) / kGenChunk);
+            memset(&g.g, 0, sizeof g.g);
+            g.g.dist = r->gen.dist;
+            g.g.state = r->gen.state;
+            memcpy(g.g.dictionary, r->gen.dictionary, sizeof g.g.dictionary);
+            memcpy(g.g.thresholds, r->gen.thresholds, sizeof g.g.thresholds);
+        }
+        bool finished;
+        if (r->n < 2) {
+            finished = true;
+        } else if (is_small(*r)) {
             int c = kSegClasses - 1;
             for (int q = kSegClasses - 1; q >= 0; --q)
                 if (r->n <= kSegClassMax[q]) c = q;
             lists[static_cast<size_t>(c) * stride + hp->count[c]++] = static_cast<uint32_t>(i);
-            any_small = true;
+            ++P.small[c];
+            finished = true;  // small requests are sorted whole in their first step
         } else {
             lists[static_cast<size_t>(kSegLarge) * stride + hp->count[kSegLarge]++] = static_cast<uint32_t>(i);
-            tiles += (r->n + kSegTile - 1) / kSegTile;
-            if (r->fresh) hlist[hh->count[kSegLarge]++] = static_cast<uint32_t>(i);
+            ++P.tiled;
+            P.tiles += (r->n + kSegTile - 1) / kSegTile;
+            if (r->fresh) {
+                hlist[hh->count[kSegLarge]++] = static_cast<uint32_t>(i);
+                ++P.fresh_tiled;
+            }
+            finished = r->pass + 1 == kSegPasses;
         }
+        r->fresh = false;
+        if (!finished) {
+            ++r->pass;
+            still.push_back(r);
+            continue;
+        }
+        slot.finishing.push_back(r);
+        if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
+        s->used -= r->tmp_bytes;
+        r->tmp_bytes = 0;
+        s->free_rows.push_back(r->row);
     }
-    if (tiles > m.max_tiles) return set_error(RT_ERR_HIP, "server: step of %zu tiles exceeds %u", tiles, m.max_tiles);
-    hipError_t e = hipMemcpyAsync(s->dmeta, hb, m.block_bytes, hipMemcpyHostToDevice, st);
+    s->active.swap(still);
+    ++s->steps;
+    return P;
+}
+
+// Enqueues a built step on the server's stream and records its event.
+rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
+    const Meta &m = s->meta;
+    hipStream_t st = s->stream;
+    const uint32_t stride = s->max_active;
+    char *dm = s->dmeta;
+    char *hb = slot.host;
+    if (P.tiles > m.max_tiles) return set_error(RT_ERR_HIP, "server: step of %zu tiles exceeds %u", P.tiles, m.max_tiles);
+    hipError_t e = hipMemcpyAsync(dm, hb, m.block_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && P.gen)
+        e = hipMemcpyAsync(dm + m.gen, hb + m.block_bytes, sizeof(GenDesc) * P.gen, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: step upload: %s", hipGetErrorString(e));
 
-    char *dm = s->dmeta;
     SegHeader *d_hp = reinterpret_cast<SegHeader *>(dm + m.hdr_pass);
     SegHeader *d_hh = reinterpret_cast<SegHeader *>(dm + m.hdr_hist);
     const SegDesc *d_descs = reinterpret_cast<const SegDesc *>(dm + m.descs);
@@ -326,118 +414,159 @@ rt_status run_step(rt_server *s, const std::vector<Request *> &fresh) {
     uint32_t *d_base = reinterpret_cast<uint32_t *>(dm + m.base);
     uint32_t *d_status = reinterpret_cast<uint32_t *>(dm + m.status);
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
-    auto grid = [](size_t want, uint32_t cap) { return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(want, cap))); };
+    auto grid = [](size_t want, uint32_t cap) {
+        return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(want, cap)));
+    };
 
-    if (hh->count[kSegLarge]) {  // histograms and prefix sums of fresh tiled requests
-        const uint32_t fresh_n = hh->count[kSegLarge];
-        hipLaunchKernelGGL(k_srv_clear_rows, dim3(grid(fresh_n, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
-                           d_hist);
+    if (P.gen)  // inputs of the fresh generated requests
+        hipLaunchKernelGGL(k_srv_generate, dim3(P.gen_chunks), dim3(256), 0, st,
+                           reinterpret_cast<const GenDesc *>(dm + m.gen), P.gen);
+    if (P.fresh_tiled) {  // histograms and prefix sums of fresh tiled requests
+        hipLaunchKernelGGL(k_srv_clear_rows, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist,
+                           d_hh, d_hist);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_hlist, d_first_h, d_hh, stride,
                            m.max_tiles);
-        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((m.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
                            d_hh, d_seg_h);
-        hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(tiles, cus * 2)), dim3(512), 0, st, d_descs, d_hlist,
-                           d_first_h, d_seg_h, d_hh, d_hist);
-        hipLaunchKernelGGL(k_seg_plan, dim3(grid(fresh_n, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh, d_hist,
-                           d_base);
+        hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_descs,
+                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist);
+        hipLaunchKernelGGL(k_seg_plan, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
+                           d_hist, d_base);
     }
-    if (hp->count[kSegLarge]) {  // one pass of every tiled request
-        hipLaunchKernelGGL(k_fill_zero, dim3(grid((tiles * kSegRadix + 4095) / 4096, 4096)), dim3(256), 0, st,
-                           d_status, tiles * kSegRadix);
+    if (P.tiled) {  // one pass of every tiled request, each at its own pass
+        hipLaunchKernelGGL(k_fill_zero, dim3(grid((P.tiles * kSegRadix + 4095) / 4096, 4096)), dim3(256), 0, st,
+                           d_status, P.tiles * kSegRadix);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_hp, stride,
                            m.max_tiles);
-        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p, d_hp,
-                           d_seg_p);
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p,
+                           d_hp, d_seg_p);
         uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, tile_ctr) / 4;
         uint32_t *err = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, error) / 4;
-        bool vals = false;
-        for (Request *r : s->active) vals = vals || r->with_values;
-        // keys-only requests inside a mixed step: their descriptors carry
-        // no value arrays, so the value kernel would dereference NULL; such
-        // steps run the keys-only kernel for them through a second launch
-        // over the same list would complicate the tile map, so a server is
-        // either all-pairs or all-keys (enforced at submit).
-        if (vals)
-            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(tiles)),
+        // a server holds one value layout (checked at submit), so one
+        // kernel flavour serves every request of the step
+        if (P.vals)
+            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
                                ctr, err);
         else
-            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(tiles)),
+            hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
                                ctr, err);
     }
-    if (any_small) {
-        bool vals = false;
-        for (Request *r : s->active) vals = vals || r->with_values;
-        const size_t n0 = hp->count[0], n1 = hp->count[1], n2 = hp->count[2];
-        if (vals) {
-            if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
-            if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, d_lists + stride, d_hp, 1);
-            if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, d_lists + 2 * static_cast<size_t>(stride), d_hp, 2);
-        } else {
-            if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
-            if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, d_lists + stride, d_hp, 1);
-            if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, d_lists + 2 * static_cast<size_t>(stride), d_hp, 2);
-        }
+    const uint32_t n0 = P.small[0], n1 = P.small[1], n2 = P.small[2];
+    const uint32_t *l1 = d_lists + stride, *l2 = d_lists + 2 * static_cast<size_t>(stride);
+    if (P.vals) {
+        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
+        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1);
+        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2);
+    } else {
+        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
+        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1);
+        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: launch: %s", hipGetErrorString(e));
     // the error words of both headers come back with the step
-    e = hipMemcpyAsync(hb + m.hdr_pass, dm + m.hdr_pass, 2 * ((sizeof(SegHeader) + 255) & ~size_t(255)),
-                       hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(s->step_done, st);
-    if (e == hipSuccess) e = hipEventSynchronize(s->step_done);
+    char *rb = hb + m.block_bytes + sizeof(GenDesc) * s->max_active;
+    e = hipMemcpyAsync(rb, dm + m.hdr_pass, 2 * 256, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, st);
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: step: %s", hipGetErrorString(e));
-    if (hp->error | hh->error)
-        return set_error(RT_ERR_HIP, "server: device error word 0x%x", hp->error | hh->error);
     return RT_OK;
+}
+
+// Retires the oldest step in flight once its event has fired (waiting for
+// it when `block`): the requests it finished become done.  Returns whether
+// a step was retired.
+bool retire_oldest(rt_server *s, bool block) {
+    if (s->ring_count == 0) return false;
+    StepSlot &slot = s->ring[s->ring_head];
+    hipError_t e = block ? hipEventSynchronize(slot.done) : hipEventQuery(slot.done);
+    if (e == hipErrorNotReady) return false;
+    const char *rb = slot.host + s->meta.block_bytes + sizeof(GenDesc) * s->max_active;
+    uint32_t err = 0;
+    rt_status status = RT_OK;
+    std::string why;
+    if (e != hipSuccess) {
+        status = RT_ERR_HIP;
+        why = std::string("server: step failed: ") + hipGetErrorString(e);
+    } else {
+        err = reinterpret_cast<const SegHeader *>(rb)->error | reinterpret_cast<const SegHeader *>(rb + 256)->error;
+        if (err) {
+            status = RT_ERR_HIP;
+            char buf[96];
+            snprintf(buf, sizeof buf, "server: device error word 0x%x", err);
+            why = buf;
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (status != RT_OK)  // every request the step touched carries the failure
+        for (Request *r : slot.members) {
+            r->status = status;
+            r->error = why;
+        }
+    const double t = now_us();
+    for (Request *r : slot.finishing) {
+        r->state = kDone;
+        r->t_done = t;
+        if (r->status == RT_OK) {
+            s->latencies.push_back(t - r->t_submit);
+            s->items_done += r->n;
+            s->last_done = t;
+        }
+    }
+    slot.members.clear();
+    slot.finishing.clear();
+    s->ring_head = (s->ring_head + 1) % kRing;
+    --s->ring_count;
+    s->cv_done.notify_all();
+    return true;
 }
 
 void scheduler(rt_server *s) {
     (void)hipSetDevice(s->device);
     for (;;) {
-        std::vector<Request *> fresh;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-            if (s->stop) return;
-            fresh = admit(s);
-            if (s->active.empty()) {  // the head of the queue waits for memory
-                s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
-                continue;
-            }
+        while (retire_oldest(s, false)) {
         }
-        const rt_status st = run_step(s, fresh);
-        if (st != RT_OK) {
-            (void)hipStreamSynchronize(s->stream);  // nothing may still use what is freed
-            fail_active(s, st);
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop) break;
+        if (s->ring_count >= s->depth) {  // enough steps in flight: wait for the oldest
+            lk.unlock();
+            retire_oldest(s, true);
             continue;
         }
-        std::lock_guard<std::mutex> lk(s->mu);
-        ++s->steps;
-        const double t = now_us();
-        std::vector<Request *> still;
-        for (Request *r : s->active) {
-            r->fresh = false;
-            const bool finished = r->n < 2 || is_small(*r) || r->pass + 1 == kSegPasses;
-            if (!finished) {
-                ++r->pass;
-                still.push_back(r);
+        admit(s);
+        if (s->active.empty()) {
+            if (s->ring_count) {
+                lk.unlock();
+                retire_oldest(s, true);
                 continue;
             }
-            r->state = kDone;
-            r->t_done = t;
-            if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
-            s->used -= r->tmp_bytes;
-            r->tmp_bytes = 0;
-            s->free_rows.push_back(r->row);
-            s->latencies.push_back(t - r->t_submit);
-            s->items_done += r->n;
-            s->last_done = t;
+            // idle, or the head of the queue waits for memory to be released
+            if (s->queue.empty())
+                s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            else
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            continue;
         }
-        s->active.swap(still);
-        s->cv_done.notify_all();
+        StepSlot &slot = s->ring[(s->ring_head + s->ring_count) % kRing];
+        const StepPlan P = build_step(s, slot);
+        ++s->ring_count;
+        lk.unlock();
+        const rt_status st = enqueue_step(s, slot, P);
+        if (st != RT_OK) {
+            // nothing of this step may have run: fail what it touched once
+            // the stream has drained, and retire it
+            (void)hipStreamSynchronize(s->stream);
+            std::lock_guard<std::mutex> g(s->mu);
+            for (Request *r : slot.members) {
+                r->status = st;
+                r->error = last_error();
+            }
+            (void)hipEventRecord(slot.done, s->stream);
+        }
     }
+    // drain: finish what is in flight, so waiters see their results
+    while (s->ring_count) retire_oldest(s, true);
 }
 
 rt_status enqueue(rt_server *s, std::unique_ptr<Request> r, uint64_t *ticket) {
@@ -481,18 +610,27 @@ extern "C" rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_acti
                          hipGetErrorString(e));
     }
     e = hipMalloc(reinterpret_cast<void **>(&s->dmeta), s->meta.total);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->hblock), s->meta.block_bytes + 2 * 256);
+    for (int i = 0; i < kRing && e == hipSuccess; ++i) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->ring[i].host), slot_bytes(s->meta, max_active));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ring[i].done, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_done, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         if (s->dmeta) (void)hipFree(s->dmeta);
-        if (s->hblock) (void)hipHostFree(s->hblock);
+        for (int i = 0; i < kRing; ++i) {
+            if (s->ring[i].host) (void)hipHostFree(s->ring[i].host);
+            if (s->ring[i].done) (void)hipEventDestroy(s->ring[i].done);
+        }
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->io) (void)hipStreamDestroy(s->io);
         (void)hipFree(s->arena);
         return set_error(RT_ERR_OUT_OF_MEMORY, "rt_server_create: metadata: %s", hipGetErrorString(e));
+    }
+    if (const char *d = getenv("RT_SERVER_DEPTH")) {  // steps in flight (tuning knob)
+        const int v = atoi(d);
+        if (v >= 1 && v <= kRing) s->depth = v;
     }
     s->alloc.reset(s->arena_bytes);
     s->free_rows.reserve(max_active);
@@ -666,10 +804,12 @@ extern "C" rt_status rt_server_destroy(rt_server *s) {
         }
         s->cv_done.notify_all();
     }
-    (void)hipEventDestroy(s->step_done);
+    for (int i = 0; i < kRing; ++i) {
+        (void)hipEventDestroy(s->ring[i].done);
+        (void)hipHostFree(s->ring[i].host);
+    }
     (void)hipStreamDestroy(s->stream);
     (void)hipStreamDestroy(s->io);
-    (void)hipHostFree(s->hblock);
     (void)hipFree(s->dmeta);
     (void)hipFree(s->arena);
     delete s;
