@@ -134,12 +134,112 @@ def bench_batched(rts, inputs, dev, K, W, single_gkeys):
             "frac_of_single_array": round(gk / single_gkeys, 4), "parity_properties_ok": ok}
 
 
+def bench_pcie(rts, dev, keys_h, vals_h, cfg, ref_k, ref_v, reps=3):
+    """Transfer-inclusive rate for host-resident data (the paper's GPU+PCIe
+    comparison in Section 5): pinned host keys/values -> device, sort,
+    device -> pinned host, timed end to end on one stream."""
+    import numpy as np
+    import torch
+    n = keys_h.size
+    hk = torch.from_numpy(keys_h.view(np.int32)).pin_memory()
+    hv = torch.from_numpy(vals_h.view(np.int32)).pin_memory()
+    ok = torch.empty_like(hk).pin_memory()
+    ov = torch.empty_like(hv).pin_memory()
+    dk = torch.empty(n, dtype=torch.int32, device=dev)
+    dv = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(rts.workspace_bytes(n, True, cfg), dtype=torch.uint8, device=dev)
+    times, h2d, d2h = [], [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        dk.copy_(hk, non_blocking=True)
+        dv.copy_(hv, non_blocking=True)
+        e[1].record()
+        rts.sort_ex(dk, dv, cfg, ws)
+        e[2].record()
+        ok.copy_(dk, non_blocking=True)
+        ov.copy_(dv, non_blocking=True)
+        e[3].record()
+        torch.cuda.synchronize()
+        if r == 0:
+            continue  # warm-up
+        times.append(e[0].elapsed_time(e[3]))
+        h2d.append(e[0].elapsed_time(e[1]))
+        d2h.append(e[2].elapsed_time(e[3]))
+    ms = float(np.median(times))
+    # the device result equals the checked sort of the same input
+    same = bool(torch.equal(dk, ref_k)) and bool(torch.equal(dv, ref_v))
+    return {"Gkeys/s": round(n / ms / 1e6, 3), "ms": round(ms, 3),
+            "h2d_GBps": round(8.0 * n / float(np.median(h2d)) / 1e6, 1),
+            "d2h_GBps": round(8.0 * n / float(np.median(d2h)) / 1e6, 1),
+            "note": "pinned host -> HBM, sort, HBM -> pinned host; context for the paper's GPU+PCIe figure",
+            "matches_device_sort": same}
+
+
+def bench_serving_closed(rts, inputs, inflight, seconds, warm_s, single_gkeys, budget_gib=32):
+    """Closed loop: `inflight` requests (the serving mix of sizes and key
+    distributions, generated on the device) are kept outstanding; each
+    completion is replaced by the next request.  Measures the server's
+    capacity and the latency at that throughput."""
+    import numpy as np
+    from paper_1008_2849_amd.api import gen_params_to_c
+    from paper_1008_2849_amd.server import Server
+    seed = inputs.SEED_SERVING + 100
+    count = 1 << 20
+    sizes = inputs.serving_request_sizes(count, seed)
+    dists = inputs.serving_request_dists(count, seed)
+    states = inputs.splitmix64_words(seed, 0, count)
+    templates = [gen_params_to_c(inputs.counter_params(d, seed, 0)) for d in range(3)]
+
+    def params(i):
+        g = templates[int(dists[i])]
+        g.state = int(states[i])
+        return g
+
+    srv = Server(hbm_budget_bytes=budget_gib << 30, max_active=4096)
+    nxt = 0
+    submit_time = {}
+    for _ in range(inflight):
+        t = srv.submit_generated(params(nxt), int(sizes[nxt]))
+        submit_time[t] = (nxt, time.perf_counter())
+        nxt += 1
+    t0 = time.perf_counter()
+    lats, items = [], 0
+    t_meas = None
+    while True:
+        t, ms = srv.wait_any()
+        i, _ = submit_time.pop(t)
+        srv.release(t)
+        now = time.perf_counter() - t0
+        if now >= warm_s:
+            if t_meas is None:
+                t_meas = time.perf_counter()
+            lats.append(ms / 1e3)
+            items += int(sizes[i])
+        if now >= warm_s + seconds:
+            break
+        t2 = srv.submit_generated(params(nxt), int(sizes[nxt]))
+        submit_time[t2] = (nxt, time.perf_counter())
+        nxt += 1
+    span = time.perf_counter() - t_meas
+    while submit_time:  # drain
+        t, _ = srv.wait_any()
+        submit_time.pop(t, None)
+        srv.release(t)
+    srv.close()
+    gk = items / span / 1e9
+    return {"mode": "closed_loop", "inflight": inflight, "achieved_Gkeys/s": round(gk, 3),
+            "frac_of_single_array": round(gk / single_gkeys, 4),
+            "p50_ms": round(float(np.percentile(lats, 50)), 3), "p99_ms": round(float(np.percentile(lats, 99)), 3),
+            "requests_measured": len(lats), "seconds": seconds}
+
+
 def bench_serving(rts, inputs, load, seconds, warm_s, single_gkeys, budget_gib=32):
     """Poisson arrivals of device-generated requests (sizes 2^U[10,24],
     distribution uniform / AND-4 / Zipf-16) offered at `load` times the
     single-array throughput; latency = completion - submission."""
     import ctypes
-    import queue
     import threading
     import numpy as np
     from paper_1008_2849_amd.api import gen_params_to_c
@@ -161,21 +261,35 @@ def bench_serving(rts, inputs, load, seconds, warm_s, single_gkeys, budget_gib=3
         g.state = int(states[i])
         params.append(g)
     srv = Server(hbm_budget_bytes=budget_gib << 30, max_active=4096)
-    tickets = queue.Queue()
+    index_of = {}      # ticket -> request index
     lat = {}
     failures = []
+    state = {"submitted": None}
+    lock = threading.Lock()
 
     def collect():
+        # completion order: a finished request's memory comes back at once
+        from paper_1008_2849_amd._lib import RtError, RT_ERR_NOT_FOUND, RT_ERR_TIMEOUT
+        got = 0
         while True:
-            item = tickets.get()
-            if item is None:
+            with lock:
+                total = state["submitted"]
+            if total is not None and got >= total:
                 return
-            i, t = item
             try:
-                lat[i] = srv.wait(t)
-                srv.release(t)
-            except Exception as e:  # reported in the result line
+                t, ms = srv.wait_any(timeout_us=20000)
+            except RtError as e:
+                if e.status in (RT_ERR_TIMEOUT, RT_ERR_NOT_FOUND):
+                    continue
                 failures.append(repr(e))
+                got += 1
+                continue
+            with lock:
+                i = index_of.get(t)
+            if i is not None:
+                lat[i] = ms
+            srv.release(t)
+            got += 1
 
     th = threading.Thread(target=collect, daemon=True)
     th.start()
@@ -187,14 +301,17 @@ def bench_serving(rts, inputs, load, seconds, warm_s, single_gkeys, budget_gib=3
         if now > end:
             break
         while i < count and arrivals[i] <= now:
-            tickets.put((i, srv.submit_generated(params[i], int(sizes[i]))))
+            t = srv.submit_generated(params[i], int(sizes[i]))
+            with lock:
+                index_of[t] = i
             i += 1
         if i < count:
             gap = arrivals[i] - (time.perf_counter() - t0)
             if gap > 2e-4:
                 time.sleep(gap - 1e-4)
     submitted = i
-    tickets.put(None)
+    with lock:
+        state["submitted"] = submitted
     th.join()
     wall = time.perf_counter() - t0
     p50_all, p99_all, gk_srv, done, peak = srv.stats()
@@ -227,9 +344,12 @@ def main() -> int:
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="comma list of offered loads (fraction of "
+    ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
+    ap.add_argument("--serve-loads", default="0.5", help="comma list of offered loads (fraction of "
                     "single-array throughput); empty to skip serving")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-inflight", default="64,256",
+                    help="comma list of closed-loop request counts kept in flight (empty to skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -361,18 +481,28 @@ def main() -> int:
                "matches_gpu_bit_exact": same}
         log(f"oracle {dt:.1f}s, GPU output {'==' if same else '!='} oracle")
 
+    pcie = None
+    if not args.no_pcie and vals_on:
+        log("transfer-inclusive leg")
+        pcie = bench_pcie(rts, dev, keys_h, vals_h, cfg, slots[W + K - 1][0], slots[W + K - 1][1])
+        log(f"pcie: {pcie}")
+
     batched = None
     if not args.no_batched and args.workload == "pairs_256m_uniform":
         log("batched workload")
         batched = bench_batched(rts, inputs, dev, K, W, gkeys)
         log(f"batched: {batched}")
     serving = []
-    if args.serve_loads and args.workload == "pairs_256m_uniform":
+    if (args.serve_loads or args.serve_inflight) and args.workload == "pairs_256m_uniform":
         del slots
         torch.cuda.empty_cache()
-        for load in (float(x) for x in args.serve_loads.split(",")):
+        for load in (float(x) for x in args.serve_loads.split(",") if x):
             log(f"serving at load {load}")
             serving.append(bench_serving(rts, inputs, load, args.serve_seconds, 1.0, gkeys))
+            log(f"serving: {serving[-1]}")
+        for inflight in (int(x) for x in args.serve_inflight.split(",") if x):
+            log(f"serving closed loop, {inflight} in flight")
+            serving.append(bench_serving_closed(rts, inputs, inflight, args.serve_seconds, 1.0, gkeys))
             log(f"serving: {serving[-1]}")
 
     line = {
@@ -403,6 +533,7 @@ def main() -> int:
         "copy_peak_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
         "parity_properties_ok": props,
+        "transfer_inclusive": pcie,
         "batched": batched,
         "serving": serving,
         "kernel_source_digest": digest,
@@ -410,7 +541,8 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     ok = props and (cpu is None or cpu["matches_gpu_bit_exact"])
     ok = ok and (batched is None or batched["parity_properties_ok"])
-    ok = ok and all(not s["failures"] for s in serving)
+    ok = ok and all(not s.get("failures") for s in serving)
+    ok = ok and (pcie is None or pcie["matches_device_sort"])
     return 0 if ok else 3
 
 

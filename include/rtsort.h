@@ -245,6 +245,15 @@ rt_status rt_server_submit_generated(rt_server *s, const rt_gen_params *params, 
 rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
 
 /*
+ * Wait for whichever request finishes next (completion order) that no wait
+ * has reported yet; *ticket receives it.  Same timeout, latency and status
+ * rules as rt_server_wait; RT_ERR_NOT_FOUND when no request is outstanding.
+ * A generated request stays fetchable until rt_server_fetch or
+ * rt_server_release.
+ */
+rt_status rt_server_wait_any(rt_server *s, int64_t timeout_us, uint64_t *ticket, double *latency_us);
+
+/*
  * Copy a finished generated request's sorted arrays into caller device
  * buffers (out_vals may be NULL) and release its memory.
  */

@@ -91,6 +91,7 @@ SIGNATURES = {
     "rt_server_submit": (ctypes.c_int, [vp, vp, vp, sz, ctypes.POINTER(u64)]),
     "rt_server_submit_generated": (ctypes.c_int, [vp, ctypes.POINTER(RtGenParams), sz, ctypes.POINTER(u64)]),
     "rt_server_wait": (ctypes.c_int, [vp, u64, i64, dblp]),
+    "rt_server_wait_any": (ctypes.c_int, [vp, i64, ctypes.POINTER(u64), dblp]),
     "rt_server_fetch": (ctypes.c_int, [vp, u64, vp, vp]),
     "rt_server_release": (ctypes.c_int, [vp, u64]),
     "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),

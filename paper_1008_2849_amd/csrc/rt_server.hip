@@ -113,6 +113,7 @@ struct Request {
     uint32_t pass = 0;  // next pass (tiled requests)
     uint32_t row = 0;   // histogram / prefix-sum row
     bool fresh = true;  // histograms not built yet
+    bool collected = false;  // reported by a wait
     double t_submit = 0, t_done = 0;
 };
 
@@ -232,6 +233,8 @@ struct rt_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
+    std::deque<uint64_t> finished;  // tickets in completion order, for rt_server_wait_any
+    uint64_t uncollected = 0;       // requests submitted and not yet reported by a wait
     std::vector<Request *> active;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
     std::vector<uint32_t> free_rows;
@@ -508,6 +511,7 @@ bool retire_oldest(rt_server *s, bool block) {
     for (Request *r : slot.finishing) {
         r->state = kDone;
         r->t_done = t;
+        s->finished.push_back(r->id);
         if (r->status == RT_OK) {
             s->latencies.push_back(t - r->t_submit);
             s->items_done += r->n;
@@ -582,6 +586,7 @@ rt_status enqueue(rt_server *s, std::unique_ptr<Request> r, uint64_t *ticket) {
     r->t_submit = now_us();
     if (s->first_submit < 0) s->first_submit = r->t_submit;
     *ticket = r->id;
+    ++s->uncollected;
     s->queue.push_back(r.get());
     s->all[r->id] = std::move(r);
     s->cv_work.notify_one();
@@ -689,6 +694,22 @@ extern "C" rt_status rt_server_submit_generated(rt_server *s, const rt_gen_param
     return enqueue(s, std::move(r), ticket);
 }
 
+// Reports a finished request (mu held): its latency and status; a request
+// with nothing left to fetch is dropped.
+static rt_status collect(rt_server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it,
+                         double *latency_us, const char *what) {
+    Request *r = it->second.get();
+    const uint64_t id = r->id;
+    if (!r->collected) --s->uncollected;
+    r->collected = true;
+    if (latency_us) *latency_us = r->t_done - r->t_submit;
+    const rt_status st = r->status;
+    const std::string why = r->error;
+    if (!r->generated) s->all.erase(it);
+    if (st != RT_OK) return set_error(st, "%s: request %llu failed: %s", what, (unsigned long long)id, why.c_str());
+    return RT_OK;
+}
+
 extern "C" rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us) {
     if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_wait: server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
@@ -709,14 +730,33 @@ extern "C" rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeo
     if (it == s->all.end())
         return set_error(RT_ERR_NOT_FOUND, "rt_server_wait: request %llu was collected by another wait",
                          (unsigned long long)ticket);
-    Request *r = it->second.get();
-    if (latency_us) *latency_us = r->t_done - r->t_submit;
-    const rt_status st = r->status;
-    const std::string why = r->error;
-    if (!r->generated) s->all.erase(it);  // nothing is left to fetch
-    if (st != RT_OK)
-        return set_error(st, "rt_server_wait: request %llu failed: %s", (unsigned long long)ticket, why.c_str());
-    return RT_OK;
+    return collect(s, it, latency_us, "rt_server_wait");
+}
+
+extern "C" rt_status rt_server_wait_any(rt_server *s, int64_t timeout_us, uint64_t *ticket, double *latency_us) {
+    if (s == nullptr || ticket == nullptr)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_wait_any: NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    // drops finished tickets that a wait by ticket has already collected
+    auto ready = [&] {
+        while (!s->finished.empty()) {
+            auto f = s->all.find(s->finished.front());
+            if (f != s->all.end() && !f->second->collected) return true;
+            s->finished.pop_front();
+        }
+        return false;
+    };
+    if (!ready()) {
+        if (s->uncollected == 0) return set_error(RT_ERR_NOT_FOUND, "rt_server_wait_any: no request outstanding");
+        if (timeout_us < 0) {
+            s->cv_done.wait(lk, ready);
+        } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+            return set_error(RT_ERR_TIMEOUT, "rt_server_wait_any: nothing finished");
+        }
+    }
+    *ticket = s->finished.front();
+    s->finished.pop_front();
+    return collect(s, s->all.find(*ticket), latency_us, "rt_server_wait_any");
 }
 
 static rt_status drop_generated(rt_server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it) {

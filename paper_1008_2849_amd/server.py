@@ -54,6 +54,13 @@ class Server:
         check(lib().rt_server_wait(self.handle, int(ticket), int(timeout_us), ctypes.byref(lat)), "rt_server_wait")
         return lat.value
 
+    def wait_any(self, timeout_us: int = -1):
+        """(ticket, latency us) of the next request to finish, in completion order."""
+        t, lat = ctypes.c_uint64(), ctypes.c_double()
+        check(lib().rt_server_wait_any(self.handle, int(timeout_us), ctypes.byref(t), ctypes.byref(lat)),
+              "rt_server_wait_any")
+        return t.value, lat.value
+
     def fetch(self, ticket: int, out_keys, out_vals=None) -> None:
         check(lib().rt_server_fetch(self.handle, int(ticket), _ptr(out_keys), _ptr(out_vals)), "rt_server_fetch")
 

@@ -100,3 +100,27 @@ def test_keys_only_server():
         for t, keys, kd in cases:
             srv.wait(t)
             assert np.array_equal(to_host(kd), np.sort(keys))
+
+
+def test_wait_any_reports_each_request_once_in_completion_order():
+    import torch
+    announce("server wait_any")
+    sizes = [100, 300_000, 5000, 20_000, 3, 70_000, 16385, 2]
+    with Server(hbm_budget_bytes=64 << 20, max_active=32) as srv:
+        tickets = {}
+        for rid, n in enumerate(sizes):
+            t, p = _generated_case(srv, 100 + rid, n, rid % 3)
+            tickets[t] = (p, n)
+        seen = []
+        while len(seen) < len(sizes):
+            t, lat = srv.wait_any()
+            assert t in tickets and t not in seen and lat >= 0
+            seen.append(t)
+            p, n = tickets[t]
+            k = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+            srv.fetch(t, k, None)
+            sync()
+            assert np.array_equal(to_host(k)[:n], np.sort(inputs.counter_keys(p, n)))
+        with pytest.raises(RtError) as e:
+            srv.wait_any(timeout_us=0)
+        assert e.value.status == RT_ERR_NOT_FOUND

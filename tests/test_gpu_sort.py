@@ -267,3 +267,43 @@ def test_copy_probe():
     rts.copy(a[1:], c[1:n])  # not 16-byte aligned
     sync()
     assert torch.equal(c[1:n], a[1:])
+
+
+def test_graph_capture_single_sort_replays():
+    """rt_sort_ex with a caller workspace only enqueues kernels: captured
+    once into a graph, each replay sorts its fresh input like the eager call
+    (fills are kernels, never memsets, so replays after the first are sound)."""
+    import torch
+    n = 3 * TILE + 1234
+    announce(f"graph capture single sort n={n}")
+    k_h = inputs.uniform_keys(n, 81)
+    v_h = inputs.index_values(n)
+    want = oracle.lsd_sort(k_h, v_h)
+    k0, v0 = to_dev(k_h), to_dev(v_h)
+    k, v = k0.clone(), v0.clone()
+    cfg = Config((8, 8, 8, 8), 1024, 16, 0)
+    ws = torch.empty(rts.workspace_bytes(n, True, cfg), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rts.sort_ex(k, v, cfg, ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    sync()
+    assert_same((to_host(k), to_host(v)), want, "eager")
+    g = torch.cuda.CUDAGraph()
+    k.copy_(k0)
+    v.copy_(v0)
+    sync()
+    with torch.cuda.graph(g, stream=s):
+        rts.sort_ex(k, v, cfg, ws, stream=s)
+    for rep in range(3):
+        k.copy_(k0)
+        v.copy_(v0)
+        sync()
+        g.replay()
+        sync()
+        assert_same((to_host(k), to_host(v)), want, f"replay {rep}")
+        k2, v2 = k0.clone(), v0.clone()
+        rts.sort_pairs(k2, v2)
+        sync()
+        assert_same((to_host(k2), to_host(v2)), want, f"eager after replay {rep}")

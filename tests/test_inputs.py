@@ -1,4 +1,6 @@
 """The seeded input generators draw what their workload descriptions say."""
+import os
+
 import numpy as np
 import pytest
 
@@ -89,3 +91,15 @@ def test_counter_keys_distributions():
     assert abs(top - 0.3653) < 0.01
     t = inputs.zipf16_thresholds()
     assert t[-1] == 2**32 and np.all(np.diff(t.astype(np.int64)) > 0)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
