@@ -182,6 +182,7 @@ def bench_serving_closed(rts, inputs, inflight, seconds, warm_s, single_gkeys, b
     distributions, generated on the device) are kept outstanding; each
     completion is replaced by the next request.  Measures the server's
     capacity and the latency at that throughput."""
+    import dataclasses
     import numpy as np
     from paper_1008_2849_amd.api import gen_params_to_c
     from paper_1008_2849_amd.server import Server
@@ -207,10 +208,26 @@ def bench_serving_closed(rts, inputs, inflight, seconds, warm_s, single_gkeys, b
     t0 = time.perf_counter()
     lats, items = [], 0
     t_meas = None
+    checked, wrong = 0, 0
     while True:
         t, ms = srv.wait_any()
         i, _ = submit_time.pop(t)
-        srv.release(t)
+        if i % 997 == 0 and sizes[i] <= (1 << 16):  # sampled parity of served results
+            import torch
+            n_i = int(sizes[i])
+            kk = torch.empty(n_i, dtype=torch.int32, device="cuda")
+            vv = torch.empty(n_i, dtype=torch.int32, device="cuda")
+            srv.fetch(t, kk, vv)
+            p_i = inputs.counter_params(int(dists[i]), seed, 0)
+            p_i = dataclasses.replace(p_i, state=int(states[i]))
+            keys_i = inputs.counter_keys(p_i, n_i)
+            order = np.argsort(keys_i, kind="stable")
+            ok_i = (np.array_equal(kk.cpu().numpy().view(np.uint32), keys_i[order]) and
+                    np.array_equal(vv.cpu().numpy().view(np.uint32), order.astype(np.uint32)))
+            checked += 1
+            wrong += 0 if ok_i else 1
+        else:
+            srv.release(t)
         now = time.perf_counter() - t0
         if now >= warm_s:
             if t_meas is None:
@@ -232,7 +249,8 @@ def bench_serving_closed(rts, inputs, inflight, seconds, warm_s, single_gkeys, b
     return {"mode": "closed_loop", "inflight": inflight, "achieved_Gkeys/s": round(gk, 3),
             "frac_of_single_array": round(gk / single_gkeys, 4),
             "p50_ms": round(float(np.percentile(lats, 50)), 3), "p99_ms": round(float(np.percentile(lats, 99)), 3),
-            "requests_measured": len(lats), "seconds": seconds}
+            "requests_measured": len(lats), "seconds": seconds,
+            "sampled_parity": {"checked": checked, "wrong": wrong}, "failures": ["parity"] if wrong else []}
 
 
 def bench_serving(rts, inputs, load, seconds, warm_s, single_gkeys, budget_gib=32):

@@ -307,3 +307,28 @@ def test_graph_capture_single_sort_replays():
         rts.sort_pairs(k2, v2)
         sync()
         assert_same((to_host(k2), to_host(v2)), want, f"eager after replay {rep}")
+
+
+@pytest.mark.parametrize("name", ["pairs_64m_and2", "pairs_64m_and4", "pairs_64m_and8", "pairs_64m_top_a5",
+                                  "pairs_64m_zipf16"])
+def test_skewed_workloads_full_size(name):
+    """The skewed workloads at their full 2^26-pair size, with the tuned
+    configuration the benchmark uses, bit-exact against the oracle."""
+    w = inputs.WORKLOADS[name]
+    announce(f"full-size workload {name} n={w.n}")
+    k, v = inputs.make_workload(w)
+    assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), name)
+
+
+def test_keys_1m_workload_tuned():
+    """The 2^20 keys-only workload with the autotuned table loaded."""
+    import os
+    from paper_1008_2849_amd import _lib
+    w = inputs.WORKLOADS["keys_1m_uniform"]
+    announce(f"keys workload n={w.n} tuned")
+    rts.load_tuning(_lib.TUNING_PATH if os.path.exists(_lib.TUNING_PATH) else None)
+    try:
+        k, _ = inputs.make_workload(w)
+        assert_same(gpu_sort(k), oracle.lsd_sort(k), "keys_1m")
+    finally:
+        rts.load_tuning(None)
