@@ -11,6 +11,12 @@ Two independent definitions live here:
   single-threaded LSD radix sort written from Sections 3 and 4 of Wassenberg
   & Sanders (naive counting sort per digit, digits least significant first,
   stable scatter in input order).
+* ``reverse_sort``: Section 4's "reverse sorting" (Algorithm 2 on one
+  processing element): an MSD partition into growable buckets, then each
+  bucket sorted locally by LSD on the three lower digits, the last pass
+  writing straight to the output.  Its buckets are filled by appending, not
+  by counting, so it shares no step with ``lsd_sort`` beyond digit
+  extraction.
 * ``brute_stable_sort``: the rank definition of the stable ascending sort
   in pure Python, O(n^2), for tiny inputs.
 
@@ -63,8 +69,9 @@ def _bind(so: ctypes.CDLL) -> ctypes.CDLL:
     so.oracle_lsd_sort.argtypes = [u32p, u32p, ctypes.c_uint64, uintp, ctypes.c_uint]
     so.oracle_lsd_sort_segmented.argtypes = [u32p, u32p, u32p, ctypes.c_uint32,
                                              uintp, ctypes.c_uint]
+    so.oracle_reverse_sort.argtypes = [u32p, u32p, ctypes.c_uint64]
     for f in (so.oracle_digit_histogram, so.oracle_counting_pass,
-              so.oracle_lsd_sort, so.oracle_lsd_sort_segmented):
+              so.oracle_lsd_sort, so.oracle_lsd_sort_segmented, so.oracle_reverse_sort):
         f.restype = ctypes.c_int
     return so
 
@@ -158,6 +165,19 @@ def lsd_sort_segmented(keys, vals, offsets, widths: Sequence[int] = DEFAULT_WIDT
     w, np_ = _widths_arg(widths)
     rc = so.oracle_lsd_sort_segmented(_ptr(k), _ptr(v), _ptr(off), off.size - 1, w, np_)
     _check(rc, "lsd_sort_segmented")
+    return k, v
+
+
+def reverse_sort(keys, vals=None, so: Optional[ctypes.CDLL] = None):
+    """MSD partition then per-bucket LSD (32-bit keys, 8-bit digits);
+    returns (sorted_keys, moved_values or None)."""
+    so = so or lib()
+    k = _u32(keys).copy()
+    v = None if vals is None else _u32(vals).copy()
+    if v is not None and v.size != k.size:
+        raise ValueError("keys and values differ in length")
+    rc = so.oracle_reverse_sort(_ptr(k), _ptr(v), k.size)
+    _check(rc, "reverse_sort")
     return k, v
 
 

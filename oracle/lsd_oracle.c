@@ -251,3 +251,175 @@ int oracle_lsd_sort_segmented(uint32_t *keys, uint32_t *vals,
     }
     return ORACLE_OK;
 }
+
+/*
+ * "Reverse sorting" (Section 4, Algorithm 2) on one processing element,
+ * with K = 32-bit keys and D = 8-bit digits numbered 0 (least significant)
+ * to 3.  The buckets are growable arrays that items are appended to in the
+ * order they are visited, as the paper's virtual-memory buckets are
+ * (Section 3): no histogram is needed to fill them.  The steps, in the
+ * algorithm's order:
+ *
+ *   1. each item is appended to buckets3[digit 3];
+ *   2. bucketSizes = the sizes of buckets3, and outputIndices = its
+ *      exclusive prefix sum: where each MSD bucket starts in the output;
+ *   3. for every bucket3, in increasing MSD order:
+ *        a. its items are appended to buckets0[digit 0];
+ *        b. the items of buckets0, bucket by bucket in increasing digit
+ *           order, are appended to buckets1[digit 1], and histogram2 counts
+ *           their digit 2;
+ *        c. the items of buckets1, bucket by bucket in increasing digit
+ *           order, are written straight to the output: an item with digit 2
+ *           equal to d goes to the bucket's start plus the number of the
+ *           bucket's items with a smaller digit 2 plus the number of items
+ *           with digit d already written.
+ *
+ * Reading of step 3c: the printed index adds outputIndices and histogram2
+ * at the same digit d; that only makes sense with outputIndices taken at the
+ * bucket's MSD and histogram2 turned into its exclusive prefix sum (counts
+ * of smaller digits 2), which is what is written here.
+ */
+typedef struct {
+    uint32_t *k, *v;
+    uint64_t len, cap;
+} obucket;
+
+static int obucket_append(obucket *b, uint32_t k, uint32_t v, int with_v)
+{
+    if (b->len == b->cap) {
+        uint64_t cap = b->cap ? 2 * b->cap : 16;
+        uint32_t *nk = (uint32_t *)realloc(b->k, cap * sizeof(uint32_t));
+        if (nk == NULL)
+            return ORACLE_ENOMEM;
+        b->k = nk;
+        if (with_v) {
+            uint32_t *nv = (uint32_t *)realloc(b->v, cap * sizeof(uint32_t));
+            if (nv == NULL)
+                return ORACLE_ENOMEM;
+            b->v = nv;
+        }
+        b->cap = cap;
+    }
+    b->k[b->len] = k;
+    if (with_v)
+        b->v[b->len] = v;
+    b->len += 1;
+    return ORACLE_OK;
+}
+
+static void obuckets_free(obucket *b, unsigned count)
+{
+    unsigned i;
+    for (i = 0; i < count; ++i) {
+        free(b[i].k);
+        free(b[i].v);
+        b[i].k = b[i].v = NULL;
+        b[i].len = b[i].cap = 0;
+    }
+}
+
+#define OR_RADIX 256u
+
+int oracle_reverse_sort(uint32_t *keys, uint32_t *vals, uint64_t n)
+{
+    obucket *buckets3, *buckets0, *buckets1;
+    uint64_t bucket_sizes[OR_RADIX], output_indices[OR_RADIX];
+    uint64_t histogram2[OR_RADIX], slot2[OR_RADIX];
+    uint32_t *out_k = NULL, *out_v = NULL;
+    uint64_t i, running;
+    unsigned b3, b, d;
+    const int with_v = vals != NULL;
+    int rc = ORACLE_OK;
+    if (n > 0 && keys == NULL)
+        return ORACLE_EINVAL;
+    if (n < 2)
+        return ORACLE_OK;
+    buckets3 = (obucket *)calloc(3 * OR_RADIX, sizeof(obucket));
+    out_k = (uint32_t *)malloc(n * sizeof(uint32_t));
+    out_v = with_v ? (uint32_t *)malloc(n * sizeof(uint32_t)) : NULL;
+    if (buckets3 == NULL || out_k == NULL || (with_v && out_v == NULL)) {
+        free(buckets3);
+        free(out_k);
+        free(out_v);
+        return ORACLE_ENOMEM;
+    }
+    buckets0 = buckets3 + OR_RADIX;
+    buckets1 = buckets0 + OR_RADIX;
+
+    /* 1: partition by the most significant digit */
+    for (i = 0; i < n && rc == ORACLE_OK; ++i) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 9
+        /* planted mistake: the partition takes digit 2 for the MSD */
+        const uint32_t d3 = digit_of(keys[i], 16, 8);
+#else
+        const uint32_t d3 = digit_of(keys[i], 24, 8);
+#endif
+        rc = obucket_append(&buckets3[d3], keys[i], with_v ? vals[i] : 0u, with_v);
+    }
+
+    /* 2: bucket sizes and where each MSD bucket starts in the output */
+    running = 0;
+    for (d = 0; d < OR_RADIX; ++d) {
+        bucket_sizes[d] = buckets3[d].len;
+        output_indices[d] = running;
+        running += bucket_sizes[d];
+    }
+
+    /* 3: local LSD passes over digits 0, 1, 2 of each MSD bucket */
+    for (b3 = 0; b3 < OR_RADIX && rc == ORACLE_OK; ++b3) {
+        const obucket *src = &buckets3[b3];
+        /* 3a */
+        for (i = 0; i < src->len && rc == ORACLE_OK; ++i)
+            rc = obucket_append(&buckets0[digit_of(src->k[i], 0, 8)], src->k[i],
+                                with_v ? src->v[i] : 0u, with_v);
+        /* 3b */
+        for (d = 0; d < OR_RADIX; ++d)
+            histogram2[d] = 0;
+        for (b = 0; b < OR_RADIX && rc == ORACLE_OK; ++b) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 10
+            /* planted mistake: buckets0 visited in decreasing digit order */
+            const obucket *b0 = &buckets0[OR_RADIX - 1 - b];
+#else
+            const obucket *b0 = &buckets0[b];
+#endif
+            for (i = 0; i < b0->len && rc == ORACLE_OK; ++i) {
+                rc = obucket_append(&buckets1[digit_of(b0->k[i], 8, 8)], b0->k[i],
+                                    with_v ? b0->v[i] : 0u, with_v);
+                histogram2[digit_of(b0->k[i], 16, 8)] += 1;
+            }
+        }
+        /* 3c */
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 8
+        /* planted mistake: every bucket is written from output slot 0 */
+        running = 0 * output_indices[b3];
+#else
+        running = output_indices[b3];
+#endif
+        for (d = 0; d < OR_RADIX; ++d) {
+            slot2[d] = running;
+            running += histogram2[d];
+        }
+        for (b = 0; b < OR_RADIX && rc == ORACLE_OK; ++b) {
+            const obucket *b1 = &buckets1[b];
+            for (i = 0; i < b1->len; ++i) {
+                uint32_t dd = digit_of(b1->k[i], 16, 8);
+                out_k[slot2[dd]] = b1->k[i];
+                if (with_v)
+                    out_v[slot2[dd]] = b1->v[i];
+                slot2[dd] += 1;
+            }
+        }
+        obuckets_free(buckets0, OR_RADIX);
+        obuckets_free(buckets1, OR_RADIX);
+    }
+    if (rc == ORACLE_OK) {
+        memcpy(keys, out_k, n * sizeof(uint32_t));
+        if (with_v)
+            memcpy(vals, out_v, n * sizeof(uint32_t));
+    }
+    obuckets_free(buckets3, 3 * OR_RADIX);
+    free(buckets3);
+    free(out_k);
+    free(out_v);
+    return rc;
+}

@@ -192,9 +192,45 @@ def pin_invariants(so, n=1 << 15):
         assert np.array_equal(ks2, ks) and np.array_equal(vs2, np.arange(n, dtype=np.uint32))
 
 
+def pin_reverse_sort(so):
+    """Algorithm 2's MSD-first sort against brute force, numpy and closed forms."""
+    for c in _all_tuples(4):
+        ks, vs = oracle.reverse_sort(np.array(c, dtype=np.uint32),
+                                     np.arange(len(c), dtype=np.uint32), so=so)
+        bk, bv = oracle.brute_stable_sort(c, list(range(len(c))))
+        assert list(ks) == bk and list(vs) == bv, c
+    rng = np.random.default_rng(321)
+    alpha = np.array([0x01000000, 0x00000001, 0x01000001, 0xFF00FF00, 0x00010000], dtype=np.uint32)
+    for _ in range(200):
+        n = int(rng.integers(0, 65))
+        k = alpha[rng.integers(0, alpha.size, size=n)]
+        v = np.arange(n, dtype=np.uint32)
+        ks, vs = oracle.reverse_sort(k, v, so=so)
+        bk, bv = oracle.brute_stable_sort(list(k), list(v))
+        assert list(ks) == bk and list(vs) == bv
+    n = 1 << 14
+    for name, k in {"uniform": inputs.uniform_keys(n, 70), "and2": inputs.and_keys(n, 2, 71),
+                    "top_00": inputs.top_byte_keys(n, 0x00, 72), "top_a5": inputs.top_byte_keys(n, 0xA5, 73),
+                    "zipf16": inputs.zipf16_keys(n, 74)}.items():
+        v = inputs.index_values(n)
+        ks, vs = oracle.reverse_sort(k, v, so=so)
+        rk, rv = _stable_reference(k, v)
+        assert np.array_equal(ks, rk) and np.array_equal(vs, rv), name
+        ko, none = oracle.reverse_sort(k, None, so=so)
+        assert none is None and np.array_equal(ko, rk), name
+    m = 12
+    idx = np.arange(1 << m, dtype=np.uint32)
+    br = np.zeros(idx.size, dtype=np.uint32)
+    for b in range(m):
+        br |= ((idx >> b) & 1) << (m - 1 - b)
+    for shift in (0, 20):  # low bits only; spread across the MSD buckets
+        ks, vs = oracle.reverse_sort(br << np.uint32(shift), idx, so=so)
+        assert np.array_equal(ks, idx << np.uint32(shift)) and np.array_equal(vs, br)
+
+
 PINS = [pin_worked_example, pin_unsigned_order, pin_closed_forms, pin_heavy_ties,
         pin_histograms, pin_numpy_stable, pin_width_invariance, pin_invariants,
-        pin_exhaustive_tiny]
+        pin_exhaustive_tiny, pin_reverse_sort]
 
 
 # --------------------------------------------------------------- tests ----
@@ -252,6 +288,9 @@ MUTANTS = {
     5: "digit mask drops its top bit",
     6: "keys treated as signed",
     7: "digits taken most significant first",
+    8: "MSD-first sort: every bucket written from output slot 0",
+    9: "MSD-first sort: partition on digit 2",
+    10: "MSD-first sort: first local pass's buckets visited in decreasing order",
 }
 
 
