@@ -8,6 +8,9 @@ pre-staged copy of the input, so no restore copy sits inside the timed
 region.  The run prints one JSON line on stdout: whole-sort throughput
 (Gkeys/s), per-pass HBM bandwidth against the chip's peak for the dominant
 kernel (the counting-sort pass), and the CPU oracle timed on this host.
+Further legs, each reported in the same line and each skippable: the
+transfer-inclusive rate, the MSD-first sort of the same input, the batched
+workload and the serving loop.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -132,6 +135,47 @@ def bench_batched(rts, inputs, dev, K, W, single_gkeys):
             "call_p99_ms": round(float(np.percentile(per_call, 99)), 4),
             "tiled_pass_ms": round(float(np.mean(pass_ms)), 4) if pass_ms else None,
             "frac_of_single_array": round(gk / single_gkeys, 4), "parity_properties_ok": ok}
+
+
+def bench_msd_first(rts, dev, k0, v0, slots, K, W, single_gkeys, ref_k, ref_v):
+    """The MSD-first sort (one partition pass on the top digit, then LSD
+    passes over the three lower digits of each of the 256 buckets) on the
+    same workload, each call on its own re-staged copy; its last output must
+    equal the LSD sort's bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1008_2849_amd._lib import RT_KIND_HISTOGRAM, RT_KIND_MSD_PASS, RT_KIND_PASS
+    n = k0.numel()
+    ws = torch.empty(rts.msd_first_workspace_bytes(n, v0 is not None), dtype=torch.uint8, device=dev)
+    for k, v in slots:
+        k.copy_(k0)
+        if v is not None:
+            v.copy_(v0)
+    for i in range(W):
+        rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws)
+    torch.cuda.synchronize()
+    rts.profile_start(max_marks=32 * K + 32)
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    calls = split_calls(rts.profile_stop(capacity=32 * K + 32))
+    part = [ms for c in calls for kind, ms in c[1] if kind == RT_KIND_MSD_PASS]
+    local = [ms for c in calls for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+    hists = [[ms for kind, ms in c[1] if kind == RT_KIND_HISTOGRAM] for c in calls]
+    ko, vo = slots[W + K - 1]
+    same = bool(torch.equal(ko, ref_k)) and (vo is None or bool(torch.equal(vo, ref_v)))
+    gk = n / (wall / K) / 1e9
+    del ws
+    return {"Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
+            "frac_of_single_array": round(gk / single_gkeys, 4),
+            "partition_pass_ms": round(float(np.mean(part)), 4) if part else None,
+            "local_pass_ms": round(float(np.mean(local)), 4) if local else None,
+            "msd_histogram_ms": round(float(np.mean([h[0] for h in hists if h])), 4) if hists else None,
+            "bucket_histogram_ms": round(float(np.mean([h[1] for h in hists if len(h) > 1])), 4)
+            if hists else None,
+            "matches_lsd_sort": same}
 
 
 def bench_pcie(rts, dev, keys_h, vals_h, cfg, ref_k, ref_v, reps=3):
@@ -362,6 +406,7 @@ def main() -> int:
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-msd-first", action="store_true", help="skip the MSD-first leg")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
     ap.add_argument("--serve-loads", default="0.5", help="comma list of offered loads (fraction of "
                     "single-array throughput); empty to skip serving")
@@ -505,6 +550,15 @@ def main() -> int:
         pcie = bench_pcie(rts, dev, keys_h, vals_h, cfg, slots[W + K - 1][0], slots[W + K - 1][1])
         log(f"pcie: {pcie}")
 
+    msd_first = None
+    if not args.no_msd_first:
+        log("MSD-first leg")
+        ko, vo = slots[W + K - 1]
+        ref = (ko.clone(), None if vo is None else vo.clone())
+        msd_first = bench_msd_first(rts, dev, k0, v0, slots, K, W, gkeys, ref[0], ref[1])
+        del ref
+        log(f"msd_first: {msd_first}")
+
     batched = None
     if not args.no_batched and args.workload == "pairs_256m_uniform":
         log("batched workload")
@@ -552,6 +606,7 @@ def main() -> int:
         "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
         "parity_properties_ok": props,
         "transfer_inclusive": pcie,
+        "msd_first": msd_first,
         "batched": batched,
         "serving": serving,
         "kernel_source_digest": digest,
@@ -561,6 +616,7 @@ def main() -> int:
     ok = ok and (batched is None or batched["parity_properties_ok"])
     ok = ok and all(not s.get("failures") for s in serving)
     ok = ok and (pcie is None or pcie["matches_device_sort"])
+    ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
     return 0 if ok else 3
 
 

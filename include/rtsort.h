@@ -56,7 +56,7 @@ typedef enum rt_status {
 /* rt_config.flags */
 #define RT_FLAG_NO_SKIP 0x1u   /* run every pass, even when its digit is constant */
 #define RT_FLAG_NT_STORES 0x2u /* scatter with non-temporal stores */
-#define RT_FLAG_VALIDATE 0x4u  /* batched: wait for the sort and report malformed offsets */
+#define RT_FLAG_VALIDATE 0x4u  /* batched, MSD-first: wait for the sort and report device errors */
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".
@@ -148,6 +148,39 @@ size_t rt_batched_workspace_bytes(uint32_t num_segments, size_t max_total, int w
 rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
                              uint32_t num_segments, size_t max_total, uint32_t flags, void *workspace,
                              size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * MSD-first sort ("reverse sorting")
+ * --------------------------------------------------------------------- */
+
+/*
+ * Workspace bytes of rt_sort_msd_first for n items (with_values 0 or 1);
+ * 0 when n < 2 or n >= 2^32.
+ */
+size_t rt_msd_first_workspace_bytes(size_t n, int with_values);
+
+/*
+ * Sorts n keys (and values) in place like rt_sort_ex, by Section 4's
+ * "reverse sorting" as Algorithm 2 arranges it on one processing element:
+ * one counting-sort pass on the most significant 8-bit digit moves the
+ * items into a temporary array of the workspace, partitioned into 256 MSD
+ * buckets whose starts are the exclusive prefix sum of the MSD histogram;
+ * then each bucket is sorted on its own by LSD passes over digits 0, 1
+ * and 2, the last of which writes the caller's arrays.  The result equals
+ * rt_sort_ex's bit for bit (a stable sort has one result); passes are never
+ * skipped, so keys whose top byte is constant still pay the partition pass.
+ * Buckets of at most 16384 items are sorted whole in LDS.
+ *
+ * keys, vals: device u32[n], not overlapping; vals may be NULL (keys only).
+ * flags: 0 or RT_FLAG_VALIDATE (wait, and report a device error word as
+ * RT_ERR_HIP).  workspace: device memory of at least
+ * rt_msd_first_workspace_bytes(n, vals != NULL) bytes, 256-byte aligned,
+ * or NULL for the library's per-stream cache; with a caller workspace and
+ * no RT_FLAG_VALIDATE the call only enqueues kernels.  Argument errors are
+ * returned before any device work; n = 0 and n = 1 do nothing.
+ */
+rt_status rt_sort_msd_first(uint32_t *keys, uint32_t *vals, size_t n, uint32_t flags, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Pieces of the path, exported for parity tests and measurement
@@ -309,6 +342,7 @@ rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
 #define RT_KIND_GENERATE 6u
 #define RT_KIND_SEGMENTED 7u /* segmented sort: tile lists of the tiled segments */
 #define RT_KIND_SEG_SMALL 8u /* segmented sort: segments sorted whole in LDS */
+#define RT_KIND_MSD_PASS 9u  /* MSD-first sort: the partition pass on the top digit */
 #define RT_KIND_PASS 16u     /* + pass index: one counting-sort pass (onesweep) */
 rt_status rt_profile_start(uint32_t max_marks);
 rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count);

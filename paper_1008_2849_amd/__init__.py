@@ -11,7 +11,7 @@ from __future__ import annotations
 
 __all__ = [
     "Config", "sort_keys", "sort_pairs", "sort_ex", "sort_pairs_batched", "sort_batched_ex",
-    "batched_workspace_bytes", "workspace_bytes",
+    "batched_workspace_bytes", "workspace_bytes", "sort_msd_first", "msd_first_workspace_bytes",
     "digit_histograms", "counting_pass", "copy", "generate", "load_tuning", "tuned_config",
     "version", "Server", "RtError", "profile_start", "profile_stop",
 ]

@@ -36,6 +36,7 @@ RT_KIND_COPY = 5
 RT_KIND_GENERATE = 6
 RT_KIND_SEGMENTED = 7
 RT_KIND_SEG_SMALL = 8
+RT_KIND_MSD_PASS = 9
 RT_KIND_PASS = 16
 
 
@@ -83,6 +84,8 @@ SIGNATURES = {
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
     "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
     "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),
+    "rt_msd_first_workspace_bytes": (sz, [sz, ctypes.c_int]),
+    "rt_sort_msd_first": (ctypes.c_int, [vp, vp, sz, u32, vp, sz, vp]),
     "rt_digit_histograms": (ctypes.c_int, [vp, sz, ctypes.POINTER(RtConfig), vp, vp]),
     "rt_counting_pass": (ctypes.c_int, [vp, vp, vp, vp, sz, u32, u32, vp]),
     "rt_copy": (ctypes.c_int, [vp, vp, sz, vp]),

@@ -160,6 +160,26 @@ def sort_batched_ex(keys, vals, offsets, max_total: Optional[int] = None, valida
           "rt_sort_batched_ex")
 
 
+def msd_first_workspace_bytes(n: int, with_values: bool = True) -> int:
+    return int(lib().rt_msd_first_workspace_bytes(n, 1 if with_values else 0))
+
+
+def sort_msd_first(keys, vals=None, validate: bool = False, workspace=None, stream=None) -> None:
+    """In-place stable sort by one MSD partition pass, then LSD passes over
+    the three lower digits of each MSD bucket (the paper's reverse sorting)."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    if vals is not None and vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr = workspace.data_ptr()
+        ws_bytes = workspace.numel() * workspace.element_size()
+    check(lib().rt_sort_msd_first(_ptr(keys), _ptr(vals), keys.numel(),
+                                  _lib.RT_FLAG_VALIDATE if validate else 0, ws_ptr, ws_bytes, _stream(stream)),
+          "rt_sort_msd_first")
+
+
 def digit_histograms(keys, cfg: Optional[Config] = None, stream=None):
     """Per-pass digit counts, shape [passes, 2^MAX_DIGIT_BITS] (uint32 as int32)."""
     torch = _torch()

@@ -13,7 +13,7 @@ namespace rt {
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values) {
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps) {
     SegLayout L{};
     L.num_segments = num_segments;
     L.capacity = capacity;
@@ -32,9 +32,12 @@ SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_valu
     L.base = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
     L.status_pass = static_cast<size_t>(L.max_tiles) * kSegRadix * sw;
     L.status = off;     off += align256(L.status_pass * kSegPasses);
-    L.tk = off;         off += align256(sizeof(uint32_t) * capacity);
-    L.tv = 0;
-    if (with_values) { L.tv = off; off += align256(sizeof(uint32_t) * capacity); }
+    L.tk = L.tv = 0;
+    if (own_temps) {
+        L.tk = off;
+        off += align256(sizeof(uint32_t) * capacity);
+        if (with_values) { L.tv = off; off += align256(sizeof(uint32_t) * capacity); }
+    }
     L.total = off;
     return L;
 }
@@ -44,12 +47,13 @@ static uint32_t cap_grid(size_t want, uint32_t cap) {
     return static_cast<uint32_t>(want < cap ? want : cap);
 }
 
-// Per-segment histograms and prefix sums, whole-in-LDS segments, and the
-// passes over the tiled segments.  The lists and the tiled list's counter
-// are already on the device.
+// Per-segment histograms and prefix sums, whole-in-LDS segments, and passes
+// 0..passes-1 over the tiled segments.  The lists and the tiled list's
+// counter are already on the device.  to_temp: the result is wanted in the
+// temporaries (odd pass counts), where the tiled passes leave it.
 template <bool VALS, typename S>
-static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint32_t list_stride,
-                                 hipStream_t stream) {
+static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint32_t list_stride, int passes,
+                                 int to_temp, hipStream_t stream) {
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
     uint32_t *large_list = P.lists + static_cast<size_t>(kSegLarge) * list_stride;
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
@@ -65,13 +69,13 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     prof_mark(stream, RT_KIND_PLAN);
     // whole-in-LDS classes
     hipLaunchKernelGGL((k_seg_small<256, 8, VALS>), dim3(cap_grid(list_stride, cus * 8)), dim3(256), 0, stream,
-                       P.descs, P.lists, P.header, 0);
+                       P.descs, P.lists, P.header, 0, passes, to_temp);
     hipLaunchKernelGGL((k_seg_small<512, 16, VALS>), dim3(cap_grid(list_stride, cus * 2)), dim3(512), 0, stream,
-                       P.descs, P.lists + list_stride, P.header, 1);
+                       P.descs, P.lists + list_stride, P.header, 1, passes, to_temp);
     hipLaunchKernelGGL((k_seg_small<1024, 16, VALS>), dim3(cap_grid(list_stride, cus)), dim3(1024), 0, stream,
-                       P.descs, P.lists + 2 * static_cast<size_t>(list_stride), P.header, 2);
+                       P.descs, P.lists + 2 * static_cast<size_t>(list_stride), P.header, 2, passes, to_temp);
     prof_mark(stream, RT_KIND_SEG_SMALL);
-    for (int p = 0; p < kSegPasses; ++p) {
+    for (int p = 0; p < passes; ++p) {
         S *status = reinterpret_cast<S *>(reinterpret_cast<char *>(P.status) + p * L.status_pass);
         hipLaunchKernelGGL((k_seg_onesweep<1024, 16, VALS, S>), dim3(L.max_tiles), dim3(1024), 0, stream, P.descs,
                            large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status,
@@ -97,30 +101,37 @@ SegPointers seg_pointers(char *ws, const SegLayout &L) {
     return P;
 }
 
-void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
-                    const SegLayout &L, char *ws, hipStream_t stream) {
+void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, const uint32_t *offsets,
+                     uint32_t num_segments, const SegLayout &L, char *ws, int passes, int to_temp,
+                     hipStream_t stream) {
     const SegPointers P = seg_pointers(ws, L);
     const bool vals_on = vals != nullptr;
-    prof_begin(stream);
     hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, stream, P.header);
     const size_t hist_words = static_cast<size_t>(kSegPasses) * kSegRadix * L.large_capacity;
     if (hist_words)
         hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((hist_words + 4095) / 4096, 1024)), dim3(256), 0, stream,
                            P.hist, hist_words);
-    const size_t status_words = L.status_pass * kSegPasses / 4;
+    const size_t status_words = L.status_pass * static_cast<size_t>(passes) / 4;
     hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((status_words + 4095) / 4096, 4096)), dim3(256), 0, stream,
                        reinterpret_cast<uint32_t *>(P.status), status_words);
     prof_mark(stream, RT_KIND_FILL);
     hipLaunchKernelGGL(k_seg_classify, dim3((num_segments + 255) / 256), dim3(256), 0, stream, offsets,
-                       num_segments, keys, vals, P.tk, vals_on ? P.tv : nullptr, L.capacity, L.large_capacity,
-                       P.descs, P.lists, P.header);
+                       num_segments, keys, vals, tk, vals_on ? tv : nullptr, L.capacity, L.large_capacity,
+                       to_temp, P.descs, P.lists, P.header);
     if (L.wide_status) {
-        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, stream);
-        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, stream);
+        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, stream);
+        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, stream);
     } else {
-        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, stream);
-        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, stream);
+        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, passes, to_temp, stream);
+        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, passes, to_temp, stream);
     }
+}
+
+void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
+                    const SegLayout &L, char *ws, hipStream_t stream) {
+    const SegPointers P = seg_pointers(ws, L);
+    prof_begin(stream);
+    launch_segments(keys, vals, P.tk, vals ? P.tv : nullptr, offsets, num_segments, L, ws, kSegPasses, 0, stream);
 }
 
 }  // namespace rt
@@ -143,7 +154,7 @@ static rt_status check_batched(uint32_t *keys, uint32_t *vals, const uint32_t *s
 
 extern "C" size_t rt_batched_workspace_bytes(uint32_t num_segments, size_t max_total, int with_values) {
     if (num_segments == 0 || max_total < 2 || max_total >= (static_cast<size_t>(1) << 32)) return 0;
-    return make_seg_layout(num_segments, max_total, with_values != 0).total;
+    return make_seg_layout(num_segments, max_total, with_values != 0, true).total;
 }
 
 extern "C" rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const uint32_t *seg_offsets,
@@ -153,7 +164,7 @@ extern "C" rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const ui
     if (s != RT_OK || num_segments == 0 || max_total < 2) return s;
     if (flags & ~static_cast<uint32_t>(RT_FLAG_VALIDATE))
         return set_error(RT_ERR_INVALID_ARG, "rt_sort_batched_ex: unknown flags 0x%x", flags);
-    const SegLayout L = make_seg_layout(num_segments, max_total, vals != nullptr);
+    const SegLayout L = make_seg_layout(num_segments, max_total, vals != nullptr, true);
     void *ws = workspace;
     if (ws != nullptr) {
         if (workspace_bytes < L.total)

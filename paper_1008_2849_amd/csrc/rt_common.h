@@ -52,8 +52,14 @@ bool shape_supported(int bits_class, int block, int ipt);
 rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolved *out);
 Layout make_layout(size_t n, const Resolved &r, bool direct);
 rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);
+// The whole sort (direct == false) or one explicit pass (direct == true:
+// keys/vals read, direct_out_* written).  Pass p's timing mark has kind
+// pass_kind + p.  After the plan kernel, the workspace's base table holds
+// pass p's exclusive digit offsets at p * kMaxRadix, with every bin past the
+// digit's range equal to n.
 void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
-                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream);
+                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream,
+                 uint32_t pass_kind = RT_KIND_PASS);
 
 // Workspace of a segmented sort (byte offsets) and its device pointers.
 struct SegLayout {
@@ -80,8 +86,17 @@ struct SegPointers {
     uint32_t *tv;
 };
 
-SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values);
+// own_temps: the workspace holds the temporaries (capacity items each);
+// otherwise the caller supplies them.
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps);
 SegPointers seg_pointers(char *ws, const SegLayout &L);
+// Sorts segment s = [offsets[s], offsets[s+1]) of keys/vals on digits
+// 0..passes-1 with temporaries tk/tv at the same distance from offsets[0];
+// an even pass count leaves the result in keys/vals, an odd one (to_temp
+// set) in tk/tv.
+void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, const uint32_t *offsets,
+                     uint32_t num_segments, const SegLayout &L, char *ws, int passes, int to_temp,
+                     hipStream_t stream);
 void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
                     const SegLayout &L, char *ws, hipStream_t stream);
 

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
 // ---------------------------------------------------------------------------
 
 // One block of 256 threads; thread t covers bins [8t, 8t + 8) of a pass.
-// Also clears the tile counters of the passes.
+// Also clears the tile counters of the passes and the error word after them.
 static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__restrict__ hist,
                                               uint32_t *__restrict__ base, SortPlan *__restrict__ plan,
                                               uint32_t *__restrict__ tile_counters, uint32_t direct) {
@@ -256,6 +256,7 @@ static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t 
         s_constant[tid] = 0u;
         tile_counters[tid] = 0u;
     }
+    if (tid == kMaxPasses) tile_counters[kMaxPasses] = 0u;  // the error word
     __syncthreads();
     for (uint32_t p = 0; p < a.num_passes; ++p) {
         const uint32_t bins = 1u << a.width[p];

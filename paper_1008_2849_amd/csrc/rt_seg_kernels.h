@@ -32,10 +32,12 @@ static __global__ __launch_bounds__(64) void k_seg_reset(SegHeader *__restrict__
 // One thread per segment.  Segment s is [off[s], off[s+1]) of keys/vals; its
 // temporaries sit at the same distance from off[0] in tk/tv, which hold
 // `capacity` elements.  A segment with an end before its start, or reaching
-// past off[0] + capacity, is left untouched and raises kSegErrBounds.
+// past off[0] + capacity, is left untouched and raises kSegErrBounds.  When
+// the result is wanted in the temporaries (to_temp), a one-item segment is
+// copied there here, as no later kernel sees it.
 static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ off, uint32_t num_segments,
                                                       uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
-                                                      size_t capacity, uint32_t large_capacity,
+                                                      size_t capacity, uint32_t large_capacity, int to_temp,
                                                       SegDesc *__restrict__ descs, uint32_t *__restrict__ lists,
                                                       SegHeader *__restrict__ h) {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
@@ -47,7 +49,13 @@ static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__r
         return;
     }
     const uint32_t n = b - a;
-    if (n < 2) return;  // nothing to sort
+    if (n < 2) {  // nothing to sort
+        if (n == 1 && to_temp) {
+            tk[a - o0] = keys[a];
+            if (vals) tv[a - o0] = vals[a];
+        }
+        return;
+    }
     SegDesc d;
     d.k = keys + a;
     d.v = vals ? vals + a : nullptr;
@@ -133,15 +141,18 @@ static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__re
 // ---------------------------------------------------------------------------
 
 // Sorts segments of at most BLOCK * IPT items, one per block at a time.  The
-// segment is loaded once, padded with all-ones keys that stay behind every
-// real item (they come last in input order and the sort is stable), taken
-// through the four passes in LDS, and stored once.  Ranking inside a pass is
-// the onesweep ranking: wave-local ballot match plus per-wave digit counters,
-// then digit offsets across the block.
+// segment is loaded once from k/v, padded with all-ones keys that stay
+// behind every real item (they come last in input order and the sort is
+// stable), taken through the digits of passes 0..passes-1 in LDS, and stored
+// once: to k/v, or to tk/tv when to_temp is set (where the tiled passes
+// leave an odd pass count's result).  Ranking inside a pass is the onesweep
+// ranking: wave-local ballot match plus per-wave digit counters, then digit
+// offsets across the block.
 template <int BLOCK, int IPT, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__ descs,
                                                      const uint32_t *__restrict__ list,
-                                                     const SegHeader *__restrict__ h, int which) {
+                                                     const SegHeader *__restrict__ h, int which, int passes,
+                                                     int to_temp) {
     constexpr int RADIX = kSegRadix;
     constexpr int WAVES = BLOCK / 64;
     constexpr int TILE = BLOCK * IPT;
@@ -172,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             key[j] = i < n ? d.k[i] : ~0u;
             if constexpr (VALS) val[j] = i < n ? d.v[i] : 0u;
         }
-        for (int p = 0; p < kSegPasses; ++p) {
+        for (int p = 0; p < passes; ++p) {
             const uint32_t shift = p * kSegBits;
             for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
             // (the previous pass finished reading wh before its last barrier)
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
                 if constexpr (VALS) s_v[r] = val[j];
             }
             __syncthreads();
-            if (p + 1 < kSegPasses) {
+            if (p + 1 < passes) {
 #pragma unroll
                 for (int j = 0; j < IPT; ++j) {
                     key[j] = s_k[wslot0 + j * 64];
@@ -235,9 +246,11 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
                 // s_k is rewritten only after the next pass's first barrier
             }
         }
+        uint32_t *out_k = to_temp ? d.tk : d.k;
+        uint32_t *out_v = to_temp ? d.tv : d.v;
         for (uint32_t i = tid; i < n; i += BLOCK) {
-            d.k[i] = s_k[i];
-            if constexpr (VALS) d.v[i] = s_v[i];
+            out_k[i] = s_k[i];
+            if constexpr (VALS) out_v[i] = s_v[i];
         }
         __syncthreads();  // s_k and s_v are reused by the next segment
     }
@@ -406,8 +419,8 @@ __device__ __forceinline__ uint32_t seg_lookback_digit(const S *__restrict__ sta
 // One block per tile (claimed in order from *tile_counter, as in
 // k_onesweep).  The tile's segment runs pass `pass` (or its own d.pass when
 // pass < 0): even passes read k/v and write tk/tv, odd passes the reverse,
-// so the fourth pass leaves the result in k/v.  Status words: one per tile
-// and digit, zeroed before the launch.
+// so four passes leave the result in k/v and three in tk/tv.  Status words:
+// one per tile and digit, zeroed before the launch.
 template <int BLOCK, int IPT, bool VALS, typename S>
 __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
                                                         const uint32_t *__restrict__ list,

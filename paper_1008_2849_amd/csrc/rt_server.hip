@@ -459,13 +459,13 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
     const uint32_t n0 = P.small[0], n1 = P.small[1], n2 = P.small[2];
     const uint32_t *l1 = d_lists + stride, *l2 = d_lists + 2 * static_cast<size_t>(stride);
     if (P.vals) {
-        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
-        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1);
-        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2);
+        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0, kSegPasses, 0);
+        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1, kSegPasses, 0);
+        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2, kSegPasses, 0);
     } else {
-        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0);
-        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1);
-        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2);
+        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0, kSegPasses, 0);
+        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1, kSegPasses, 0);
+        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2, kSegPasses, 0);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: launch: %s", hipGetErrorString(e));

@@ -255,7 +255,8 @@ void prof_mark(hipStream_t stream, uint32_t kind) { prof_record(stream, kind); }
 
 template <int BITS, int BLOCK, int IPT>
 static void launch_pass_shape(const Layout &L, bool vals, bool nt, hipStream_t stream, const SortPlan *plan,
-                              int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr) {
+                              int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr,
+                              uint32_t kind) {
     const dim3 grid(L.tiles), block(BLOCK);
     uint32_t *err = ctr + kMaxPasses;
 #define RT_OS(V, NTV, S)                                                                                     \
@@ -269,15 +270,15 @@ static void launch_pass_shape(const Layout &L, bool vals, bool nt, hipStream_t s
         else      { if (nt) RT_OS(false, true, uint32_t); else RT_OS(false, false, uint32_t); }
     }
 #undef RT_OS
-    prof_mark(stream, RT_KIND_PASS + pass);
+    prof_mark(stream, kind);
 }
 
 static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, bool nt, hipStream_t stream,
                         const SortPlan *plan, int pass, uint32_t n, const uint32_t *base, void *status,
-                        uint32_t *ctr) {
+                        uint32_t *ctr, uint32_t kind) {
 #define RT_SHAPE_LAUNCH(B, BLK, I)                                                                  \
     if (bits_class == B && block == BLK && ipt == I) {                                              \
-        launch_pass_shape<B, BLK, I>(L, vals, nt, stream, plan, pass, n, base, status, ctr);       \
+        launch_pass_shape<B, BLK, I>(L, vals, nt, stream, plan, pass, n, base, status, ctr, kind); \
         return;                                                                                     \
     }
     RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
@@ -344,7 +345,8 @@ void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint
 // The whole sort (direct == false) or one explicit pass (direct == true,
 // user_* read and direct_out_* written).
 void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, const Layout &L, char *ws,
-                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream) {
+                 bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream,
+                 uint32_t pass_kind) {
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(ws + L.ctr);
     uint32_t *base = reinterpret_cast<uint32_t *>(ws + L.base);
@@ -383,7 +385,8 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     const bool nt = (r.flags & RT_FLAG_NT_STORES) != 0;
     for (uint32_t p = 0; p < r.num_passes; ++p)
         launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, nt, stream, plan,
-                    static_cast<int>(p), n, base + p * kMaxRadix, status + L.status_pass[p], ctr);
+                    static_cast<int>(p), n, base + p * kMaxRadix, status + L.status_pass[p], ctr,
+                    pass_kind + p);
 
     if (!direct && (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP))) {
         const uint32_t grid_c = grid_for(n, 256 * 8, static_cast<uint32_t>(device_cu_count()) * 8);
@@ -438,7 +441,15 @@ extern "C" rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const 
     }
     launch_sort(keys, vals, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws), false, nullptr, nullptr,
                 stream);
-    return finish_call(stream, "rt_sort_ex");
+    s = finish_call(stream, "rt_sort_ex");
+    if (s == RT_OK && debug_sync_enabled()) {  // the stream has drained: read the error word
+        uint32_t err = 0;
+        hipError_t e = hipMemcpy(&err, static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses,
+                                 sizeof err, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_sort_ex: %s", hipGetErrorString(e));
+        if (err) return set_error(RT_ERR_HIP, "rt_sort_ex: device error word 0x%x", err);
+    }
+    return s;
 }
 
 extern "C" rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream) {

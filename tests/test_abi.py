@@ -160,6 +160,33 @@ def test_batched_workspace_bytes(so):
     assert keys >= 4 * cap and keys < 4 * cap + (128 << 20)
 
 
+def test_msd_first_argument_errors(so):
+    fake = ctypes.c_void_p(0x10000)
+    assert so.rt_sort_msd_first(fake, None, 1 << 32, 0, None, 0, None) == _lib.RT_ERR_TOO_LARGE
+    assert so.rt_sort_msd_first(None, None, 100, 0, None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_msd_first(ctypes.c_void_p(0x10002), None, 100, 0, None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_msd_first(fake, ctypes.c_void_p(0x10100), 100, 0, None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_msd_first(fake, None, 100, 0x1, None, 0, None) == _lib.RT_ERR_INVALID_ARG  # unknown flag
+    need = so.rt_msd_first_workspace_bytes(100, 0)
+    assert so.rt_sort_msd_first(fake, None, 100, 0, ctypes.c_void_p(0x100000), need - 1,
+                                None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_msd_first(fake, None, 100, 0, ctypes.c_void_p(0x100010), need,
+                                None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_msd_first(None, None, 1, 0, None, 0, None) == _lib.RT_OK  # nothing to sort
+
+
+def test_msd_first_workspace_bytes(so):
+    assert so.rt_msd_first_workspace_bytes(1, 1) == 0
+    assert so.rt_msd_first_workspace_bytes(1 << 32, 1) == 0
+    n = 1 << 28
+    with_v = so.rt_msd_first_workspace_bytes(n, 1)
+    keys = so.rt_msd_first_workspace_bytes(n, 0)
+    # one temporary per array (the local passes use the caller's arrays as
+    # the other buffer), plus lookback words and tables
+    assert with_v - keys == 4 * n
+    assert keys >= 4 * n and keys < 4 * n + (128 << 20)
+
+
 def test_server_argument_errors(so):
     out = ctypes.c_void_p()
     assert so.rt_server_create(1 << 30, 0, ctypes.byref(out)) == _lib.RT_ERR_INVALID_ARG
