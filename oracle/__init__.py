@@ -17,6 +17,8 @@ Two independent definitions live here:
   writing straight to the output.  Its buckets are filled by appending, not
   by counting, so it shares no step with ``lsd_sort`` beyond digit
   extraction.
+* ``lsd_sort64``: the same LSD sort on 64-bit keys (digit widths summing
+  to 64) with values of zero, one or two 32-bit words per item.
 * ``brute_stable_sort``: the rank definition of the stable ascending sort
   in pure Python, O(n^2), for tiny inputs.
 
@@ -70,8 +72,10 @@ def _bind(so: ctypes.CDLL) -> ctypes.CDLL:
     so.oracle_lsd_sort_segmented.argtypes = [u32p, u32p, u32p, ctypes.c_uint32,
                                              uintp, ctypes.c_uint]
     so.oracle_reverse_sort.argtypes = [u32p, u32p, ctypes.c_uint64]
+    so.oracle_lsd_sort64.argtypes = [u64p, u32p, ctypes.c_uint, ctypes.c_uint64, uintp, ctypes.c_uint]
     for f in (so.oracle_digit_histogram, so.oracle_counting_pass,
-              so.oracle_lsd_sort, so.oracle_lsd_sort_segmented, so.oracle_reverse_sort):
+              so.oracle_lsd_sort, so.oracle_lsd_sort_segmented, so.oracle_reverse_sort,
+              so.oracle_lsd_sort64):
         f.restype = ctypes.c_int
     return so
 
@@ -181,13 +185,37 @@ def reverse_sort(keys, vals=None, so: Optional[ctypes.CDLL] = None):
     return k, v
 
 
-def brute_stable_sort(keys: Sequence[int], vals: Optional[Sequence[int]] = None):
+DEFAULT_WIDTHS64: Tuple[int, ...] = (8,) * 8
+
+
+def lsd_sort64(keys, vals=None, widths: Sequence[int] = DEFAULT_WIDTHS64,
+               so: Optional[ctypes.CDLL] = None):
+    """Stable LSD radix sort of 64-bit keys; vals (optional) is uint32 of
+    shape [n] or [n, 2] (one or two words per item) and moves with its key.
+    Returns (sorted_keys, moved_values or None)."""
+    so = so or lib()
+    k = np.ascontiguousarray(keys, dtype=np.uint64).copy()
+    v = None
+    vw = 0
+    if vals is not None:
+        v = np.ascontiguousarray(vals, dtype=np.uint32).copy()
+        if v.shape[0] != k.size or v.ndim not in (1, 2) or (v.ndim == 2 and v.shape[1] != 2):
+            raise ValueError("values must be [n] or [n, 2] uint32")
+        vw = 1 if v.ndim == 1 else 2
+    w, np_ = _widths_arg(widths)
+    rc = so.oracle_lsd_sort64(k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(v), vw, k.size, w, np_)
+    _check(rc, "lsd_sort64")
+    return k, v
+
+
+def brute_stable_sort(keys: Sequence[int], vals: Optional[Sequence[int]] = None, bits: int = 32):
     """Stable ascending sort by its rank definition, in pure Python.
 
     rank(i) = #{j : k_j < k_i} + #{j < i : k_j == k_i}; item i goes to slot
-    rank(i).  Quadratic: for tiny inputs only.
+    rank(i).  Keys are taken as unsigned `bits`-bit integers.  Quadratic:
+    for tiny inputs only.
     """
-    ks = [int(x) & 0xFFFFFFFF for x in keys]
+    ks = [int(x) & ((1 << bits) - 1) for x in keys]
     n = len(ks)
     out_k = [0] * n
     out_v = None if vals is None else [0] * n

@@ -423,3 +423,101 @@ int oracle_reverse_sort(uint32_t *keys, uint32_t *vals, uint64_t n)
     free(out_v);
     return rc;
 }
+
+/*
+ * 64-bit keys (the wider items Section 4 allows: a key with a value
+ * adjacent to it, larger combinations than one 64-bit word being possible).
+ * The same LSD radix sort as above, on K = 64-bit keys: digit widths sum to
+ * 64, each pass is Section 3's counting sort on one digit, and each item's
+ * value of vw 32-bit words (0, 1 or 2) moves with its key.
+ */
+static uint32_t digit_of64(uint64_t key, unsigned shift, unsigned width)
+{
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 11
+    /* planted mistake: the shift wraps at 32 bits */
+    return (uint32_t)(key >> (shift & 31u)) & ((1u << width) - 1u);
+#else
+    return (uint32_t)(key >> shift) & ((1u << width) - 1u);
+#endif
+}
+
+static int oracle_counting_pass64(const uint64_t *kin, const uint32_t *vin,
+                                  uint64_t *kout, uint32_t *vout, unsigned vw,
+                                  uint64_t n, unsigned shift, unsigned width)
+{
+    uint64_t buckets = (uint64_t)1 << width, d, i, running = 0;
+    uint64_t *next = (uint64_t *)calloc(buckets, sizeof(uint64_t));
+    unsigned w;
+    if (next == NULL)
+        return ORACLE_ENOMEM;
+    for (i = 0; i < n; ++i) /* histogram */
+        next[digit_of64(kin[i], shift, width)] += 1;
+    for (d = 0; d < buckets; ++d) { /* exclusive prefix sum */
+        uint64_t count = next[d];
+        next[d] = running;
+        running += count;
+    }
+    for (i = 0; i < n; ++i) { /* scatter in input order */
+        uint32_t dd = digit_of64(kin[i], shift, width);
+        uint64_t slot = next[dd];
+        kout[slot] = kin[i];
+        for (w = 0; w < vw; ++w) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 12
+            /* planted mistake: only the first value word moves */
+            vout[slot * vw + w] = w == 0 ? vin[i * vw] : vin[slot * vw + w];
+#else
+            vout[slot * vw + w] = vin[i * vw + w];
+#endif
+        }
+        next[dd] = slot + 1;
+    }
+    free(next);
+    return ORACLE_OK;
+}
+
+int oracle_lsd_sort64(uint64_t *keys, uint32_t *vals, unsigned vw, uint64_t n,
+                      const unsigned *widths, unsigned npasses)
+{
+    uint64_t *ka, *kb, *tk;
+    uint32_t *va = NULL, *vb = NULL, *tv;
+    unsigned p, shift = 0, total = 0;
+    int rc = ORACLE_OK;
+    if (widths == NULL || npasses == 0 || npasses > 64 || vw > 2 || (vw > 0 && vals == NULL))
+        return ORACLE_EINVAL;
+    for (p = 0; p < npasses; ++p) {
+        if (widths[p] < 1 || widths[p] > 16)
+            return ORACLE_EINVAL;
+        total += widths[p];
+    }
+    if (total != 64 || (n > 0 && keys == NULL))
+        return ORACLE_EINVAL;
+    if (n < 2)
+        return ORACLE_OK;
+    ka = keys;
+    kb = (uint64_t *)malloc(n * sizeof(uint64_t));
+    if (kb == NULL)
+        return ORACLE_ENOMEM;
+    if (vw > 0) {
+        va = vals;
+        vb = (uint32_t *)malloc(n * vw * sizeof(uint32_t));
+        if (vb == NULL) {
+            free(kb);
+            return ORACLE_ENOMEM;
+        }
+    }
+    for (p = 0; p < npasses && rc == ORACLE_OK; ++p) {
+        rc = oracle_counting_pass64(ka, va, kb, vb, vw, n, shift, widths[p]);
+        tk = ka; ka = kb; kb = tk;
+        tv = va; va = vb; vb = tv;
+        shift += widths[p];
+    }
+    if (rc == ORACLE_OK && ka != keys) {
+        memcpy(keys, ka, n * sizeof(uint64_t));
+        if (vw > 0)
+            memcpy(vals, va, n * vw * sizeof(uint32_t));
+    }
+    free(ka == keys ? kb : ka);
+    if (vw > 0)
+        free(va == vals ? vb : va);
+    return rc;
+}

@@ -228,9 +228,49 @@ def pin_reverse_sort(so):
         assert np.array_equal(ks, idx << np.uint32(shift)) and np.array_equal(vs, br)
 
 
+ALPHABET64 = [0, 1, 0xFF, 0x100, 0xFFFFFFFF, 0x100000000, 0x7FFFFFFFFFFFFFFF,
+              0x8000000000000000, 0xFFFFFFFFFFFFFFFF]
+
+
+def pin_sort64(so):
+    """The 64-bit-key sort against brute force, numpy's stable argsort, and
+    the 32-bit sort on keys below 2^32."""
+    for length in range(0, 4):
+        for t in itertools.product(ALPHABET64, repeat=length):
+            ks, vs = oracle.lsd_sort64(np.array(t, dtype=np.uint64), np.arange(length, dtype=np.uint32), so=so)
+            bk, bv = oracle.brute_stable_sort(t, list(range(length)), bits=64)
+            assert [int(x) for x in ks] == bk and list(vs) == bv, t
+    rng = np.random.default_rng(77)
+    n = 1 << 14
+    u = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    dists = {
+        "uniform": u,
+        "small": u >> np.uint64(44),
+        "high_only": u & np.uint64(0xFFFF000000000000),
+        "and2": u & rng.integers(0, 1 << 64, size=n, dtype=np.uint64),
+        "dict16": rng.integers(0, 1 << 64, size=16, dtype=np.uint64)[rng.integers(0, 16, size=n)],
+        "equal": np.full(n, 0x0123456789ABCDEF, dtype=np.uint64),
+    }
+    v1 = np.arange(n, dtype=np.uint32)
+    v2 = np.stack([v1, v1 ^ np.uint32(0x5A5A5A5A)], axis=1)
+    for name, k in dists.items():
+        perm = np.argsort(k, kind="stable")
+        for widths in [(8,) * 8, (11, 11, 11, 11, 10, 10), (16, 16, 16, 16), (5, 13, 7, 9, 16, 14)]:
+            ks, vs = oracle.lsd_sort64(k, v1, widths, so=so)
+            assert np.array_equal(ks, k[perm]) and np.array_equal(vs, v1[perm]), (name, widths)
+        ks, vs = oracle.lsd_sort64(k, v2, so=so)
+        assert np.array_equal(ks, k[perm]) and np.array_equal(vs, v2[perm]), name
+        ks, none = oracle.lsd_sort64(k, None, so=so)
+        assert none is None and np.array_equal(ks, np.sort(k)), name
+    k32 = inputs.and_keys(n, 2, 78)
+    ks, vs = oracle.lsd_sort64(k32.astype(np.uint64), v1, so=so)
+    rk, rv = oracle.lsd_sort(k32, v1, so=so)
+    assert np.array_equal(ks, rk.astype(np.uint64)) and np.array_equal(vs, rv)
+
+
 PINS = [pin_worked_example, pin_unsigned_order, pin_closed_forms, pin_heavy_ties,
         pin_histograms, pin_numpy_stable, pin_width_invariance, pin_invariants,
-        pin_exhaustive_tiny, pin_reverse_sort]
+        pin_exhaustive_tiny, pin_reverse_sort, pin_sort64]
 
 
 # --------------------------------------------------------------- tests ----
@@ -291,6 +331,8 @@ MUTANTS = {
     8: "MSD-first sort: every bucket written from output slot 0",
     9: "MSD-first sort: partition on digit 2",
     10: "MSD-first sort: first local pass's buckets visited in decreasing order",
+    11: "64-bit keys: digit shift wraps at 32 bits",
+    12: "64-bit keys: only the first of two value words moves",
 }
 
 
