@@ -10,7 +10,7 @@ region.  The run prints one JSON line on stdout: whole-sort throughput
 kernel (the counting-sort pass), and the CPU oracle timed on this host.
 Further legs, each reported in the same line and each skippable: the
 transfer-inclusive rate, the MSD-first sort of the same input, the batched
-workload and the serving loop.
+workload, 64-bit keys and the serving loop.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -176,6 +176,54 @@ def bench_msd_first(rts, dev, k0, v0, slots, K, W, single_gkeys, ref_k, ref_v):
             "bucket_histogram_ms": round(float(np.mean([h[1] for h in hists if len(h) > 1])), 4)
             if hists else None,
             "matches_lsd_sort": same}
+
+
+def bench_sort64(rts, inputs, dev, K, W):
+    """64-bit keys: 2^28 uniform u64 keys carrying u32 index values, eight
+    8-bit passes, each timed call on its own pre-staged copy."""
+    import numpy as np
+    import torch
+    from paper_1008_2849_amd._lib import RT_KIND_HISTOGRAM, RT_KIND_PASS
+    w = inputs.WORKLOADS["pairs64_256m_uniform"]
+    n = w.n
+    k_h, _ = inputs.make_workload(w)
+    k0 = torch.from_numpy(k_h.view(np.int64)).to(dev)
+    del k_h
+    v0 = torch.arange(n, dtype=torch.int32, device=dev)
+    slots = [(k0.clone(), v0.clone()) for _ in range(K + W)]
+    ws = torch.empty(rts.workspace_bytes64(n, 4), dtype=torch.uint8, device=dev)
+    for i in range(W):
+        rts.sort64_ex(slots[i][0], slots[i][1], None, ws)
+    torch.cuda.synchronize()
+    rts.profile_start(max_marks=32 * K + 32)
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        rts.sort64_ex(slots[i][0], slots[i][1], None, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    calls = split_calls(rts.profile_stop(capacity=32 * K + 32))
+    pass_ms = [ms for c in calls for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+    hist_ms = [ms for c in calls for kind, ms in c[1] if kind == RT_KIND_HISTOGRAM]
+    ko, vo = slots[W + K - 1]
+    # properties that fix a stable sort of original indices (unsigned order
+    # through the sign flip)
+    ku = ko ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+    ok = bool((ku[1:] >= ku[:-1]).all().item())
+    vl = vo.to(torch.int64)
+    ok &= bool((torch.bincount(vl, minlength=n) == 1).all().item())
+    ok &= bool(torch.equal(k0[vl], ko))
+    eq = ko[1:] == ko[:-1]
+    ok &= bool((vl[1:][eq] > vl[:-1][eq]).all().item())
+    del slots, ws, ku, vl, eq
+    pm = float(np.mean(pass_ms))
+    pass_bytes = 2.0 * 12 * n
+    gk = n / (wall / K) / 1e9
+    return {"workload": w.name, "n": n, "key_bits": 64, "value_bytes": 4, "digit_bits": [8] * 8,
+            "Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
+            "pass_ms": round(pm, 4), "pass_GBps": round(pass_bytes / pm / 1e6, 1),
+            "pass_frac_of_peak": round(pass_bytes / pm / 1e6 / PEAK_HBM_GBPS, 4),
+            "histogram_ms": round(float(np.mean(hist_ms)), 4) if hist_ms else None,
+            "parity_properties_ok": ok}
 
 
 def bench_pcie(rts, dev, keys_h, vals_h, cfg, ref_k, ref_v, reps=3):
@@ -407,6 +455,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-msd-first", action="store_true", help="skip the MSD-first leg")
+    ap.add_argument("--no-sort64", action="store_true", help="skip the 64-bit-key leg")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
     ap.add_argument("--serve-loads", default="0.5", help="comma list of offered loads (fraction of "
                     "single-array throughput); empty to skip serving")
@@ -564,10 +613,16 @@ def main() -> int:
         log("batched workload")
         batched = bench_batched(rts, inputs, dev, K, W, gkeys)
         log(f"batched: {batched}")
+    del slots
+    torch.cuda.empty_cache()
+    sort64 = None
+    if not args.no_sort64 and args.workload == "pairs_256m_uniform":
+        log("64-bit keys leg")
+        sort64 = bench_sort64(rts, inputs, dev, K, W)
+        torch.cuda.empty_cache()
+        log(f"sort64: {sort64}")
     serving = []
     if (args.serve_loads or args.serve_inflight) and args.workload == "pairs_256m_uniform":
-        del slots
-        torch.cuda.empty_cache()
         for load in (float(x) for x in args.serve_loads.split(",") if x):
             log(f"serving at load {load}")
             serving.append(bench_serving(rts, inputs, load, args.serve_seconds, 1.0, gkeys))
@@ -607,6 +662,7 @@ def main() -> int:
         "parity_properties_ok": props,
         "transfer_inclusive": pcie,
         "msd_first": msd_first,
+        "sort64": sort64,
         "batched": batched,
         "serving": serving,
         "kernel_source_digest": digest,
@@ -617,6 +673,7 @@ def main() -> int:
     ok = ok and all(not s.get("failures") for s in serving)
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
+    ok = ok and (sort64 is None or sort64["parity_properties_ok"])
     return 0 if ok else 3
 
 

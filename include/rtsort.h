@@ -108,6 +108,45 @@ rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * 64-bit keys
+ * --------------------------------------------------------------------- */
+
+/*
+ * Sort n 64-bit unsigned keys in place, ascending and stable, by the same
+ * LSD radix sort on K = 64-bit keys (Section 4; each pass Section 3's
+ * counting sort).  The paper sorts 32-bit keys and notes that its items may
+ * be wider than one 64-bit key-value word; this is that variant.
+ * keys: device u64[n], 8-byte aligned.
+ */
+rt_status rt_sort_keys64(uint64_t *keys, size_t n, hipStream_t stream);
+
+/*
+ * As rt_sort_keys64, moving a 32-bit value with each key.  keys: device
+ * u64[n], 8-byte aligned; vals: device u32[n], 4-byte aligned, not
+ * overlapping the keys.  vals == NULL is RT_ERR_INVALID_ARG.
+ */
+rt_status rt_sort_pairs64(uint64_t *keys, uint32_t *vals, size_t n, hipStream_t stream);
+
+/*
+ * Explicit form.  value_bytes: 0 (keys only, vals ignored), 4 or 8 bytes per
+ * item; vals is then a device array of n such values, aligned to
+ * value_bytes.  cfg (NULL = built-in default, eight 8-bit digits in 8K-item
+ * tiles): digit_bits must sum to 64, each 1..RT_MAX_DIGIT_BITS; tile shapes
+ * built are 1024x8 and 512x16 for digits of up to 8 bits and 512x8 for
+ * wider ones (correct, but several times slower than 8-bit digits); flags:
+ * 0 or RT_FLAG_NO_SKIP (anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
+ * 256-byte aligned, or NULL for the library's per-stream cache; with a
+ * caller workspace the call only enqueues kernels.  Errors and stream
+ * behaviour as for rt_sort_ex.
+ */
+rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_bytes, size_t n, const rt_config *cfg,
+                       void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Workspace bytes of rt_sort64_ex (0 for n < 2, n >= 2^32, a value_bytes
+ * other than 0, 4 or 8, or an invalid cfg). */
+size_t rt_workspace_bytes64(size_t n, uint32_t value_bytes, const rt_config *cfg);
+
+/* ------------------------------------------------------------------------
  * Batched segmented sort
  * --------------------------------------------------------------------- */
 

@@ -84,6 +84,10 @@ SIGNATURES = {
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
     "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
     "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),
+    "rt_sort_keys64": (ctypes.c_int, [vp, sz, vp]),
+    "rt_sort_pairs64": (ctypes.c_int, [vp, vp, sz, vp]),
+    "rt_sort64_ex": (ctypes.c_int, [vp, vp, u32, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
+    "rt_workspace_bytes64": (sz, [sz, u32, ctypes.POINTER(RtConfig)]),
     "rt_msd_first_workspace_bytes": (sz, [sz, ctypes.c_int]),
     "rt_sort_msd_first": (ctypes.c_int, [vp, vp, sz, u32, vp, sz, vp]),
     "rt_digit_histograms": (ctypes.c_int, [vp, sz, ctypes.POINTER(RtConfig), vp, vp]),

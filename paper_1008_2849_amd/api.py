@@ -124,6 +124,62 @@ def sort_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, strea
           "rt_sort_ex")
 
 
+def _check_tensor64(t, name: str, dtypes):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must be one of {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def sort64_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, stream=None) -> None:
+    """Sort 64-bit keys (an int64/uint64 GPU tensor holding u64 bit
+    patterns) in place, stably, moving vals (None, or int32/uint32 for
+    4-byte values, int64/uint64 for 8-byte values) with them."""
+    torch = _torch()
+    _check_tensor64(keys, "keys", (torch.int64, torch.uint64))
+    _check_tensor64(vals, "vals", (torch.int32, torch.uint32, torch.int64, torch.uint64))
+    vb = 0 if vals is None else vals.element_size()
+    if vals is not None and vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    c, p = _cfg_ptr(cfg)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr = workspace.data_ptr()
+        ws_bytes = workspace.numel() * workspace.element_size()
+    check(lib().rt_sort64_ex(_ptr(keys), _ptr(vals), vb, keys.numel(), p, ws_ptr, ws_bytes, _stream(stream)),
+          "rt_sort64_ex")
+
+
+def sort_keys64(keys, stream=None) -> None:
+    """Sort a 1-D int64/uint64 GPU tensor in place (unsigned 64-bit order)."""
+    torch = _torch()
+    _check_tensor64(keys, "keys", (torch.int64, torch.uint64))
+    check(lib().rt_sort_keys64(_ptr(keys), keys.numel(), _stream(stream)), "rt_sort_keys64")
+
+
+def sort_pairs64(keys, vals, stream=None) -> None:
+    """Sort 64-bit keys in place and move 32-bit vals with them (stable)."""
+    torch = _torch()
+    _check_tensor64(keys, "keys", (torch.int64, torch.uint64))
+    _check_tensor(vals, "vals")
+    if vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    check(lib().rt_sort_pairs64(_ptr(keys), _ptr(vals), keys.numel(), _stream(stream)), "rt_sort_pairs64")
+
+
+def workspace_bytes64(n: int, value_bytes: int, cfg: Optional[Config] = None) -> int:
+    c, p = _cfg_ptr(cfg)
+    return int(lib().rt_workspace_bytes64(n, value_bytes, p))
+
+
 def sort_pairs_batched(keys, vals, offsets, max_total: Optional[int] = None, stream=None) -> None:
     """Sort every segment [offsets[s], offsets[s+1]) independently (stable).
     vals may be None; offsets is a device tensor of num_segments + 1 entries."""

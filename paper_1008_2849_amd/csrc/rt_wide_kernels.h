@@ -1,0 +1,279 @@
+// rt_wide_kernels.h -- gfx950 kernels of the LSD radix sort of 64-bit keys.
+//
+// The sort is the one of rt_kernels.h with K = 64-bit keys (Section 4 allows
+// larger items than one 64-bit key-value word): an upfront read builds the
+// digit histograms of every pass, the shared planning kernel turns them into
+// digit offsets, skips constant digits and assigns buffers, and one onesweep
+// kernel per executed pass ranks, looks back, stages by digit in LDS and
+// writes each digit run as consecutive addresses.  Values ride along as one
+// or two 32-bit words per item (VW), or are absent (VW = 0).
+//
+// What differs from the 32-bit kernels: keys live in registers and LDS as
+// 64-bit words (a tile of 8K items stages 64 KiB of keys), a digit is taken
+// from the whole 64-bit key (an 11-bit digit may straddle its two halves),
+// and global addresses are formed in 64 bits.
+#include "rt_kernels.h"
+
+namespace rt {
+
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+
+template <int VW>
+struct ValWord {
+    typedef uint32_t type;  // VW = 0 (unused) or 1
+};
+template <>
+struct ValWord<2> {
+    typedef uint64_t type;  // two 32-bit words moved as one
+};
+
+__device__ __forceinline__ uint32_t digit64(uint64_t key, uint32_t shift, uint32_t mask) {
+    return static_cast<uint32_t>(key >> shift) & mask;
+}
+
+// ---------------------------------------------------------------------------
+// upfront histograms of all passes (one read of the 64-bit keys)
+// ---------------------------------------------------------------------------
+
+// As k_histogram: C lane-class copies of every pass's counters in padded LDS
+// rows, and a wave batch of 64 * U keys that shares a pass's digit counted
+// with one add.  hist[p * kMaxRadix + d] must start at zero.
+template <int BLOCK, int C>
+__global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restrict__ keys, uint32_t n, HistArgs ha,
+                                                       uint32_t *__restrict__ hist) {
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int U = 8;
+    extern __shared__ uint32_t s_h[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    const uint32_t row = ha.total_bins + 1u;
+    for (uint32_t i = tid; i < C * row; i += BLOCK) s_h[i] = 0u;
+    __syncthreads();
+    uint32_t *h = s_h + (lane % C) * row;
+
+    const size_t wave_span = static_cast<size_t>(64) * U;
+    const size_t stride = static_cast<size_t>(gridDim.x) * WAVES * wave_span;
+    for (size_t base = (static_cast<size_t>(blockIdx.x) * WAVES + wave) * wave_span; base < n; base += stride) {
+        if (base + wave_span <= n) {
+            uint64_t k[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) k[u] = keys[base + u * 64 + lane];
+            const uint64_t k0 = (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(k[0] >> 32)))
+                                 << 32) |
+                                __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(k[0]));
+            uint64_t differ = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) differ |= k[u] ^ k0;
+#pragma unroll
+            for (int p = 0; p < kMaxPasses; ++p) {
+                if (p >= static_cast<int>(ha.num_passes)) break;
+                uint32_t *hp = h + ha.lds_offset[p];
+                if (__builtin_amdgcn_ballot_w64(digit64(differ, ha.shift[p], ha.mask[p]) != 0u) == 0u) {
+                    if (lane == 0) atomicAdd(&hp[digit64(k0, ha.shift[p], ha.mask[p])], static_cast<uint32_t>(64 * U));
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) atomicAdd(&hp[digit64(k[u], ha.shift[p], ha.mask[p])], 1u);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t i = base + u * 64 + lane;
+                if (i >= n) continue;
+                const uint64_t key = keys[i];
+                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p)
+                    atomicAdd(&h[ha.lds_offset[p] + digit64(key, ha.shift[p], ha.mask[p])], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < ha.total_bins; i += BLOCK) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < C; ++w) c += s_h[w * row + i];
+        if (c == 0) continue;
+        uint32_t p = 0;
+        while (p + 1 < ha.num_passes && i >= ha.lds_offset[p + 1]) ++p;
+        atomicAdd(&hist[p * kMaxRadix + (i - ha.lds_offset[p])], c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// onesweep counting-sort pass over 64-bit keys
+// ---------------------------------------------------------------------------
+
+// The structure of k_onesweep: tiles claimed in order from an atomic
+// counter; wave w owns items [w * 64 * IPT, (w + 1) * 64 * IPT) of the tile
+// and lane l holds item j * 64 + l in slot j, so the ballot ranking follows
+// input order (stable); per-digit tile counts are published as the tile's
+// aggregate, the tile is staged by digit in LDS, the lookback gives each
+// digit's offset among earlier tiles, and consecutive LDS slots of a digit
+// go to consecutive output addresses.  The plan's pointers are reinterpreted
+// as 64-bit keys and VW-word values.
+template <int BITS, int BLOCK, int IPT, int VW, typename S>
+__global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict__ plan, int pass, uint32_t n,
+                                                      const uint32_t *__restrict__ pass_base, S *__restrict__ status,
+                                                      uint32_t *__restrict__ tile_counter,
+                                                      uint32_t *__restrict__ error_flag) {
+    constexpr int RADIX = 1 << BITS;
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int TILE = BLOCK * IPT;
+    constexpr int WAVE_ITEMS = 64 * IPT;
+    constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;
+    constexpr int DT = RADIX / R;
+    constexpr bool VALS = VW > 0;
+    typedef typename ValWord<VW>::type V;
+    typedef __attribute__((address_space(1))) V g_v;
+    using St = Status<S>;
+
+    const PassPlan pp = plan->pass[pass];
+    if (!pp.active) return;
+
+    __shared__ uint64_t s_stage_k[TILE];
+    __shared__ V s_stage_v[VALS ? TILE : 1];
+    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
+    __shared__ uint32_t s_gbase[RADIX];
+    __shared__ uint32_t s_wsum[WAVES];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    const uint32_t shift = pp.shift;
+    const uint32_t mask = (1u << pp.width) - 1u;
+    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;
+    uint32_t *wh = s_whist + wave * RADIX;
+    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
+    const g_u64 *src_k = (const g_u64 *)pp.src_k;
+    g_u64 *dst_k = (g_u64 *)pp.dst_k;
+    const g_v *src_v = (const g_v *)pp.src_v;
+    g_v *dst_v = (g_v *)pp.dst_v;
+
+    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
+    if (tid == 0) s_tile = atomicAdd(tile_counter + pass, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const size_t tile_base = static_cast<size_t>(tile) * TILE;
+    if (tile_base >= n) return;
+    const uint32_t valid = static_cast<uint32_t>(min(static_cast<size_t>(TILE), n - tile_base));
+    const bool full = valid == static_cast<uint32_t>(TILE);
+
+    uint64_t key[IPT];
+    V val[VALS ? IPT : 1];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t i = wslot0 + j * 64;
+        key[j] = (full || i < valid) ? src_k[tile_base + i] : 0ull;
+    }
+    if constexpr (VALS) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = wslot0 + j * 64;
+            val[j] = (full || i < valid) ? src_v[tile_base + i] : V(0);
+        }
+    }
+
+    // stable rank inside the wave; items past the end take the last digit
+    uint32_t rnk[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        uint32_t d = digit64(key[j], shift, mask);
+        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
+        uint32_t lo, hi;
+        match_digit<BITS>(d, lo, hi);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        const uint32_t cnt = wh[d];
+        rnk[j] = cnt + below;
+        uint32_t *dst = below == 0 ? wh + d : scratch;
+        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
+        compiler_fence();
+    }
+    __syncthreads();
+
+    // per digit: earlier waves' counts, tile count, publish the aggregate
+    uint32_t tcount[R];
+    uint32_t tsum = 0;
+    if (tid < DT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = tid * R + r;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = s_whist[w * RADIX + d];
+                s_whist[w * RADIX + d] = run;
+                run += c;
+            }
+            tcount[r] = run;
+            tsum += run;
+            status_store(status + static_cast<size_t>(tile) * RADIX + d,
+                         St::make(tile == 0 ? kFlagIncl : kFlagAgg, run));
+        }
+    }
+    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
+    uint32_t dexcl[R];
+    if (tid < DT) {
+        uint32_t run = texcl;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = tid * R + r;
+            dexcl[r] = run;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + d] += run;
+            run += tcount[r];
+        }
+    }
+    __syncthreads();
+
+    // gather by digit in LDS
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        uint32_t d = digit64(key[j], shift, mask);
+        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
+        const uint32_t r = wh[d] + rnk[j];
+        s_stage_k[r] = key[j];
+        if constexpr (VALS) s_stage_v[r] = val[j];
+    }
+
+    // lookback
+    if (tid < DT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = tid * R + r;
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), d, RADIX, error_flag);
+            if (tile != 0)
+                status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
+            s_gbase[d] = pass_base[d] + excl - dexcl[r];
+        }
+    }
+    __syncthreads();
+
+    // scatter; the clamp keeps a logic error from storing outside the array
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t i = j * BLOCK + tid;
+        const uint64_t k = s_stage_k[i];
+        const uint32_t p = min(s_gbase[digit64(k, shift, mask)] + i, n - 1u);
+        if (full || i < valid) {
+            dst_k[p] = k;
+            if constexpr (VALS) dst_v[p] = s_stage_v[i];
+        }
+    }
+}
+
+// Moves the result of a sort with exactly one executed pass from the
+// temporary back into the caller's arrays: key_words and val_words 32-bit
+// words per item.
+static __global__ __launch_bounds__(256) void k_copy_back_words(const SortPlan *__restrict__ plan,
+                                                               const uint32_t *__restrict__ tk,
+                                                               const uint32_t *__restrict__ tv,
+                                                               uint32_t *__restrict__ uk, uint32_t *__restrict__ uv,
+                                                               size_t key_words, size_t val_words) {
+    if (!plan->copy_back) return;
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < key_words; i += stride) uk[i] = tk[i];
+    for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < val_words; i += stride) uv[i] = tv[i];
+}
+
+}  // namespace rt

@@ -38,6 +38,7 @@ SEED_TOP_BYTE = 34        # 24 significant bits, 2^26 pairs
 SEED_ZIPF16 = 35          # 16 distinct keys, Zipf s = 1.2, 2^26 pairs
 SEED_BATCHED = 4          # 4096 segments
 SEED_SERVING = 5          # serving request stream
+SEED_PAIRS64_256M = 6     # 2^28 uniform 64-bit keys with 32-bit index values
 
 # Distribution ids shared with the device generator.
 DIST_UNIFORM = 0
@@ -53,6 +54,29 @@ def _rng(seed: int) -> np.random.Generator:
 def uniform_keys(n: int, seed: int) -> np.ndarray:
     """n keys uniform over [0, 2^32)."""
     return _rng(seed).integers(0, 2**32, size=n, dtype=U32)
+
+
+def uniform_keys64(n: int, seed: int) -> np.ndarray:
+    """n keys uniform over [0, 2^64)."""
+    return _rng(seed).integers(0, 1 << 64, size=n, dtype=np.uint64)
+
+
+def keys64(kind: str, n: int, seed: int) -> np.ndarray:
+    """64-bit keys: uniform; `small` (below 2^20, so the high digits are
+    constant); `high` (only the top 16 bits vary); `low32` (the high half is
+    zero); `and2` (AND of two uniform words)."""
+    u = uniform_keys64(n, seed)
+    if kind == "uniform":
+        return u
+    if kind == "small":
+        return u >> np.uint64(44)
+    if kind == "high":
+        return u & np.uint64(0xFFFF000000000000)
+    if kind == "low32":
+        return u & np.uint64(0xFFFFFFFF)
+    if kind == "and2":
+        return u & uniform_keys64(n, seed + 1000)
+    raise ValueError(f"unknown 64-bit key distribution {kind!r}")
 
 
 def index_values(n: int, start: int = 0) -> np.ndarray:
@@ -245,6 +269,7 @@ class Workload:
     kind: str                 # uniform | and | top_byte | zipf16
     seed: int
     param: int = 0            # k for AND-of-k, the top byte for top_byte
+    key_bits: int = 32        # 64: u64 keys (kind as in keys64)
 
 
 WORKLOADS: Dict[str, Workload] = {
@@ -255,6 +280,8 @@ WORKLOADS: Dict[str, Workload] = {
     "pairs_64m_and8": Workload("pairs_64m_and8", 2**26, True, "and", SEED_AND[8], 8),
     "pairs_64m_top_a5": Workload("pairs_64m_top_a5", 2**26, True, "top_byte", SEED_TOP_BYTE, 0xA5),
     "pairs_64m_zipf16": Workload("pairs_64m_zipf16", 2**26, True, "zipf16", SEED_ZIPF16),
+    "pairs64_256m_uniform": Workload("pairs64_256m_uniform", 2**28, True, "uniform", SEED_PAIRS64_256M,
+                                     key_bits=64),
 }
 
 
@@ -274,6 +301,6 @@ def make_workload(w: Workload, n: Optional[int] = None):
     """(keys, values-or-None) for a named workload, optionally at a smaller n
     with the same distribution and seed."""
     n = w.n if n is None else n
-    keys = make_keys(w.kind, n, w.seed, w.param)
+    keys = keys64(w.kind, n, w.seed) if w.key_bits == 64 else make_keys(w.kind, n, w.seed, w.param)
     vals = index_values(n) if w.with_values else None
     return keys, vals
