@@ -184,7 +184,7 @@ template <int BLOCK, int C>
 __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict__ keys, uint32_t n,
                                                      HistArgs ha, uint32_t *__restrict__ hist) {
     constexpr int WAVES = BLOCK / 64;
-    constexpr int U = 8;  // slots in flight per lane
+    constexpr int U = 16;  // slots in flight per lane (8 measured 18 % slower on 2^28 keys)
     extern __shared__ uint32_t s_h[];  // C rows of total_bins + 1 counters
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
     constexpr int BINS = kSegPasses * kSegRadix;
     constexpr int ROW = BINS + 1;
     constexpr int WAVES = BLOCK / 64;
-    constexpr int U = 8;
+    constexpr int U = 16;
     constexpr uint32_t SPAN = 64 * U;  // keys per wave batch
     __shared__ uint32_t s_h[C * ROW];
     const uint32_t tid = threadIdx.x;
