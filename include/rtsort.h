@@ -351,9 +351,13 @@ rt_status rt_server_destroy(rt_server *s);
  * --------------------------------------------------------------------- */
 
 /*
- * Load a tuning table (JSON written by the autotuner) that maps
- * (with_values, size class) to digit widths, block size, items per thread
- * and flags.  NULL restores the built-in defaults.
+ * Load a tuning table (JSON written by the autotuner).  Its "keys" and
+ * "pairs" entries map single-array sorts of n in [min_n, max_n] to digit
+ * widths, block size, items per thread and flags; its "segments" entries
+ * (increasing max_n, at most 4, each at most 16384 and within its shape,
+ * digits 8,8,8,8) are the whole-in-LDS size classes of the segmented sort
+ * (see rt_segment_classes).  A malformed table is RT_ERR_INVALID_ARG and
+ * leaves the loaded one in force.  NULL restores the built-in defaults.
  */
 rt_status rt_load_tuning(const char *json_path);
 
@@ -385,6 +389,18 @@ rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
 #define RT_KIND_PASS 16u     /* + pass index: one counting-sort pass (onesweep) */
 rt_status rt_profile_start(uint32_t max_marks);
 rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count);
+
+/*
+ * The whole-in-LDS size classes of the segmented sort in force (built in,
+ * or the tuning table's "segments" entries): *count classes, class c sorting
+ * the segments of up to max_n[c] items (more than max_n[c - 1]) with one
+ * block of block[c] threads x ipt[c] items; larger segments are tiled.  The
+ * host arrays hold at least 4 entries; any of them may be NULL.  Batched
+ * calls and the MSD-first sort use the classes in force when their layout
+ * is computed (rt_batched_workspace_bytes sizes the workspace for them), a
+ * server those in force when it was created.
+ */
+rt_status rt_segment_classes(uint32_t *count, uint32_t *max_n, uint32_t *block, uint32_t *ipt);
 
 const char *rt_status_string(rt_status s);
 const char *rt_last_error(void);

@@ -290,10 +290,27 @@ def load_tuning(path: Optional[str]) -> None:
     check(lib().rt_load_tuning(None if path is None else path.encode()), "rt_load_tuning")
 
 
+def load_default_tuning() -> None:
+    """Back to the table the library loads on first use: RT_TUNING_FILE, else
+    the committed table for gfx950, else the built-in defaults."""
+    so = lib()
+    check(so.rt_load_tuning(None), "rt_load_tuning")
+    _lib._load_default_tuning(so)
+
+
 def tuned_config(n: int, with_values: bool) -> Config:
     c = RtConfig()
     check(lib().rt_tuned_config(n, 1 if with_values else 0, ctypes.byref(c)), "rt_tuned_config")
     return Config.from_c(c)
+
+
+def segment_classes():
+    """The segmented sort's whole-in-LDS size classes in force:
+    [(max_n, block, ipt), ...] in increasing max_n."""
+    count = ctypes.c_uint32(0)
+    arrs = [(ctypes.c_uint32 * 4)() for _ in range(3)]
+    check(lib().rt_segment_classes(ctypes.byref(count), *arrs), "rt_segment_classes")
+    return [(int(arrs[0][c]), int(arrs[1][c]), int(arrs[2][c])) for c in range(count.value)]
 
 
 def version() -> str:

@@ -2,13 +2,25 @@
 GPU and writes the tuning table that rt_load_tuning() reads.
 
     python -m paper_1008_2849_amd.autotune --out paper_1008_2849_amd/tuning/gfx950.json
+    python -m paper_1008_2849_amd.autotune --out ... --ops segments   # keep the other entries
 
-For keys-only and key/value sorts at each size class it times every
+Single-array sorts ("keys", "pairs"): at each measured size it times every
 (digit widths, tile shape, store flavour) the library has kernels for and
-keeps the fastest.  Each candidate's output is checked against a stable
-argsort of the same keys on the device before its time counts, so a
-configuration can only win by sorting correctly.  Entries cover size
-ranges split at the geometric midpoints between measured sizes.
+keeps the fastest; entries cover size ranges split at the geometric
+midpoints between measured sizes.  Each candidate's output is checked
+against a stable argsort of the same keys on the device before its time
+counts, so a configuration can only win by sorting correctly.
+
+Segmented sort ("segments"): for each size range (2^(k-1), 2^k], k = 6..14,
+it sorts a batch of about 2^23 items in segments of sizes uniform in the
+range, once with each whole-in-LDS kernel shape that holds 2^k items and
+once with the range left to the tiled path, and keeps the fastest (each
+output must equal the built-in classes' output bit for bit).  Consecutive
+ranges with the same winner form one class; the classes stop at the first
+range where tiling wins, and at most four are kept (the split with the
+least per-segment time, found by dynamic programming).  The split is then
+timed on the batched workload's log-uniform mix against the built-in
+classes, and the faster of the two is written.
 """
 from __future__ import annotations
 
@@ -108,20 +120,225 @@ def tune(sizes, reps, log=print):
     return entries, report
 
 
+# whole-in-LDS shapes the library compiles; keep in step with
+# RT_FOR_EACH_SEG_SMALL_SHAPE in csrc/rt_common.h
+SEG_SHAPES = [(64, 4), (64, 8), (128, 4), (128, 8), (256, 4), (256, 8), (512, 4), (512, 8), (256, 16),
+              (512, 16), (1024, 8), (1024, 16)]
+SEG_RANGES = list(range(6, 15))  # (2^(k-1), 2^k]
+SEG_BATCH_ITEMS = 1 << 23
+
+
+def _segment_table(classes):
+    return {"entries": [{"op": "segments", "min_n": 0, "max_n": m, "digit_bits": [8, 8, 8, 8],
+                         "block": b, "ipt": i} for m, b, i in classes]}
+
+
+def _time_batched(keys0, vals0, off, n, classes, reps, check, tmpdir):
+    """Median call time (ms, from the library's kernel marks) of a batched
+    sort under the given classes, after checking its output."""
+    import os
+    import torch
+    path = os.path.join(tmpdir, "seg_candidate.json")
+    with open(path, "w") as f:
+        json.dump(_segment_table(classes), f)
+    api.load_tuning(path)
+    ws = torch.empty(api.batched_workspace_bytes(off.numel() - 1, n, True), dtype=torch.uint8, device=keys0.device)
+    slots = [(keys0.clone(), vals0.clone()) for _ in range(reps + 1)]
+    api.sort_batched_ex(slots[0][0], slots[0][1], off, n, workspace=ws)
+    torch.cuda.synchronize()
+    if check is not None and not (torch.equal(slots[0][0], check[0]) and torch.equal(slots[0][1], check[1])):
+        raise RuntimeError(f"classes {classes} sorted incorrectly")
+    api.profile_start(64 * reps + 64)
+    for k, v in slots[1:]:
+        api.sort_batched_ex(k, v, off, n, workspace=ws)
+    torch.cuda.synchronize()
+    calls, cur = [], None
+    for kind, ms in api.profile_stop(64 * reps + 64):
+        if kind == 0:
+            cur = [0.0]
+            calls.append(cur)
+        elif cur is not None:
+            cur[0] += ms
+    times = sorted(c[0] for c in calls)
+    return times[len(times) // 2], (slots[0][0], slots[0][1])
+
+
+def tune_segments(reps, log=print):
+    """Whole-in-LDS size classes of the segmented sort; returns (entries, report)."""
+    import tempfile
+    import numpy as np
+    import torch
+    from . import inputs
+    rng = np.random.default_rng(1234)
+    report = []
+    with tempfile.TemporaryDirectory() as tmpdir:
+        for k in SEG_RANGES:
+            lo, hi = (1 << (k - 1)) + 1, 1 << k
+            count = max(1, SEG_BATCH_ITEMS // ((lo + hi) // 2))
+            sizes = rng.integers(lo, hi + 1, size=count)
+            off_h = np.zeros(count + 1, dtype=np.uint32)
+            off_h[1:] = np.cumsum(sizes)
+            n = int(off_h[-1])
+            keys0 = torch.from_numpy(inputs.uniform_keys(n, 800 + k).view(np.int32)).cuda()
+            vals0 = torch.arange(n, dtype=torch.int32, device="cuda")
+            off = torch.from_numpy(off_h.view(np.int32)).cuda()
+            api.load_tuning(None)  # the reference output: built-in classes (parity-tested)
+            ref = keys0.clone(), vals0.clone()
+            api.sort_pairs_batched(ref[0], ref[1], off, n)
+            torch.cuda.synchronize()
+            times = {}
+            for b, i in SEG_SHAPES:
+                if b * i < hi:
+                    continue
+                t, _ = _time_batched(keys0, vals0, off, n, [(hi, b, i)], reps, ref, tmpdir)
+                times[(b, i)] = t
+                log(f"  segments ({lo}..{hi}] x{count}: {b}x{i} {t:.4f} ms")
+            # one class that ends below the range: every segment of it is tiled
+            t, _ = _time_batched(keys0, vals0, off, n, [(lo - 1, 1024, 16)], reps, ref, tmpdir)
+            times["tiled"] = t
+            log(f"  segments ({lo}..{hi}] x{count}: tiled {t:.4f} ms")
+            best = min(times, key=times.get)
+            report.append({"op": "segments", "range": [lo, hi], "segments": count, "items": n,
+                           "best": list(best) if best != "tiled" else "tiled",
+                           "ms": {("x".join(map(str, c)) if c != "tiled" else c): round(v, 4)
+                                  for c, v in times.items()}})
+            del keys0, vals0, off, ref
+            torch.cuda.empty_cache()
+    api.load_tuning(None)
+    entries = segment_entries(report)
+    # the split must also pay off on a mix of sizes: the batched workload
+    # (log-uniform sizes) under the split and under the built-in classes
+    sizes = inputs.batched_sizes()
+    off_h = np.zeros(len(sizes) + 1, dtype=np.uint32)
+    off_h[1:] = np.cumsum(sizes)
+    n = int(off_h[-1])
+    keys0 = torch.from_numpy(inputs.uniform_keys(n, inputs.SEED_BATCHED).view(np.int32)).cuda()
+    vals0 = torch.arange(n, dtype=torch.int32, device="cuda")
+    off = torch.from_numpy(off_h.view(np.int32)).cuda()
+    ref = keys0.clone(), vals0.clone()
+    api.sort_pairs_batched(ref[0], ref[1], off, n)
+    torch.cuda.synchronize()
+    split = [(e["max_n"], e["block"], e["ipt"]) for e in entries]
+    builtin = [(2048, 256, 8), (8192, 512, 16), (16384, 1024, 16)]
+    with tempfile.TemporaryDirectory() as tmpdir:
+        t_split, _ = _time_batched(keys0, vals0, off, n, split, max(reps, 9), ref, tmpdir)
+        t_builtin, _ = _time_batched(keys0, vals0, off, n, builtin, max(reps, 9), ref, tmpdir)
+    api.load_tuning(None)
+    chosen = "split" if t_split <= t_builtin else "builtin"
+    log(f"  batched workload: split {t_split:.4f} ms, built-in {t_builtin:.4f} ms -> {chosen}")
+    report.append({"op": "segments_workload", "segments": len(sizes), "items": n,
+                   "split": [list(c) for c in split], "split_ms": round(t_split, 4),
+                   "builtin_ms": round(t_builtin, 4), "chosen": chosen})
+    if chosen == "builtin":
+        entries = [{"op": "segments", "min_n": lo + 1, "max_n": m, "digit_bits": [8, 8, 8, 8], "block": b,
+                    "ipt": i, "flags": 0} for lo, (m, b, i) in zip([0, 2048, 8192], builtin)]
+    return entries, report
+
+
+def segment_entries(report):
+    """Size classes from the per-range measurements of tune_segments.
+
+    The ranges are split, from the smallest up, into at most four
+    contiguous classes, each sorted by one whole-in-LDS shape that holds its
+    largest range, with every range above the last class left to the tiled
+    path.  Among all such splits (by dynamic programming over the ranges)
+    the one with the least total time per segment wins; per-segment times
+    (a range's time over its segment count) weigh the ranges as a
+    log-uniform size mix does.
+    """
+    rows = sorted((r for r in report if r["op"] == "segments"), key=lambda r: r["range"][1])
+    if not rows:
+        return []
+    per_seg = [{c: t / r["segments"] for c, t in r["ms"].items()} for r in rows]
+    shapes = sorted({c for r in rows for c in r["ms"] if c != "tiled"},
+                    key=lambda c: [int(x) for x in c.split("x")])
+    cap = {c: int(c.split("x")[0]) * int(c.split("x")[1]) for c in shapes}
+    R = len(rows)
+    tiled_tail = [0.0] * (R + 1)  # ranges i.. left to the tiled path
+    for i in range(R - 1, -1, -1):
+        tiled_tail[i] = tiled_tail[i + 1] + per_seg[i]["tiled"]
+
+    def span(i, j):  # ranges i..j as one class: its best shape and cost
+        best = None
+        for c in shapes:
+            if cap[c] < rows[j]["range"][1] or any(c not in per_seg[q] for q in range(i, j + 1)):
+                continue
+            cost = sum(per_seg[q][c] for q in range(i, j + 1))
+            if best is None or cost < best[0]:
+                best = (cost, c)
+        return best
+
+    # best[k][j]: least cost of ranges 0..j-1 split into k classes
+    INF = float("inf")
+    best = [[(INF, None)] * (R + 1) for _ in range(5)]
+    best[0][0] = (0.0, None)
+    for k in range(1, 5):
+        for j in range(1, R + 1):
+            for i in range(j):
+                prev = best[k - 1][i][0]
+                sp = span(i, j - 1)
+                if prev == INF or sp is None:
+                    continue
+                if prev + sp[0] < best[k][j][0]:
+                    best[k][j] = (prev + sp[0], (i, sp[1]))
+    choice = None
+    for k in range(1, 5):
+        for j in range(1, R + 1):
+            total = best[k][j][0] + tiled_tail[j]
+            if choice is None or total < choice[0]:
+                choice = (total, k, j)
+    classes = []
+    _, k, j = choice
+    while k > 0:
+        i, c = best[k][j][1]
+        classes.append((rows[j - 1]["range"][1], c))
+        k, j = k - 1, i
+    classes.reverse()
+    entries, prev = [], 0
+    for max_n, c in classes:
+        b, i = (int(x) for x in c.split("x"))
+        entries.append({"op": "segments", "min_n": prev + 1, "max_n": max_n, "digit_bits": [8, 8, 8, 8],
+                        "block": b, "ipt": i, "flags": 0})
+        prev = max_n
+    return entries
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--sizes", default=",".join(str(int(math.log2(s))) for s in SIZES),
                     help="comma list of log2 sizes")
+    ap.add_argument("--ops", default="keys,pairs,segments",
+                    help="what to tune; the --out table's other entries are kept")
     args = ap.parse_args(argv)
+    import os
     import torch
     if not torch.cuda.is_available():
         print("autotune: no GPU visible", file=sys.stderr)
         return 1
+    ops = set(args.ops.split(","))
+    old = {"entries": [], "measurements": []}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
     sizes = [1 << int(x) for x in args.sizes.split(",")]
     api.load_tuning(None)  # measure every candidate from the built-in defaults
-    entries, report = tune(sizes, args.reps, log=lambda m: print(m, flush=True))
+    log = lambda m: print(m, flush=True)
+    single_ops = ops & {"keys", "pairs"}
+    if single_ops:
+        entries, report = tune(sizes, args.reps, log=log)
+        entries = [e for e in entries if e["op"] in single_ops]
+        report = [r for r in report if r["op"] in single_ops]
+    else:
+        entries, report = [], []
+    if "segments" in ops:
+        seg_entries, seg_report = tune_segments(args.reps, log=log)
+        entries += seg_entries
+        report += seg_report
+    tuned = {e["op"] for e in entries} | ops
+    entries = [e for e in old.get("entries", []) if e["op"] not in tuned] + entries
+    report = [r for r in old.get("measurements", []) if r.get("op") not in tuned] + report
     table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0),
              "cus": torch.cuda.get_device_properties(0).multi_processor_count,
              "library": api.version(), "entries": entries, "measurements": report}

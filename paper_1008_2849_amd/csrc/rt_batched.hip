@@ -13,11 +13,47 @@ namespace rt {
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+SegClassLimits SegClassTable::limits() const {
+    SegClassLimits l{};
+    l.count = count;
+    for (uint32_t c = 0; c < count; ++c) l.max_n[c] = cls[c].max_n;
+    return l;
+}
+
+bool seg_small_shape_supported(int block, int ipt) {
+#define RT_SEG_SHAPE_CASE(BLK, I) \
+    if (block == BLK && ipt == I) return true;
+    RT_FOR_EACH_SEG_SMALL_SHAPE(RT_SEG_SHAPE_CASE)
+#undef RT_SEG_SHAPE_CASE
+    return false;
+}
+
+void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStream_t stream, const SegDesc *descs,
+                      const uint32_t *list, const SegHeader *h, int which, int passes, int to_temp) {
+    // enough blocks to fill the CUs: more per CU for smaller shapes (LDS)
+    const uint32_t cus = static_cast<uint32_t>(device_cu_count());
+    const uint32_t per_cu = std::max<uint32_t>(1u, kSegLdsMax / static_cast<uint32_t>(c.block * c.ipt));
+    const uint32_t grid = std::max<uint32_t>(1u, std::min<uint32_t>(max_listed, cus * per_cu));
+#define RT_SEG_SHAPE_LAUNCH(BLK, I)                                                                              \
+    if (c.block == BLK && c.ipt == I) {                                                                          \
+        if (vals)                                                                                                \
+            hipLaunchKernelGGL((k_seg_small<BLK, I, true>), dim3(grid), dim3(BLK), 0, stream, descs, list, h,    \
+                               which, passes, to_temp);                                                          \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_seg_small<BLK, I, false>), dim3(grid), dim3(BLK), 0, stream, descs, list, h,   \
+                               which, passes, to_temp);                                                          \
+        return;                                                                                                  \
+    }
+    RT_FOR_EACH_SEG_SMALL_SHAPE(RT_SEG_SHAPE_LAUNCH)
+#undef RT_SEG_SHAPE_LAUNCH
+}
+
 SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps) {
     SegLayout L{};
     L.num_segments = num_segments;
     L.capacity = capacity;
-    const size_t large_cap = std::min<size_t>(num_segments, capacity / (kSegClassMax[kSegClasses - 1] + 1));
+    L.classes = seg_class_table();
+    const size_t large_cap = std::min<size_t>(num_segments, capacity / (L.classes.lds_max() + 1));
     L.large_capacity = static_cast<uint32_t>(large_cap);
     L.max_tiles = static_cast<uint32_t>((capacity + kSegTile - 1) / kSegTile + large_cap);
     L.wide_status = capacity >= (static_cast<size_t>(1) << 30);
@@ -25,7 +61,7 @@ SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_valu
     size_t off = 0;
     L.header = off;     off += align256(sizeof(SegHeader));
     L.descs = off;      off += align256(sizeof(SegDesc) * num_segments);
-    L.lists = off;      off += align256(sizeof(uint32_t) * (kSegClasses + 1) * static_cast<size_t>(num_segments));
+    L.lists = off;      off += align256(sizeof(uint32_t) * (kSegMaxClasses + 1) * static_cast<size_t>(num_segments));
     L.first_tile = off; off += align256(sizeof(uint32_t) * (large_cap + 1));
     L.tile_seg = off;   off += align256(sizeof(uint32_t) * L.max_tiles);
     L.hist = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
@@ -68,12 +104,10 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
                        large_list, P.header, P.hist, P.base);
     prof_mark(stream, RT_KIND_PLAN);
     // whole-in-LDS classes
-    hipLaunchKernelGGL((k_seg_small<256, 8, VALS>), dim3(cap_grid(list_stride, cus * 8)), dim3(256), 0, stream,
-                       P.descs, P.lists, P.header, 0, passes, to_temp);
-    hipLaunchKernelGGL((k_seg_small<512, 16, VALS>), dim3(cap_grid(list_stride, cus * 2)), dim3(512), 0, stream,
-                       P.descs, P.lists + list_stride, P.header, 1, passes, to_temp);
-    hipLaunchKernelGGL((k_seg_small<1024, 16, VALS>), dim3(cap_grid(list_stride, cus)), dim3(1024), 0, stream,
-                       P.descs, P.lists + 2 * static_cast<size_t>(list_stride), P.header, 2, passes, to_temp);
+    for (uint32_t c = 0; c < L.classes.count; ++c)
+        launch_seg_small(L.classes.cls[c], VALS, list_stride, stream, P.descs,
+                         P.lists + static_cast<size_t>(c) * list_stride, P.header, static_cast<int>(c), passes,
+                         to_temp);
     prof_mark(stream, RT_KIND_SEG_SMALL);
     for (int p = 0; p < passes; ++p) {
         S *status = reinterpret_cast<S *>(reinterpret_cast<char *>(P.status) + p * L.status_pass);
@@ -117,7 +151,7 @@ void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
     prof_mark(stream, RT_KIND_FILL);
     hipLaunchKernelGGL(k_seg_classify, dim3((num_segments + 255) / 256), dim3(256), 0, stream, offsets,
                        num_segments, keys, vals, tk, vals_on ? tv : nullptr, L.capacity, L.large_capacity,
-                       to_temp, P.descs, P.lists, P.header);
+                       to_temp, L.classes.limits(), P.descs, P.lists, P.header);
     if (L.wide_status) {
         if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, stream);
         else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, stream);

@@ -61,6 +61,44 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
                  bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream,
                  uint32_t pass_kind = RT_KIND_PASS);
 
+// Whole-in-LDS kernel shapes (threads, items per thread) compiled for the
+// segmented sort; a shape holds segments of up to threads x items.
+#define RT_FOR_EACH_SEG_SMALL_SHAPE(X) \
+    X(64, 4)                           \
+    X(64, 8)                           \
+    X(128, 4)                          \
+    X(128, 8)                          \
+    X(256, 4)                          \
+    X(256, 8)                          \
+    X(512, 4)                          \
+    X(512, 8)                          \
+    X(256, 16)                         \
+    X(512, 16)                         \
+    X(1024, 8)                         \
+    X(1024, 16)
+
+// The whole-in-LDS size classes of the segmented sort: class c holds the
+// segments of more than cls[c - 1].max_n and at most cls[c].max_n items and
+// sorts each with one block of the given shape.  Built in: up to 2048 items
+// with 256x8, up to 8192 with 512x16, up to 16384 with 1024x16; a tuning
+// table's "segments" entries replace it.
+struct SegClass {
+    uint32_t max_n;
+    int block, ipt;
+};
+struct SegClassTable {
+    uint32_t count;
+    SegClass cls[kSegMaxClasses];
+    SegClassLimits limits() const;
+    uint32_t lds_max() const { return count ? cls[count - 1].max_n : 0u; }
+};
+SegClassTable seg_class_table();
+bool seg_small_shape_supported(int block, int ipt);
+// Launches the whole-in-LDS kernel of class `which` over its list.
+void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStream_t stream,
+                      const SegDesc *descs, const uint32_t *list, const SegHeader *h, int which, int passes,
+                      int to_temp);
+
 // Workspace of a segmented sort (byte offsets) and its device pointers.
 struct SegLayout {
     uint32_t num_segments;
@@ -68,6 +106,7 @@ struct SegLayout {
     uint32_t large_capacity;  // most segments the tiled path can hold
     uint32_t max_tiles;
     bool wide_status;
+    SegClassTable classes;    // size classes the layout was made for
     size_t header, descs, lists, first_tile, tile_seg, hist, base, status, status_pass, tk, tv;
     size_t total;
 };
@@ -87,7 +126,8 @@ struct SegPointers {
 };
 
 // own_temps: the workspace holds the temporaries (capacity items each);
-// otherwise the caller supplies them.
+// otherwise the caller supplies them.  The layout takes the current size
+// classes, and a call uses those of its layout.
 SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps);
 SegPointers seg_pointers(char *ws, const SegLayout &L);
 // Sorts segment s = [offsets[s], offsets[s+1]) of keys/vals on digits

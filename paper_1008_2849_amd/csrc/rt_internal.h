@@ -56,11 +56,18 @@ constexpr int kSegBits = 8;
 constexpr int kSegPasses = 4;
 constexpr int kSegRadix = 1 << kSegBits;
 constexpr int kSegTile = 1024 * 16;  // items per tile of the pass kernels
-constexpr int kSegClasses = 3;       // whole-in-LDS size classes
-// largest segment of each whole-in-LDS class (block threads x items per thread)
-constexpr uint32_t kSegClassMax[kSegClasses] = {256 * 8, 512 * 16, 1024 * 16};
-constexpr int kSegLarge = kSegClasses;  // list index of the tiled segments
+constexpr int kSegMaxClasses = 4;    // whole-in-LDS size classes at most
+constexpr uint32_t kSegLdsMax = 1024 * 16;  // largest segment one block sorts in LDS
+constexpr int kSegLarge = kSegMaxClasses;   // list index of the tiled segments
 constexpr uint32_t kSegErrBounds = 2u;  // a segment reached past the workspace
+
+// Size limits of the whole-in-LDS classes of a call: class c takes the
+// segments of more than max_n[c - 1] and at most max_n[c] items (increasing,
+// at most kSegLdsMax); larger segments are tiled.
+struct SegClassLimits {
+    uint32_t count;
+    uint32_t max_n[kSegMaxClasses];
+};
 
 // One segment.  The sorted result ends in k/v (the segment's own arrays);
 // tk/tv are temporaries of n elements.  v and tv are NULL for keys only.
@@ -75,11 +82,11 @@ struct SegDesc {
 
 // Device-side counters of a segmented sort.
 struct SegHeader {
-    uint32_t count[kSegClasses + 1];  // list lengths: whole-in-LDS classes, tiled
-    uint32_t total_tiles;             // tiles of the tiled list
+    uint32_t count[kSegMaxClasses + 1];  // list lengths: whole-in-LDS classes, tiled
+    uint32_t total_tiles;                // tiles of the tiled list
     uint32_t tile_ctr[kSegPasses + 1];
     uint32_t error;
-    uint32_t pad[5];
+    uint32_t pad[4];
 };
 
 }  // namespace rt

@@ -38,8 +38,8 @@ static __global__ __launch_bounds__(64) void k_seg_reset(SegHeader *__restrict__
 static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ off, uint32_t num_segments,
                                                       uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
                                                       size_t capacity, uint32_t large_capacity, int to_temp,
-                                                      SegDesc *__restrict__ descs, uint32_t *__restrict__ lists,
-                                                      SegHeader *__restrict__ h) {
+                                                      SegClassLimits classes, SegDesc *__restrict__ descs,
+                                                      uint32_t *__restrict__ lists, SegHeader *__restrict__ h) {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
     if (s >= num_segments) return;
     const uint32_t o0 = off[0];
@@ -67,8 +67,8 @@ static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__r
     d.pad = 0;
     int c = kSegLarge;
 #pragma unroll
-    for (int i = kSegClasses - 1; i >= 0; --i)
-        if (n <= kSegClassMax[i]) c = i;
+    for (int i = kSegMaxClasses - 1; i >= 0; --i)
+        if (i < static_cast<int>(classes.count) && n <= classes.max_n[i]) c = i;
     const uint32_t at = atomicAdd(&h->count[c], 1u);
     if (c == kSegLarge) {
         if (at >= large_capacity) {  // only if capacity does not bound the offsets

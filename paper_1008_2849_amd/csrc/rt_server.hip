@@ -117,7 +117,8 @@ struct Request {
     double t_submit = 0, t_done = 0;
 };
 
-bool is_small(const Request &r) { return r.n <= kSegClassMax[kSegClasses - 1]; }
+// Sorted whole in LDS (in its first step) rather than tiled.
+bool is_small(const Request &r, uint32_t lds_max) { return r.n <= lds_max; }
 
 // One generated request of a step: its arrays and stream parameters.
 struct GenDesc {
@@ -139,21 +140,23 @@ struct Meta {
     uint32_t max_tiles;
 };
 
-Meta make_meta(uint32_t max_active, size_t arena_bytes) {
+Meta make_meta(uint32_t max_active, size_t arena_bytes, uint32_t lds_max) {
     Meta m{};
     auto a = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-    // A tiled request (n > 16K items) holds at least 4n bytes of arena and
-    // has ceil(n / 16K) <= n / 16K + 1 <= 2n / 16K tiles, so a step has at
-    // most min(arena / 32K, arena / 64K + max_active) tiles.
-    const size_t by_size = arena_bytes / (sizeof(uint32_t) * kSegTile / 2);
+    // A tiled request (n > L = lds_max items) holds at least 4n bytes of
+    // arena and has ceil(n / 16K) <= n / 16K + 1 < n / 16K + n / L tiles, so
+    // a step has at most min(arena / 64K + arena / 4L, arena / 64K +
+    // max_active) tiles.
+    const size_t by_size = arena_bytes / (sizeof(uint32_t) * kSegTile) +
+                           arena_bytes / (sizeof(uint32_t) * (static_cast<size_t>(lds_max) + 1));
     const size_t by_count = arena_bytes / (sizeof(uint32_t) * kSegTile) + max_active;
     m.max_tiles = static_cast<uint32_t>(std::min(by_size, by_count) + 1);
     size_t off = 0;
     m.hdr_pass = off;   off += a(sizeof(SegHeader));
     m.hdr_hist = off;   off += a(sizeof(SegHeader));
     m.descs = off;      off += a(sizeof(SegDesc) * max_active);
-    m.lists_pass = off; off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
-    m.list_hist = off;  off += a(sizeof(uint32_t) * (kSegClasses + 1) * max_active);
+    m.lists_pass = off; off += a(sizeof(uint32_t) * (kSegMaxClasses + 1) * max_active);
+    m.list_hist = off;  off += a(sizeof(uint32_t) * (kSegMaxClasses + 1) * max_active);
     m.block_bytes = off;
     m.gen = off;        off += a(sizeof(GenDesc) * max_active);
     m.first_pass = off; off += a(sizeof(uint32_t) * (max_active + 1));
@@ -223,6 +226,7 @@ struct rt_server {
     Arena alloc;
     size_t used = 0, peak = 0;
     uint32_t max_active = 0;
+    rt::SegClassTable classes{};  // whole-in-LDS size classes, fixed at creation
     Meta meta{};
     char *dmeta = nullptr;
     StepSlot ring[kRing];
@@ -250,10 +254,10 @@ struct rt_server {
 
 namespace {
 
-size_t footprint(const Request &r) {
+size_t footprint(const rt_server *s, const Request &r) {
     const size_t arr = round_up(r.n * sizeof(uint32_t));
     const size_t per = r.with_values ? 2 : 1;
-    return (r.generated ? per * arr : 0) + (is_small(r) ? 0 : per * arr);
+    return (r.generated ? per * arr : 0) + (is_small(r, s->classes.lds_max()) ? 0 : per * arr);
 }
 
 size_t slot_bytes(const Meta &m, uint32_t max_active) {
@@ -270,7 +274,7 @@ std::vector<Request *> admit(rt_server *s) {
         const size_t per = r->with_values ? 2 : 1;
         size_t data_off = 0, tmp_off = 0;
         const size_t data_bytes = r->generated ? per * arr : 0;
-        const size_t tmp_bytes = is_small(*r) ? 0 : per * arr;
+        const size_t tmp_bytes = is_small(*r, s->classes.lds_max()) ? 0 : per * arr;
         if (data_bytes && !s->alloc.alloc(data_bytes, &data_off)) break;
         if (tmp_bytes && !s->alloc.alloc(tmp_bytes, &tmp_off)) {
             if (data_bytes) s->alloc.release(data_off, data_bytes);
@@ -310,7 +314,7 @@ std::vector<Request *> admit(rt_server *s) {
 // stream, so reusing them is ordered behind its kernels).
 struct StepPlan {
     size_t tiles = 0;
-    uint32_t fresh_tiled = 0, tiled = 0, small[kSegClasses] = {0, 0, 0}, gen = 0, gen_chunks = 0;
+    uint32_t fresh_tiled = 0, tiled = 0, small[kSegMaxClasses] = {0, 0, 0, 0}, gen = 0, gen_chunks = 0;
     bool vals = false;
 };
 
@@ -356,10 +360,10 @@ StepPlan build_step(rt_server *s, StepSlot &slot) {
         bool finished;
         if (r->n < 2) {
             finished = true;
-        } else if (is_small(*r)) {
-            int c = kSegClasses - 1;
-            for (int q = kSegClasses - 1; q >= 0; --q)
-                if (r->n <= kSegClassMax[q]) c = q;
+        } else if (is_small(*r, s->classes.lds_max())) {
+            int c = static_cast<int>(s->classes.count) - 1;
+            for (int q = c; q >= 0; --q)
+                if (r->n <= s->classes.cls[q].max_n) c = q;
             lists[static_cast<size_t>(c) * stride + hp->count[c]++] = static_cast<uint32_t>(i);
             ++P.small[c];
             finished = true;  // small requests are sorted whole in their first step
@@ -456,17 +460,10 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
                                ctr, err);
     }
-    const uint32_t n0 = P.small[0], n1 = P.small[1], n2 = P.small[2];
-    const uint32_t *l1 = d_lists + stride, *l2 = d_lists + 2 * static_cast<size_t>(stride);
-    if (P.vals) {
-        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, true>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0, kSegPasses, 0);
-        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, true>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1, kSegPasses, 0);
-        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, true>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2, kSegPasses, 0);
-    } else {
-        if (n0) hipLaunchKernelGGL((k_seg_small<256, 8, false>), dim3(grid(n0, cus * 8)), dim3(256), 0, st, d_descs, d_lists, d_hp, 0, kSegPasses, 0);
-        if (n1) hipLaunchKernelGGL((k_seg_small<512, 16, false>), dim3(grid(n1, cus * 2)), dim3(512), 0, st, d_descs, l1, d_hp, 1, kSegPasses, 0);
-        if (n2) hipLaunchKernelGGL((k_seg_small<1024, 16, false>), dim3(grid(n2, cus)), dim3(1024), 0, st, d_descs, l2, d_hp, 2, kSegPasses, 0);
-    }
+    for (uint32_t c = 0; c < s->classes.count; ++c)  // small requests, whole in LDS
+        if (P.small[c])
+            launch_seg_small(s->classes.cls[c], P.vals, P.small[c], st, d_descs,
+                             d_lists + static_cast<size_t>(c) * stride, d_hp, static_cast<int>(c), kSegPasses, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: launch: %s", hipGetErrorString(e));
     // the error words of both headers come back with the step
@@ -607,7 +604,8 @@ extern "C" rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_acti
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_server_create: %s", hipGetErrorString(e));
     s->arena_bytes = round_up(hbm_budget_bytes);
     s->max_active = max_active;
-    s->meta = make_meta(max_active, s->arena_bytes);
+    s->classes = rt::seg_class_table();
+    s->meta = make_meta(max_active, s->arena_bytes, s->classes.lds_max());
     e = hipMalloc(reinterpret_cast<void **>(&s->arena), s->arena_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -652,8 +650,8 @@ static rt_status check_request_size(rt_server *s, size_t n, bool generated, bool
     probe.n = n;
     probe.generated = generated;
     probe.with_values = with_values;
-    if (footprint(probe) > s->arena_bytes)
-        return set_error(RT_ERR_BUDGET, "%s: %zu bytes needed, the budget is %zu", what, footprint(probe),
+    if (footprint(s, probe) > s->arena_bytes)
+        return set_error(RT_ERR_BUDGET, "%s: %zu bytes needed, the budget is %zu", what, footprint(s, probe),
                          s->arena_bytes);
     return RT_OK;
 }

@@ -5,7 +5,13 @@
 //   {"arch": "gfx950", "entries": [
 //      {"op": "keys"|"pairs"|"segments", "min_n": N0, "max_n": N1,
 //       "digit_bits": [w0, w1, ...], "block": B, "ipt": I, "flags": F}, ...]}
-// An entry applies to n in [min_n, max_n]; the first matching entry wins.
+// A "keys" or "pairs" entry applies to single-array sorts of n in
+// [min_n, max_n]; the first matching entry wins.  The "segments" entries, in
+// increasing max_n, are the whole-in-LDS size classes of the segmented sort
+// (batched calls, the MSD-first sort's buckets, small server requests): each
+// sorts the segments of up to max_n items (and more than the previous
+// entry's) in one block of B threads x I items, with 8-bit digits; larger
+// segments are tiled.  Without "segments" entries the built-in classes hold.
 #include <cctype>
 #include <cstdio>
 #include <cstdlib>
@@ -127,6 +133,17 @@ struct Entry {
 
 std::mutex g_mu;
 std::vector<Entry> g_table;
+bool g_seg_tuned = false;
+SegClassTable g_seg;
+
+SegClassTable builtin_seg_classes() {
+    SegClassTable t{};
+    t.count = 3;
+    t.cls[0] = SegClass{256 * 8, 256, 8};
+    t.cls[1] = SegClass{512 * 16, 512, 16};
+    t.cls[2] = SegClass{1024 * 16, 1024, 16};
+    return t;
+}
 
 void builtin(size_t n, int op, rt_config *out) {
     (void)n;
@@ -158,6 +175,11 @@ void tuned_config_op(size_t n, int op, rt_config *out) {
 
 void tuned_config(size_t n, int with_values, rt_config *out) { tuned_config_op(n, with_values ? 1 : 0, out); }
 
+SegClassTable seg_class_table() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_seg_tuned ? g_seg : builtin_seg_classes();
+}
+
 }  // namespace rt
 
 using namespace rt;
@@ -166,6 +188,7 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
     if (json_path == nullptr) {
         std::lock_guard<std::mutex> lk(g_mu);
         g_table.clear();
+        g_seg_tuned = false;
         return RT_OK;
     }
     FILE *f = fopen(json_path, "rb");
@@ -184,6 +207,7 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
     if (!entries || entries->kind != JValue::Array)
         return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: no \"entries\" array");
     std::vector<Entry> table;
+    SegClassTable seg{};
     for (size_t i = 0; i < entries->arr.size(); ++i) {
         const JValue &e = entries->arr[i];
         const JValue *op = e.get("op"), *lo = e.get("min_n"), *hi = e.get("max_n"), *bits = e.get("digit_bits"),
@@ -209,11 +233,44 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
         if (en.op != 2) {
             if (resolve_config(&en.cfg, 1024, en.op, &r) != RT_OK)
                 return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: %s", i, last_error());
+            table.push_back(en);
+            continue;
         }
-        table.push_back(en);
+        // a whole-in-LDS class of the segmented sort
+        const int blk = static_cast<int>(en.cfg.block_threads), ip = static_cast<int>(en.cfg.items_per_thread);
+        bool eight = en.cfg.num_passes == static_cast<uint32_t>(kSegPasses);
+        for (uint32_t p = 0; p < en.cfg.num_passes; ++p) eight = eight && en.cfg.digit_bits[p] == kSegBits;
+        if (!eight)
+            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: segments use four 8-bit digits", i);
+        if (!seg_small_shape_supported(blk, ip))
+            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: no whole-in-LDS kernel %dx%d", i, blk,
+                             ip);
+        if (seg.count == static_cast<uint32_t>(kSegMaxClasses))
+            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: more than %d segment classes", kSegMaxClasses);
+        const double prev = seg.count ? seg.cls[seg.count - 1].max_n : 0.0;
+        if (en.max_n <= prev || en.max_n > static_cast<double>(blk) * ip || en.max_n > kSegLdsMax)
+            return set_error(RT_ERR_INVALID_ARG,
+                             "rt_load_tuning: entry %zu: segment class limit %.0f must rise, fit %dx%d and be at "
+                             "most %u",
+                             i, en.max_n, blk, ip, kSegLdsMax);
+        seg.cls[seg.count++] = SegClass{static_cast<uint32_t>(en.max_n), blk, ip};
     }
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.swap(table);
+    g_seg_tuned = seg.count > 0;
+    g_seg = seg;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_segment_classes(uint32_t *count, uint32_t *max_n, uint32_t *block, uint32_t *ipt) {
+    if (count == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_segment_classes: count is NULL");
+    const SegClassTable t = seg_class_table();
+    *count = t.count;
+    for (uint32_t c = 0; c < t.count; ++c) {
+        if (max_n) max_n[c] = t.cls[c].max_n;
+        if (block) block[c] = static_cast<uint32_t>(t.cls[c].block);
+        if (ipt) ipt[c] = static_cast<uint32_t>(t.cls[c].ipt);
+    }
     return RT_OK;
 }
 

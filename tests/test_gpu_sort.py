@@ -331,4 +331,4 @@ def test_keys_1m_workload_tuned():
         k, _ = inputs.make_workload(w)
         assert_same(gpu_sort(k), oracle.lsd_sort(k), "keys_1m")
     finally:
-        rts.load_tuning(None)
+        rts.load_default_tuning()
