@@ -10,7 +10,8 @@ region.  The run prints one JSON line on stdout: whole-sort throughput
 kernel (the counting-sort pass), and the CPU oracle timed on this host.
 Further legs, each reported in the same line and each skippable: the
 transfer-inclusive rate, the MSD-first sort of the same input, the batched
-workload, 64-bit keys and the serving loop.
+workload, 64-bit keys, the paper's Table 1 configurations with and
+without the LDS staging (write-combining), and the serving loop.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -255,6 +256,58 @@ def bench_sort64(rts, inputs, dev, K, W):
             "parity_properties_ok": ok}
 
 
+def bench_write_combining(rts, inputs, dev, K, W):
+    """The paper's Table 1 configurations on this GPU: N = 64 Mi uniform
+    keys, without and with 32-bit values, sorted with the LDS staging by
+    digit (the GPU form of write-combining) and with every item scattered
+    straight from registers (RT_FLAG_DIRECT_SCATTER, the "VM only" row's
+    counterpart).  Same tile shape for both; outputs must agree."""
+    import numpy as np
+    import torch
+    from paper_1008_2849_amd._lib import RT_FLAG_DIRECT_SCATTER, RT_FLAG_NT_STORES, RT_KIND_PASS
+    out = {}
+    for name in ("keys_64m_uniform", "pairs_64m_uniform"):
+        w = inputs.WORKLOADS[name]
+        k_h, v_h = inputs.make_workload(w)
+        k0 = torch.from_numpy(k_h.view(np.int32)).to(dev)
+        v0 = torch.from_numpy(v_h.view(np.int32)).to(dev) if v_h is not None else None
+        tuned = rts.tuned_config(w.n, w.with_values)
+        row = {}
+        results = {}
+        for label, flags in (("staged", tuned.flags), ("direct", (tuned.flags & ~RT_FLAG_NT_STORES)
+                                                        | RT_FLAG_DIRECT_SCATTER)):
+            cfg = rts.Config(tuned.digit_bits, tuned.block_threads, tuned.items_per_thread, flags)
+            slots = [(k0.clone(), None if v0 is None else v0.clone()) for _ in range(K + W)]
+            ws = torch.empty(rts.workspace_bytes(w.n, w.with_values, cfg), dtype=torch.uint8, device=dev)
+            for i in range(W):
+                rts.sort_ex(slots[i][0], slots[i][1], cfg, ws)
+            torch.cuda.synchronize()
+            rts.profile_start(max_marks=16 * K + 16)
+            t0 = time.perf_counter()
+            for i in range(W, W + K):
+                rts.sort_ex(slots[i][0], slots[i][1], cfg, ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            passes = [ms for kind, ms in rts.profile_stop(capacity=16 * K + 16)
+                      if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+            pm = float(np.mean(passes))
+            item = 8 if w.with_values else 4
+            row[label + "_Gkeys/s"] = round(w.n / (wall / K) / 1e9, 3)
+            row[label + "_pass_ms"] = round(pm, 4)
+            row[label + "_pass_GBps"] = round(2 * item * w.n / pm / 1e6, 1)
+            results[label] = slots[W + K - 1]
+            del slots, ws
+        row["staging_speedup"] = round(row["staged_Gkeys/s"] / row["direct_Gkeys/s"], 3)
+        a, b = results["staged"], results["direct"]
+        row["outputs_equal"] = bool(torch.equal(a[0], b[0])) and (a[1] is None or bool(torch.equal(a[1], b[1])))
+        row["config"] = {"digit_bits": list(tuned.digit_bits), "block_threads": tuned.block_threads,
+                         "items_per_thread": tuned.items_per_thread}
+        out[name] = row
+        del results, a, b, k0, v0
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_pcie(rts, dev, keys_h, vals_h, cfg, ref_k, ref_v, reps=3):
     """Transfer-inclusive rate for host-resident data (the paper's GPU+PCIe
     comparison in Section 5): pinned host keys/values -> device, sort,
@@ -485,6 +538,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-msd-first", action="store_true", help="skip the MSD-first leg")
     ap.add_argument("--no-sort64", action="store_true", help="skip the 64-bit-key leg")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip the write-combining leg (the paper's Table 1 configurations)")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
     ap.add_argument("--serve-loads", default="0.5", help="comma list of offered loads (fraction of "
                     "single-array throughput); empty to skip serving")
@@ -650,6 +705,11 @@ def main() -> int:
         sort64 = bench_sort64(rts, inputs, dev, K, W)
         torch.cuda.empty_cache()
         log(f"sort64: {sort64}")
+    table1 = None
+    if not args.no_table1 and args.workload == "pairs_256m_uniform":
+        log("write-combining leg (N = 64 Mi, staged vs direct scatter)")
+        table1 = bench_write_combining(rts, inputs, dev, K, W)
+        log(f"table1: {table1}")
     serving = []
     if (args.serve_loads or args.serve_inflight) and args.workload == "pairs_256m_uniform":
         for load in (float(x) for x in args.serve_loads.split(",") if x):
@@ -692,6 +752,7 @@ def main() -> int:
         "transfer_inclusive": pcie,
         "msd_first": msd_first,
         "sort64": sort64,
+        "write_combining": table1,
         "batched": batched,
         "serving": serving,
         "kernel_source_digest": digest,
@@ -703,6 +764,7 @@ def main() -> int:
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
     ok = ok and (sort64 is None or sort64["parity_properties_ok"])
+    ok = ok and (table1 is None or all(r["outputs_equal"] for r in table1.values()))
     return 0 if ok else 3
 
 

@@ -57,6 +57,12 @@ typedef enum rt_status {
 #define RT_FLAG_NO_SKIP 0x1u   /* run every pass, even when its digit is constant */
 #define RT_FLAG_NT_STORES 0x2u /* scatter with non-temporal stores */
 #define RT_FLAG_VALIDATE 0x4u  /* batched, MSD-first: wait for the sort and report device errors */
+/* Write every item straight from registers to its output slot instead of
+ * staging the tile by digit in LDS first: the counting-sort pass without
+ * write-combining (Section 2's technique switched off, the paper's "VM
+ * only" row of Table 1), for measuring what the staging buys.  Same result;
+ * not combinable with RT_FLAG_NT_STORES. */
+#define RT_FLAG_DIRECT_SCATTER 0x8u
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".

@@ -26,6 +26,7 @@ RT_MAX_PASSES = 8
 RT_MAX_DIGIT_BITS = 11
 RT_FLAG_NO_SKIP = 0x1
 RT_FLAG_NT_STORES = 0x2
+RT_FLAG_DIRECT_SCATTER = 0x8
 RT_FLAG_VALIDATE = 0x4
 
 RT_KIND_FILL = 1

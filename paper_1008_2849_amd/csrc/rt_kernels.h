@@ -400,7 +400,12 @@ __device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status,
 // published as this tile's aggregate -> tile-local digit offsets -> gather
 // keys and values by digit in LDS -> lookback for the global offset of each
 // digit -> write every digit run to consecutive output addresses.
-template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S>
+//
+// STAGE = false drops the gather: every item is written straight from its
+// registers to its output slot, so a wave's stores scatter over the digit
+// runs.  This is the pass without write-combining (the paper's "VM only"
+// counterpart), kept to measure what the staging buys.
+template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                                     const uint32_t *__restrict__ pass_base, S *__restrict__ status,
                                                     uint32_t *__restrict__ tile_counter,
@@ -523,13 +528,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
 
     // ---- gather keys and values by digit in LDS (tile rank = digit start +
     // earlier waves + rank inside the wave)
+    if constexpr (STAGE) {
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
-        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
-        const uint32_t r = wh[d] + rnk[j];
-        s_stage_k[r] = key[j];
-        if constexpr (VALS) s_stage_v[r] = val[j];
+        for (int j = 0; j < IPT; ++j) {
+            uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
+            if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
+            const uint32_t r = wh[d] + rnk[j];
+            s_stage_k[r] = key[j];
+            if constexpr (VALS) s_stage_v[r] = val[j];
+        }
     }
 
     // ---- lookback: the count of each digit in all earlier tiles
@@ -549,14 +556,25 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     // ---- scatter: consecutive LDS slots of one digit go to consecutive
     // output addresses.  The clamp to n - 1 costs one op and keeps a logic
     // error from ever turning into a store outside the array.
+    if constexpr (STAGE) {
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t i = j * BLOCK + tid;
-        const uint32_t k = s_stage_k[i];
-        const uint32_t p = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, width)] + i, n - 1u);
-        if (full || i < valid) {
-            store_g<NT>(gelem<SMALL>(pp.dst_k, p), k);
-            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), s_stage_v[i]);
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = j * BLOCK + tid;
+            const uint32_t k = s_stage_k[i];
+            const uint32_t p = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, width)] + i, n - 1u);
+            if (full || i < valid) {
+                store_g<NT>(gelem<SMALL>(pp.dst_k, p), k);
+                if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), s_stage_v[i]);
+            }
+        }
+    } else {  // each item from its registers: output slot = digit start + tile rank
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            if (!full && wslot0 + j * 64 >= valid) continue;
+            const uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
+            const uint32_t p = min(s_gbase[d] + wh[d] + rnk[j], n - 1u);
+            store_g<NT>(gelem<SMALL>(pp.dst_k, p), key[j]);
+            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), val[j]);
         }
     }
 }

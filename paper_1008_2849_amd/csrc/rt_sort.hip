@@ -132,6 +132,10 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
                              bits_class_of(r.width[p]), r.block, r.ipt);
     r.flags = c.flags;
     r.with_values = with_values != 0;
+    if (r.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER))
+        return set_error(RT_ERR_INVALID_ARG, "unknown flags 0x%x", r.flags);
+    if ((r.flags & RT_FLAG_DIRECT_SCATTER) && (r.flags & RT_FLAG_NT_STORES))
+        return set_error(RT_ERR_UNSUPPORTED, "RT_FLAG_DIRECT_SCATTER with RT_FLAG_NT_STORES is not built");
     *out = r;
     return RT_OK;
 }
@@ -254,32 +258,37 @@ void prof_mark(hipStream_t stream, uint32_t kind) { prof_record(stream, kind); }
 // ---------------------------------------------------------------------------
 
 template <int BITS, int BLOCK, int IPT>
-static void launch_pass_shape(const Layout &L, bool vals, bool nt, hipStream_t stream, const SortPlan *plan,
+static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStream_t stream, const SortPlan *plan,
                               int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr,
                               uint32_t kind) {
     const dim3 grid(L.tiles), block(BLOCK);
     uint32_t *err = ctr + kMaxPasses;
-#define RT_OS(V, NTV, S)                                                                                     \
-    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S>), grid, block, 0, stream, plan, pass, n, base, \
+    const bool nt = (flags & RT_FLAG_NT_STORES) != 0;
+    const bool stage = (flags & RT_FLAG_DIRECT_SCATTER) == 0;
+#define RT_OS(V, NTV, S, STG)                                                                                      \
+    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG>), grid, block, 0, stream, plan, pass, n, base, \
                        static_cast<S *>(status), ctr, err)
-    if (L.wide_status) {
-        if (vals) { if (nt) RT_OS(true, true, uint64_t); else RT_OS(true, false, uint64_t); }
-        else      { if (nt) RT_OS(false, true, uint64_t); else RT_OS(false, false, uint64_t); }
+    if (!stage) {  // resolve_config rules out the non-temporal form here
+        if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, false); else RT_OS(false, false, uint64_t, false); }
+        else               { if (vals) RT_OS(true, false, uint32_t, false); else RT_OS(false, false, uint32_t, false); }
+    } else if (L.wide_status) {
+        if (vals) { if (nt) RT_OS(true, true, uint64_t, true); else RT_OS(true, false, uint64_t, true); }
+        else      { if (nt) RT_OS(false, true, uint64_t, true); else RT_OS(false, false, uint64_t, true); }
     } else {
-        if (vals) { if (nt) RT_OS(true, true, uint32_t); else RT_OS(true, false, uint32_t); }
-        else      { if (nt) RT_OS(false, true, uint32_t); else RT_OS(false, false, uint32_t); }
+        if (vals) { if (nt) RT_OS(true, true, uint32_t, true); else RT_OS(true, false, uint32_t, true); }
+        else      { if (nt) RT_OS(false, true, uint32_t, true); else RT_OS(false, false, uint32_t, true); }
     }
 #undef RT_OS
     prof_mark(stream, kind);
 }
 
-static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, bool nt, hipStream_t stream,
-                        const SortPlan *plan, int pass, uint32_t n, const uint32_t *base, void *status,
-                        uint32_t *ctr, uint32_t kind) {
-#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                  \
-    if (bits_class == B && block == BLK && ipt == I) {                                              \
-        launch_pass_shape<B, BLK, I>(L, vals, nt, stream, plan, pass, n, base, status, ctr, kind); \
-        return;                                                                                     \
+static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, uint32_t flags,
+                        hipStream_t stream, const SortPlan *plan, int pass, uint32_t n, const uint32_t *base,
+                        void *status, uint32_t *ctr, uint32_t kind) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                     \
+    if (bits_class == B && block == BLK && ipt == I) {                                                 \
+        launch_pass_shape<B, BLK, I>(L, vals, flags, stream, plan, pass, n, base, status, ctr, kind); \
+        return;                                                                                        \
     }
     RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
 #undef RT_SHAPE_LAUNCH
@@ -382,9 +391,8 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, stream, a, hist, base, plan, ctr, direct ? 1u : 0u);
     prof_mark(stream, RT_KIND_PLAN);
 
-    const bool nt = (r.flags & RT_FLAG_NT_STORES) != 0;
     for (uint32_t p = 0; p < r.num_passes; ++p)
-        launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, nt, stream, plan,
+        launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, r.flags, stream, plan,
                     static_cast<int>(p), n, base + p * kMaxRadix, status + L.status_pass[p], ctr,
                     pass_kind + p);
 

@@ -39,6 +39,7 @@ SEED_ZIPF16 = 35          # 16 distinct keys, Zipf s = 1.2, 2^26 pairs
 SEED_BATCHED = 4          # 4096 segments
 SEED_SERVING = 5          # serving request stream
 SEED_PAIRS64_256M = 6     # 2^28 uniform 64-bit keys with 32-bit index values
+SEED_TABLE1 = 7           # 2^26 (64 Mi) uniform keys: the paper's own N, keys only and pairs
 
 # Distribution ids shared with the device generator.
 DIST_UNIFORM = 0
@@ -280,6 +281,8 @@ WORKLOADS: Dict[str, Workload] = {
     "pairs_64m_and8": Workload("pairs_64m_and8", 2**26, True, "and", SEED_AND[8], 8),
     "pairs_64m_top_a5": Workload("pairs_64m_top_a5", 2**26, True, "top_byte", SEED_TOP_BYTE, 0xA5),
     "pairs_64m_zipf16": Workload("pairs_64m_zipf16", 2**26, True, "zipf16", SEED_ZIPF16),
+    "keys_64m_uniform": Workload("keys_64m_uniform", 2**26, False, "uniform", SEED_TABLE1),
+    "pairs_64m_uniform": Workload("pairs_64m_uniform", 2**26, True, "uniform", SEED_TABLE1),
     "pairs64_256m_uniform": Workload("pairs64_256m_uniform", 2**28, True, "uniform", SEED_PAIRS64_256M,
                                      key_bits=64),
 }

@@ -77,6 +77,11 @@ def test_config_validation(so):
         c.digit_bits[i] = 8
     c.block_threads, c.items_per_thread = 128, 7
     assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+    c.block_threads, c.items_per_thread = 1024, 16
+    c.flags = _lib.RT_FLAG_DIRECT_SCATTER | _lib.RT_FLAG_NT_STORES  # not built
+    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+    c.flags = 0x100  # unknown
+    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
 
 
 def test_workspace_bytes(so):

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_1008_2849_amd as rts
 from paper_1008_2849_amd import inputs
-from paper_1008_2849_amd.api import Config, FLAG_NO_SKIP, FLAG_NT_STORES
+from paper_1008_2849_amd.api import Config, FLAG_DIRECT_SCATTER, FLAG_NO_SKIP, FLAG_NT_STORES
 from gpu_util import announce, sync, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -124,7 +124,8 @@ def test_configs(widths, shape):
     assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {shape}")
 
 
-@pytest.mark.parametrize("flags", [FLAG_NO_SKIP, FLAG_NT_STORES, FLAG_NO_SKIP | FLAG_NT_STORES])
+@pytest.mark.parametrize("flags", [FLAG_NO_SKIP, FLAG_NT_STORES, FLAG_NO_SKIP | FLAG_NT_STORES,
+                                   FLAG_DIRECT_SCATTER, FLAG_DIRECT_SCATTER | FLAG_NO_SKIP])
 @pytest.mark.parametrize("dist", ["top_a5", "low_byte_only", "all_equal", "and4"])
 def test_flags(flags, dist):
     n = 200_017
@@ -134,6 +135,20 @@ def test_flags(flags, dist):
     cfg = Config((8, 8, 8, 8), 1024, 16, flags)
     assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v), f"flags={flags} {dist}")
     assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k), f"keys flags={flags} {dist}")
+
+
+@pytest.mark.parametrize("widths,shape", [((11, 11, 10), (512, 16)), ((8, 8, 8, 8), (256, 16)),
+                                          ((4,) * 8, (1024, 8))])
+def test_direct_scatter_configs(widths, shape):
+    """The pass without LDS staging gives the same result under other digit
+    widths and tile shapes, with a ragged last tile."""
+    n = 7 * shape[0] * shape[1] + 4321
+    announce(f"direct scatter widths={widths} shape={shape} n={n}")
+    k = inputs.and_keys(n, 2, 17)
+    v = inputs.index_values(n)
+    cfg = Config(widths, shape[0], shape[1], FLAG_DIRECT_SCATTER)
+    assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {shape}")
+    assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k, None, widths), f"keys {widths} {shape}")
 
 
 @pytest.mark.parametrize("skip_pattern", range(16))
