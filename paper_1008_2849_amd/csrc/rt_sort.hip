@@ -153,11 +153,9 @@ Layout make_layout(size_t n, const Resolved &r, bool direct) {
     L.tiles = static_cast<uint32_t>(tiles);
     L.wide_status = n >= (static_cast<size_t>(1) << 30);
     const size_t sw = L.wide_status ? 8 : 4;
+    // the histograms and the lookback words are adjacent: one fill clears both
     size_t off = 0;
     L.hist = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
-    L.ctr = off;     off += align256(sizeof(uint32_t) * (kMaxPasses + 1));  // tile counters, error word
-    L.base = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
-    L.plan = off;    off += align256(sizeof(SortPlan));
     L.status = off;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         L.status_pass[p] = off - L.status;
@@ -165,6 +163,9 @@ Layout make_layout(size_t n, const Resolved &r, bool direct) {
     }
     off = align256(off);
     L.status_bytes = off - L.status;
+    L.ctr = off;     off += align256(sizeof(uint32_t) * (kMaxPasses + 1));  // tile counters, error word
+    L.base = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.plan = off;    off += align256(sizeof(SortPlan));
     L.t1k = L.t1v = L.t2k = L.t2v = 0;
     if (!direct) {
         // A second temporary is needed whenever the executed pass count can
@@ -333,15 +334,21 @@ static void launch_histogram_copies(const uint32_t *keys, uint32_t n, const Hist
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram<kBlock, C>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
     });
-    const uint32_t grid = grid_for(n, kBlock * 8 * 16, static_cast<uint32_t>(device_cu_count()) * 4);
+    // about 8K keys per block (one batch per wave) for small n, at most four
+    // blocks per CU for large n
+    const uint32_t grid = grid_for(n, 8192, static_cast<uint32_t>(device_cu_count()) * 4);
     hipLaunchKernelGGL((k_histogram<kBlock, C>), dim3(grid), dim3(kBlock), lds, stream, keys, n, ha, hist);
 }
 
-void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream) {
+// hist_zeroed: the caller has cleared the counters already.
+void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream,
+                       bool hist_zeroed) {
     const HistArgs ha = hist_args(r);
-    hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
-                       static_cast<size_t>(r.num_passes) * kMaxRadix);
-    prof_mark(stream, RT_KIND_FILL);
+    if (!hist_zeroed) {
+        hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
+                           static_cast<size_t>(r.num_passes) * kMaxRadix);
+        prof_mark(stream, RT_KIND_FILL);
+    }
     switch (hist_copies(ha.total_bins)) {
         case 16: launch_histogram_copies<16>(keys, n, ha, hist, stream); break;
         case 8: launch_histogram_copies<8>(keys, n, ha, hist, stream); break;
@@ -363,11 +370,13 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     char *status = ws + L.status;
 
     prof_begin(stream);
-    // the lookback words of every pass start at zero ("not published")
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(L.status_bytes / 4, 256 * 16, 4096)), dim3(256), 0, stream,
-                       reinterpret_cast<uint32_t *>(status), L.status_bytes / 4);
+    // the histogram counters and the lookback words of every pass ("not
+    // published") start at zero: one fill over both (adjacent in the layout)
+    const size_t fill_words = (L.status + L.status_bytes - L.hist) / 4;
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(fill_words, 256 * 16, 4096)), dim3(256), 0, stream, hist,
+                       fill_words);
     prof_mark(stream, RT_KIND_FILL);
-    launch_histograms(keys, n, r, hist, stream);
+    launch_histograms(keys, n, r, hist, stream, true);
 
     PlanArgs a{};
     a.num_passes = r.num_passes;
@@ -487,7 +496,7 @@ extern "C" rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const r
     rt_status s = resolve_config(cfg, n < 2 ? 2 : n, 0, &r);
     if (s != RT_OK) return s;
     prof_begin(stream);
-    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream);
+    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream, false);
     return finish_call(stream, "rt_digit_histograms");
 }
 

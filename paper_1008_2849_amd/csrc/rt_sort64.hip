@@ -111,11 +111,9 @@ Layout64 make_layout64(size_t n, const Resolved &r, uint32_t value_words) {
     L.tiles = static_cast<uint32_t>(tiles);
     L.wide_status = n >= (static_cast<size_t>(1) << 30);
     const size_t sw = L.wide_status ? 8 : 4;
+    // the histograms and the lookback words are adjacent: one fill clears both
     size_t off = 0;
     L.hist = off;  off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
-    L.ctr = off;   off += align256(sizeof(uint32_t) * (kMaxPasses + 1));
-    L.base = off;  off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
-    L.plan = off;  off += align256(sizeof(SortPlan));
     L.status = off;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         L.status_pass[p] = off - L.status;
@@ -123,6 +121,9 @@ Layout64 make_layout64(size_t n, const Resolved &r, uint32_t value_words) {
     }
     off = align256(off);
     L.status_bytes = off - L.status;
+    L.ctr = off;   off += align256(sizeof(uint32_t) * (kMaxPasses + 1));
+    L.base = off;  off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.plan = off;  off += align256(sizeof(SortPlan));
     const bool need_t2 = (r.num_passes & 1u) || !(r.flags & RT_FLAG_NO_SKIP);
     const size_t karr = align256(n * sizeof(uint64_t));
     const size_t varr = align256(n * sizeof(uint32_t) * value_words);
@@ -155,7 +156,7 @@ void launch_histogram64_copies(const uint64_t *keys, uint32_t n, const HistArgs 
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram64<kBlock, C>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
     });
-    const uint32_t grid = grid_for(n, kBlock * 8 * 16, static_cast<uint32_t>(device_cu_count()) * 4);
+    const uint32_t grid = grid_for(n, 4096, static_cast<uint32_t>(device_cu_count()) * 4);
     hipLaunchKernelGGL((k_histogram64<kBlock, C>), dim3(grid), dim3(kBlock), lds, stream, keys, n, ha, hist);
 }
 
@@ -197,10 +198,10 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
 
     prof_begin(stream);
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(L.status_bytes / 4, 256 * 16, 4096)), dim3(256), 0, stream,
-                       reinterpret_cast<uint32_t *>(status), L.status_bytes / 4);
-    hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
-                       static_cast<size_t>(r.num_passes) * kMaxRadix);
+    // histogram counters and lookback words, adjacent in the layout
+    const size_t fill_words = (L.status + L.status_bytes - L.hist) / 4;
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(fill_words, 256 * 16, 4096)), dim3(256), 0, stream, hist,
+                       fill_words);
     prof_mark(stream, RT_KIND_FILL);
 
     HistArgs ha{};
