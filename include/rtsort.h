@@ -349,6 +349,32 @@ rt_status rt_server_release(rt_server *s, uint64_t ticket);
 rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
                           uint64_t *completed, size_t *peak_bytes);
 
+/* One request of an arrival trace for rt_server_replay: a generated input
+ * of n key/value pairs (as rt_server_submit_generated), arriving
+ * arrival_us microseconds after the replay starts. */
+typedef struct rt_replay_request {
+    double arrival_us;
+    uint64_t n;
+    rt_gen_params params;
+} rt_replay_request;
+
+/*
+ * Open-loop replay of an arrival trace, for measuring the server under a
+ * given offered load without the client's own submission cost in the way.
+ * A native thread submits reqs[i] (arrival_us nondecreasing) at its arrival
+ * time, never earlier; the calling thread collects completions in
+ * completion order and releases each result.  latency_us[i] receives the
+ * completion time of request i minus its scheduled arrival (so a late
+ * submission counts against the server, not for it); *span_us (may be
+ * NULL) the last completion minus the start.  The server must have no
+ * other requests outstanding and no other client while it runs.  Returns
+ * when every submitted request has finished: RT_OK, or the first failure
+ * (a submission refused, e.g. RT_ERR_BUDGET, or a request's own error), in
+ * which case latencies of requests not completed are negative.
+ */
+rt_status rt_server_replay(rt_server *s, const rt_replay_request *reqs, size_t count, double *latency_us,
+                           double *span_us);
+
 /* Stop the scheduler; requests not yet finished end as RT_ERR_CANCELLED. */
 rt_status rt_server_destroy(rt_server *s);
 

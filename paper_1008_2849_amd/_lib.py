@@ -60,6 +60,14 @@ class RtGenParams(ctypes.Structure):
     ]
 
 
+class RtReplayRequest(ctypes.Structure):
+    _fields_ = [
+        ("arrival_us", ctypes.c_double),
+        ("n", ctypes.c_uint64),
+        ("params", RtGenParams),
+    ]
+
+
 class RtError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status} ({detail})")
@@ -104,6 +112,7 @@ SIGNATURES = {
     "rt_server_fetch": (ctypes.c_int, [vp, u64, vp, vp]),
     "rt_server_release": (ctypes.c_int, [vp, u64]),
     "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),
+    "rt_server_replay": (ctypes.c_int, [vp, vp, sz, dblp, dblp]),
     "rt_server_destroy": (ctypes.c_int, [vp]),
     "rt_profile_start": (ctypes.c_int, [u32]),
     "rt_profile_stop": (ctypes.c_int, [ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float), u32,

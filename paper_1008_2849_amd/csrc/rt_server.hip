@@ -820,6 +820,101 @@ extern "C" rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_u
     return RT_OK;
 }
 
+extern "C" rt_status rt_server_replay(rt_server *s, const rt_replay_request *reqs, size_t count, double *latency_us,
+                                     double *span_us) {
+    if (s == nullptr || (count > 0 && (reqs == nullptr || latency_us == nullptr)))
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_replay: NULL argument");
+    for (size_t i = 0; i < count; ++i) {
+        latency_us[i] = -1.0;
+        if (i && reqs[i].arrival_us < reqs[i - 1].arrival_us)
+            return set_error(RT_ERR_INVALID_ARG, "rt_server_replay: arrivals decrease at request %zu", i);
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->uncollected) return set_error(RT_ERR_INVALID_ARG, "rt_server_replay: requests are outstanding");
+    }
+    if (span_us) *span_us = 0.0;
+    if (count == 0) return RT_OK;
+
+    std::mutex mu;  // ticket -> request index, and the submitter's outcome
+    std::unordered_map<uint64_t, size_t> index_of;
+    size_t submitted = 0;
+    bool submit_done = false;
+    rt_status submit_status = RT_OK;
+    std::string submit_error;
+    const double t0 = now_us() + 1000.0;  // the trace starts 1 ms from now
+
+    std::thread submitter([&] {
+        for (size_t i = 0; i < count; ++i) {
+            const double at = t0 + reqs[i].arrival_us;
+            for (double now = now_us(); now < at; now = now_us())
+                if (at - now > 300.0) std::this_thread::sleep_for(std::chrono::microseconds(static_cast<int64_t>(at - now - 200.0)));
+            uint64_t ticket = 0;
+            const rt_status st = rt_server_submit_generated(s, &reqs[i].params, static_cast<size_t>(reqs[i].n), &ticket);
+            std::lock_guard<std::mutex> g(mu);
+            if (st != RT_OK) {
+                submit_status = st;
+                submit_error = last_error();
+                break;
+            }
+            index_of[ticket] = i;
+            submitted = i + 1;
+        }
+        std::lock_guard<std::mutex> g(mu);
+        submit_done = true;
+    });
+
+    rt_status result = RT_OK;
+    std::string result_error;
+    size_t collected = 0;
+    double last_done = t0;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (submit_done && collected == submitted) break;
+        }
+        uint64_t ticket = 0;
+        double ignored = 0;
+        const rt_status st = rt_server_wait_any(s, 20000, &ticket, &ignored);
+        if (st == RT_ERR_TIMEOUT || st == RT_ERR_NOT_FOUND) continue;  // nothing finished yet
+        // the request may finish before the submitter has recorded its
+        // ticket: look until it is there or the submitter has stopped
+        size_t i = count;
+        for (bool stopped = false; i == count && !stopped;) {
+            std::lock_guard<std::mutex> g(mu);
+            auto f = index_of.find(ticket);
+            if (f != index_of.end()) i = f->second;
+            stopped = submit_done;
+        }
+        if (i == count) {  // not from this trace (another client broke the rule)
+            (void)rt_server_release(s, ticket);
+            continue;
+        }
+        if (st == RT_OK) {
+            double done = 0;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                auto it = s->all.find(ticket);
+                if (it != s->all.end()) done = it->second->t_done;
+            }
+            latency_us[i] = done - (t0 + reqs[i].arrival_us);
+            last_done = std::max(last_done, done);
+        } else if (result == RT_OK) {
+            result = st;
+            result_error = last_error();
+        }
+        (void)rt_server_release(s, ticket);
+        ++collected;
+    }
+    submitter.join();
+    if (span_us) *span_us = last_done - t0;
+    if (submit_status != RT_OK)
+        return set_error(submit_status, "rt_server_replay: submission %zu refused: %s", submitted,
+                         submit_error.c_str());
+    if (result != RT_OK) return set_error(result, "rt_server_replay: %s", result_error.c_str());
+    return RT_OK;
+}
+
 extern "C" rt_status rt_server_destroy(rt_server *s) {
     if (s == nullptr) return RT_OK;
     {

@@ -61,6 +61,34 @@ class Server:
               "rt_server_wait_any")
         return t.value, lat.value
 
+    def replay(self, arrivals_s, sizes, params):
+        """Open-loop replay of an arrival trace (rt_server_replay): request i,
+        of sizes[i] generated pairs with generator parameters params[i]
+        (RtGenParams), is submitted by a native thread arrivals_s[i] seconds
+        after the start.  Returns (latencies in us from each scheduled
+        arrival to completion, span in us from the start to the last
+        completion)."""
+        import numpy as np
+        from ._lib import RtReplayRequest
+        count = len(sizes)
+        reqs = (RtReplayRequest * count)()
+        base = ctypes.addressof(reqs)
+        size = ctypes.sizeof(RtReplayRequest)
+        arr = np.frombuffer((ctypes.c_uint8 * (count * size)).from_address(base), dtype=np.uint8)
+        arr = arr.reshape(count, size)
+        arr[:, 0:8] = np.ascontiguousarray(np.asarray(arrivals_s, dtype=np.float64) * 1e6).view(np.uint8).reshape(count, 8)
+        arr[:, 8:16] = np.ascontiguousarray(np.asarray(sizes, dtype=np.uint64)).view(np.uint8).reshape(count, 8)
+        off = RtReplayRequest.params.offset
+        psize = ctypes.sizeof(RtGenParams)
+        for i, p in enumerate(params):  # the generator parameters are copied as raw bytes
+            ctypes.memmove(base + i * size + off, ctypes.addressof(p), psize)
+        lat = np.full(count, -1.0, dtype=np.float64)
+        span = ctypes.c_double()
+        check(lib().rt_server_replay(self.handle, ctypes.cast(reqs, ctypes.c_void_p), count,
+                                     lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(span)),
+              "rt_server_replay")
+        return lat, span.value
+
     def fetch(self, ticket: int, out_keys, out_vals=None) -> None:
         check(lib().rt_server_fetch(self.handle, int(ticket), _ptr(out_keys), _ptr(out_vals)), "rt_server_fetch")
 

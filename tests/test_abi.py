@@ -273,6 +273,8 @@ def test_server_argument_errors(so):
     assert so.rt_server_submit(None, None, None, 0, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_submit_generated(None, None, 10, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_wait(None, 1, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_replay(None, None, 0, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert ctypes.sizeof(_lib.RtReplayRequest) == 224 and _lib.RtReplayRequest.params.offset == 16
     assert so.rt_server_wait_any(None, 0, ctypes.byref(t), None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_fetch(None, 1, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_release(None, 1) == _lib.RT_ERR_INVALID_ARG

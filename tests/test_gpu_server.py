@@ -124,3 +124,47 @@ def test_wait_any_reports_each_request_once_in_completion_order():
         with pytest.raises(RtError) as e:
             srv.wait_any(timeout_us=0)
         assert e.value.status == RT_ERR_NOT_FOUND
+
+
+def _trace(count, seed, max_log2=16, span_s=0.05):
+    import ctypes
+    rng = np.random.default_rng(seed)
+    arrivals = np.sort(rng.uniform(0, span_s, size=count))
+    sizes = np.floor(2.0 ** rng.uniform(0, max_log2, size=count)).astype(np.uint64)
+    params = []
+    for i in range(count):
+        params.append(gen_params_to_c(inputs.counter_params(i % 3, inputs.SEED_SERVING, 900 + i)))
+    return arrivals, sizes, params
+
+
+def test_replay_open_loop_trace():
+    """The native open-loop replay submits every request of a trace, and
+    each latency (completion - scheduled arrival) is non-negative; the
+    server is left with nothing outstanding."""
+    announce("server replay of a 300-request trace")
+    arrivals, sizes, params = _trace(300, 7)
+    with Server(hbm_budget_bytes=64 << 20, max_active=64) as srv:
+        lat, span = srv.replay(arrivals, sizes, params)
+        assert np.all(lat >= 0), lat[lat < 0][:5]
+        assert span >= arrivals[-1] * 1e6
+        assert np.all(lat <= span - arrivals * 1e6 + 1.0)
+        p50, p99, gk, done, peak = srv.stats()
+        assert done == 300
+        # nothing left: a second replay on the same server is accepted
+        lat2, _ = srv.replay(arrivals[:20], sizes[:20], params[:20])
+        assert np.all(lat2 >= 0)
+
+
+def test_replay_reports_a_refused_submission():
+    """A request over the budget stops the submitter; the replay returns
+    RT_ERR_BUDGET after the requests already submitted have finished, and
+    the refused and later requests have no latency."""
+    announce("server replay with a request over the budget")
+    arrivals, sizes, params = _trace(40, 8)
+    sizes[25] = 1 << 22  # 32 MiB of pairs: over the 8 MiB budget
+    with Server(hbm_budget_bytes=8 << 20, max_active=16) as srv:
+        with pytest.raises(RtError) as e:
+            srv.replay(arrivals, sizes, params)
+        assert e.value.status == RT_ERR_BUDGET
+        p50, p99, gk, done, peak = srv.stats()
+        assert done == 25
