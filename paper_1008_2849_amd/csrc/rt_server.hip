@@ -876,7 +876,11 @@ extern "C" rt_status rt_server_replay(rt_server *s, const rt_replay_request *req
         uint64_t ticket = 0;
         double ignored = 0;
         const rt_status st = rt_server_wait_any(s, 20000, &ticket, &ignored);
-        if (st == RT_ERR_TIMEOUT || st == RT_ERR_NOT_FOUND) continue;  // nothing finished yet
+        if (st == RT_ERR_TIMEOUT) continue;  // nothing finished yet
+        if (st == RT_ERR_NOT_FOUND) {        // all collected, the next arrival still ahead:
+            std::this_thread::sleep_for(std::chrono::microseconds(20));  // leave the lock to the scheduler
+            continue;
+        }
         // the request may finish before the submitter has recorded its
         // ticket: look until it is there or the submitter has stopped
         size_t i = count;
