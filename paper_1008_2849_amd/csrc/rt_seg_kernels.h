@@ -34,42 +34,58 @@ static __global__ __launch_bounds__(64) void k_seg_reset(SegHeader *__restrict__
 // `capacity` elements.  A segment with an end before its start, or reaching
 // past off[0] + capacity, is left untouched and raises kSegErrBounds.  When
 // the result is wanted in the temporaries (to_temp), a one-item segment is
-// copied there here, as no later kernel sees it.
+// copied there here, as no later kernel sees it.  List slots are taken per
+// wave: one atomic per class and wave, each lane's slot found from the
+// class's ballot.
 static __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ off, uint32_t num_segments,
                                                       uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
                                                       size_t capacity, uint32_t large_capacity, int to_temp,
                                                       SegClassLimits classes, SegDesc *__restrict__ descs,
                                                       uint32_t *__restrict__ lists, SegHeader *__restrict__ h) {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= num_segments) return;
-    const uint32_t o0 = off[0];
-    const uint32_t a = off[s], b = off[s + 1];
-    if (b < a || a < o0 || static_cast<size_t>(b - o0) > capacity) {
-        atomicOr(&h->error, kSegErrBounds);
-        return;
-    }
-    const uint32_t n = b - a;
-    if (n < 2) {  // nothing to sort
-        if (n == 1 && to_temp) {
-            tk[a - o0] = keys[a];
-            if (vals) tv[a - o0] = vals[a];
-        }
-        return;
-    }
+    int c = -1;  // list of this lane's segment (-1: none)
     SegDesc d;
-    d.k = keys + a;
-    d.v = vals ? vals + a : nullptr;
-    d.tk = tk + (a - o0);
-    d.tv = tv ? tv + (a - o0) : nullptr;
-    d.n = n;
-    d.pass = 0;
-    d.row = 0;
-    d.pad = 0;
-    int c = kSegLarge;
+    if (s < num_segments) {
+        const uint32_t o0 = off[0];
+        const uint32_t a = off[s], b = off[s + 1];
+        if (b < a || a < o0 || static_cast<size_t>(b - o0) > capacity) {
+            atomicOr(&h->error, kSegErrBounds);
+        } else if (b - a < 2) {  // nothing to sort
+            if (b - a == 1 && to_temp) {
+                tk[a - o0] = keys[a];
+                if (vals) tv[a - o0] = vals[a];
+            }
+        } else {
+            const uint32_t n = b - a;
+            d.k = keys + a;
+            d.v = vals ? vals + a : nullptr;
+            d.tk = tk + (a - o0);
+            d.tv = tv ? tv + (a - o0) : nullptr;
+            d.n = n;
+            d.pass = 0;
+            d.row = 0;
+            d.pad = 0;
+            c = kSegLarge;
 #pragma unroll
-    for (int i = kSegMaxClasses - 1; i >= 0; --i)
-        if (i < static_cast<int>(classes.count) && n <= classes.max_n[i]) c = i;
-    const uint32_t at = atomicAdd(&h->count[c], 1u);
+            for (int i = kSegMaxClasses - 1; i >= 0; --i)
+                if (i < static_cast<int>(classes.count) && n <= classes.max_n[i]) c = i;
+        }
+    }
+    uint32_t at = 0;
+#pragma unroll
+    for (int q = 0; q <= kSegLarge; ++q) {
+        const uint64_t mine = __builtin_amdgcn_ballot_w64(c == q);
+        if (mine == 0) continue;
+        const uint32_t lane_lo = static_cast<uint32_t>(mine), lane_hi = static_cast<uint32_t>(mine >> 32);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(lane_hi, __builtin_amdgcn_mbcnt_lo(lane_lo, 0u));
+        uint32_t first = 0;
+        if (below == 0 && c == q) first = atomicAdd(&h->count[q], static_cast<uint32_t>(__popcll(mine)));
+        // the wave's first lane of class q took the block of slots: share it
+        const int leader = __builtin_ffsll(static_cast<long long>(mine)) - 1;
+        first = __shfl(first, leader, 64);
+        if (c == q) at = first + below;
+    }
+    if (c < 0) return;
     if (c == kSegLarge) {
         if (at >= large_capacity) {  // only if capacity does not bound the offsets
             atomicOr(&h->error, kSegErrBounds);
