@@ -305,6 +305,9 @@ def bench_write_combining(rts, inputs, dev, K, W):
         out[name] = row
         del results, a, b, k0, v0
         torch.cuda.empty_cache()
+    # context only: the paper's Table 1 rows on its dual-CPU machine
+    out["paper_table1_context"] = {"unit": "M items/s", "machine": "2x Xeon W5580 (2010), N = 64 Mi",
+                                   "keys": {"VM+WC": 621, "VM only": 334}, "pairs": {"VM+WC": 430, "VM only": 203}}
     return out
 
 
@@ -723,7 +726,7 @@ def main() -> int:
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
     ok = ok and (sort64 is None or sort64["parity_properties_ok"])
-    ok = ok and (table1 is None or all(r["outputs_equal"] for r in table1.values()))
+    ok = ok and (table1 is None or all(r["outputs_equal"] for k, r in table1.items() if "outputs_equal" in r))
     return 0 if ok else 3
 
 
