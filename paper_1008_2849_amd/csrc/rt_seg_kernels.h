@@ -496,11 +496,13 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
         const uint32_t i = wslot0 + j * 64;
         key[j] = (full || i < valid) ? *gelem<SMALL>(src_k, tile_base + i) : 0u;
     }
-    if constexpr (VALS) {
+    if constexpr (VALS) {  // a full tile loads its values halfway through the ranking
+        if (!full) {
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const uint32_t i = wslot0 + j * 64;
-            val[j] = (full || i < valid) ? *gelem<SMALL>(src_v, tile_base + i) : 0u;
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t i = wslot0 + j * 64;
+                val[j] = i < valid ? *gelem<SMALL>(src_v, tile_base + i) : 0u;
+            }
         }
     }
 
@@ -517,6 +519,12 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
         uint32_t *dst = below == 0 ? wh + dg : scratch;
         *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
         compiler_fence();
+        if constexpr (VALS) {
+            if (full && j == IPT / 2 - 1) {
+#pragma unroll
+                for (int q = 0; q < IPT; ++q) val[q] = *gelem<SMALL>(src_v, tile_base + wslot0 + q * 64);
+            }
+        }
     }
     __syncthreads();
 

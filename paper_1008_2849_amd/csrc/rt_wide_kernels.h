@@ -166,11 +166,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
         const uint32_t i = wslot0 + j * 64;
         key[j] = (full || i < valid) ? src_k[tile_base + i] : 0ull;
     }
-    if constexpr (VALS) {
+    if constexpr (VALS) {  // a full tile loads its values halfway through the ranking
+        if (!full) {
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const uint32_t i = wslot0 + j * 64;
-            val[j] = (full || i < valid) ? src_v[tile_base + i] : V(0);
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t i = wslot0 + j * 64;
+                val[j] = i < valid ? src_v[tile_base + i] : V(0);
+            }
         }
     }
 
@@ -188,6 +190,12 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
         uint32_t *dst = below == 0 ? wh + d : scratch;
         *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
         compiler_fence();
+        if constexpr (VALS) {
+            if (full && j == IPT / 2 - 1) {
+#pragma unroll
+                for (int q = 0; q < IPT; ++q) val[q] = src_v[tile_base + wslot0 + q * 64];
+            }
+        }
     }
     __syncthreads();
 
