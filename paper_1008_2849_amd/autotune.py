@@ -337,6 +337,8 @@ def main(argv=None) -> int:
         entries += seg_entries
         report += seg_report
     tuned = {e["op"] for e in entries} | ops
+    if "segments" in tuned:
+        tuned.add("segments_workload")
     entries = [e for e in old.get("entries", []) if e["op"] not in tuned] + entries
     report = [r for r in old.get("measurements", []) if r.get("op") not in tuned] + report
     table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0),
