@@ -1,0 +1,65 @@
+"""Sorts past 2^30 items, where the lookback words become 64-bit and element
+offsets no longer fit 32-bit byte offsets: the single-array sort, the
+MSD-first sort (whose segmented passes switch too) and 64-bit keys.
+
+At this size the oracle is checked on the output's defining properties, on
+the device: keys ascend (unsigned), the values are a permutation of the
+original indices, every key arrives with its own index, and equal keys keep
+index order -- together they fix the stable sort uniquely.  Inputs come from
+the library's counter-based generator (checked against its host definition
+in test_gpu_sort.py) or torch's seeded device generator.
+"""
+import pytest
+
+import paper_1008_2849_amd as rts
+from paper_1008_2849_amd import inputs
+from gpu_util import announce, sync
+
+pytestmark = pytest.mark.gpu
+
+N = (1 << 30) + 4321
+
+
+def _check_pairs(k0, k, v):
+    import torch
+    ku = k.to(torch.int64) & 0xFFFFFFFF
+    assert bool((ku[1:] >= ku[:-1]).all()), "keys ascend"
+    vl = v.to(torch.int64)
+    assert bool(((vl >= 0) & (vl < k.numel())).all()), "values in range"
+    assert bool((torch.bincount(vl, minlength=k.numel()) == 1).all()), "values are a permutation"
+    assert bool(torch.equal(k0[vl], k)), "each key arrives with its own index"
+    eq = ku[1:] == ku[:-1]
+    assert bool((vl[1:][eq] > vl[:-1][eq]).all()), "equal keys keep index order"
+
+
+@pytest.mark.parametrize("path", ["lsd", "msd_first"])
+def test_pairs_past_2_30(path):
+    import torch
+    announce(f"{path} pairs n={N}")
+    k = torch.empty(N, dtype=torch.int32, device="cuda")
+    v = torch.empty(N, dtype=torch.int32, device="cuda")
+    rts.generate(k, v, inputs.counter_params(inputs.DIST_AND4, 61, 0))  # low-entropy keys, values = index
+    k0 = k.clone()
+    if path == "lsd":
+        rts.sort_pairs(k, v)
+    else:
+        rts.sort_msd_first(k, v, validate=True)
+    sync()
+    _check_pairs(k0, k, v)
+    del k, v, k0
+    torch.cuda.empty_cache()
+
+
+def test_keys64_past_2_30():
+    import torch
+    announce(f"64-bit keys n={N}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(62)
+    k = torch.randint(-(1 << 63), (1 << 63) - 1, (N,), dtype=torch.int64, device="cuda", generator=g)
+    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device="cuda")
+    want = torch.sort(k ^ sign).values ^ sign  # unsigned ascending order
+    rts.sort_keys64(k)
+    sync()
+    assert bool(torch.equal(k, want))
+    del k, want
+    torch.cuda.empty_cache()
