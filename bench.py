@@ -503,7 +503,7 @@ def main() -> int:
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the write-combining leg (the paper's Table 1 configurations)")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
-    ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="comma list of offered loads (fraction "
+    ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
                     "of single-array throughput), replayed open loop; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-inflight", default="64,256",

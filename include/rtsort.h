@@ -63,6 +63,20 @@ typedef enum rt_status {
  * only" row of Table 1), for measuring what the staging buys.  Same result;
  * not combinable with RT_FLAG_NT_STORES. */
 #define RT_FLAG_DIRECT_SCATTER 0x8u
+/* XCD chunks.  A sort whose digits are all at most 8 bits wide may split
+ * every pass's input into 8 chunks, one per XCD: the tiles of a chunk run on
+ * that XCD, and each chunk has its own lookback chain and output start per
+ * digit (from per-chunk counts taken by the upfront histogram read), so the
+ * ends of neighbouring digit runs, which share cache lines, are written
+ * through one L2.  By default a sort of at least 2^22 items samples its keys
+ * first and uses chunks unless they would be badly unbalanced or the
+ * per-chunk counting would contend on a few frequent digits (skewed keys).
+ * RT_FLAG_ONE_CHAIN: never use chunks (one lookback chain per pass).
+ * RT_FLAG_CHUNKS: always use chunks, at any size, without sampling (ignored
+ * if a digit is wider than 8 bits).  The result is the same in every case;
+ * the flags are for measuring and testing.  They exclude each other. */
+#define RT_FLAG_ONE_CHAIN 0x10u
+#define RT_FLAG_CHUNKS 0x20u
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".
@@ -418,6 +432,7 @@ rt_status rt_tuned_config(size_t n, int with_values, rt_config *out);
 #define RT_KIND_SEGMENTED 7u /* segmented sort: tile lists of the tiled segments */
 #define RT_KIND_SEG_SMALL 8u /* segmented sort: segments sorted whole in LDS */
 #define RT_KIND_MSD_PASS 9u  /* MSD-first sort: the partition pass on the top digit */
+#define RT_KIND_PROBE 10u    /* sample of the keys that chooses XCD chunks or one chain */
 #define RT_KIND_PASS 16u     /* + pass index: one counting-sort pass (onesweep) */
 rt_status rt_profile_start(uint32_t max_marks);
 rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_t *count);

@@ -27,6 +27,8 @@ RT_MAX_DIGIT_BITS = 11
 RT_FLAG_NO_SKIP = 0x1
 RT_FLAG_NT_STORES = 0x2
 RT_FLAG_DIRECT_SCATTER = 0x8
+RT_FLAG_ONE_CHAIN = 0x10
+RT_FLAG_CHUNKS = 0x20
 RT_FLAG_VALIDATE = 0x4
 
 RT_KIND_FILL = 1
@@ -38,6 +40,7 @@ RT_KIND_GENERATE = 6
 RT_KIND_SEGMENTED = 7
 RT_KIND_SEG_SMALL = 8
 RT_KIND_MSD_PASS = 9
+RT_KIND_PROBE = 10
 RT_KIND_PASS = 16
 
 

@@ -17,6 +17,8 @@ from ._lib import RtConfig, RtGenParams, check, lib
 FLAG_NO_SKIP = _lib.RT_FLAG_NO_SKIP
 FLAG_NT_STORES = _lib.RT_FLAG_NT_STORES
 FLAG_DIRECT_SCATTER = _lib.RT_FLAG_DIRECT_SCATTER
+FLAG_ONE_CHAIN = _lib.RT_FLAG_ONE_CHAIN
+FLAG_CHUNKS = _lib.RT_FLAG_CHUNKS
 MAX_DIGIT_BITS = _lib.RT_MAX_DIGIT_BITS
 MAX_PASSES = _lib.RT_MAX_PASSES
 

@@ -89,13 +89,13 @@ static uint32_t cap_grid(size_t want, uint32_t cap) {
 // temporaries (odd pass counts), where the tiled passes leave it.
 template <bool VALS, typename S>
 static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint32_t list_stride, int passes,
-                                 int to_temp, hipStream_t stream) {
+                                 int to_temp, uint32_t nchunks, hipStream_t stream) {
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
     uint32_t *large_list = P.lists + static_cast<size_t>(kSegLarge) * list_stride;
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
                        L.large_capacity, L.max_tiles);
     hipLaunchKernelGGL(k_seg_tilemap, dim3(cap_grid((L.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, stream,
-                       P.first_tile, P.header, P.tile_seg);
+                       P.first_tile, P.header, P.tile_seg, nchunks);
     prof_mark(stream, RT_KIND_SEGMENTED);
     hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
                        P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist);
@@ -113,8 +113,8 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
         S *status = reinterpret_cast<S *>(reinterpret_cast<char *>(P.status) + p * L.status_pass);
         hipLaunchKernelGGL((k_seg_onesweep<1024, 16, VALS, S>), dim3(L.max_tiles), dim3(1024), 0, stream, P.descs,
                            large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status,
-                           P.header_words + offsetof(SegHeader, tile_ctr) / 4 + p,
-                           P.header_words + offsetof(SegHeader, error) / 4);
+                           P.header_words + offsetof(SegHeader, chunk_ctr) / 4 + p * kChunks,
+                           P.header_words + offsetof(SegHeader, error) / 4, nchunks);
         prof_mark(stream, RT_KIND_PASS + p);
     }
 }
@@ -152,12 +152,16 @@ void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
     hipLaunchKernelGGL(k_seg_classify, dim3((num_segments + 255) / 256), dim3(256), 0, stream, offsets,
                        num_segments, keys, vals, tk, vals_on ? tv : nullptr, L.capacity, L.large_capacity,
                        to_temp, L.classes.limits(), P.descs, P.lists, P.header);
+    // XCD chunks of the tile list pay off for long segments only: with a few
+    // tiles per segment (many partial tiles, short lookback chains) one
+    // chunk measured faster.  The segments' mean size bounds their tiles.
+    const uint32_t nchunks = seg_chunk_count(L.capacity, num_segments);
     if (L.wide_status) {
-        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, stream);
-        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, stream);
+        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
+        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
     } else {
-        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, passes, to_temp, stream);
-        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, passes, to_temp, stream);
+        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
+        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
     }
 }
 

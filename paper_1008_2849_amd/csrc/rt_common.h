@@ -30,16 +30,19 @@ struct Resolved {
     int ipt;
     uint32_t flags;
     bool with_values;
+    bool chunked;  // passes may run in XCD chunks (every digit of at most 8 bits)
+    bool probe;    // chunked: the probe kernel decides per sort (else chunks always)
 };
 
 // Byte offsets of the workspace regions.
 struct Layout {
-    size_t hist, base, plan, ctr, status, status_bytes;
+    size_t hist, base, cbase, plan, ctr, status, status_bytes;
     size_t status_pass[kMaxPasses];
     size_t t1k, t1v, t2k, t2v;
     size_t total;
-    uint32_t tiles;     // tiles per pass
-    bool wide_status;   // n >= 2^30: 64-bit lookback words and byte offsets
+    uint32_t tiles;       // tiles of the global grid per pass
+    uint32_t grid_tiles;  // blocks per pass: the grid cut at up to kChunks - 1 chunk ends
+    bool wide_status;     // n >= 2^30: 64-bit lookback words and byte offsets
 };
 
 rt_status set_error(rt_status s, const char *fmt, ...);
@@ -110,6 +113,13 @@ struct SegLayout {
     size_t header, descs, lists, first_tile, tile_seg, hist, base, status, status_pass, tk, tv;
     size_t total;
 };
+
+// Chunks of a segmented pass's tile list: kChunks when the segments hold
+// kSegChunkMinTiles tiles or more on average (items / segments), else 1.
+constexpr uint32_t kSegChunkMinTiles = 16;
+inline uint32_t seg_chunk_count(size_t items, size_t segments) {
+    return segments > 0 && items / segments >= static_cast<size_t>(kSegChunkMinTiles) * kSegTile ? kChunks : 1u;
+}
 
 struct SegPointers {
     SegHeader *header;

@@ -170,7 +170,20 @@ struct HistArgs {
     uint32_t mask[kMaxPasses];
     uint32_t lds_offset[kMaxPasses];
     uint32_t total_bins;
+    // per-chunk counts (CHUNKED): pass 0 by position, chunk x = keys
+    // [pos_bound[x], pos_bound[x + 1]); pass p > 0 by the top bits of digit
+    // p - 1, chunk = digit(p - 1) >> cshift[p - 1]
+    uint32_t cshift[kMaxPasses];
+    uint32_t pos_bound[kChunks + 1];
 };
+
+// Chunk of pass 0 that holds key i.
+__device__ __forceinline__ uint32_t pos_chunk(const HistArgs &ha, size_t i) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int q = 1; q < kChunks; ++q) x += i >= ha.pos_bound[q] ? 1u : 0u;
+    return x;
+}
 
 // Counts per pass and digit into hist[p * kMaxRadix + d], which must start at
 // zero.  A block keeps C copies of the counters of all passes in LDS, one
@@ -180,12 +193,19 @@ struct HistArgs {
 // wave's batch of 64 * U keys, one test per pass checks whether the whole
 // batch shares that pass's digit (constant bytes, runs of equal keys); such
 // a digit is counted with a single add.  Keys are read in 256-byte slots.
-template <int BLOCK, int C>
-__global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict__ keys, uint32_t n,
-                                                     HistArgs ha, uint32_t *__restrict__ hist) {
+//
+// CHUNKED: every pass's counts are split by chunk (see PassPlan) into
+// hist[(p * kChunks + x) * kChunkRadix + d], LDS rows kChunks times longer.
+// The chunks of pass p > 0 are ranges of digit p - 1, which is how pass p's
+// input (pass p - 1's output) is ordered, so one read of the keys gives
+// every pass's per-chunk counts.  A wave's batch never straddles a chunk of
+// pass 0 (the bounds are multiples of 1024 keys).
+template <int BLOCK, int C, bool CHUNKED>
+__device__ __forceinline__ void histogram_body(const uint32_t *__restrict__ keys, uint32_t n, const HistArgs &ha,
+                                               uint32_t *__restrict__ hist, uint32_t *s_h) {
     constexpr int WAVES = BLOCK / 64;
     constexpr int U = 16;  // slots in flight per lane (8 measured 18 % slower on 2^28 keys)
-    extern __shared__ uint32_t s_h[];  // C rows of total_bins + 1 counters
+    // s_h: C rows of total_bins + 1 counters
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
@@ -210,11 +230,33 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
             for (int p = 0; p < kMaxPasses; ++p) {
                 if (p >= static_cast<int>(ha.num_passes)) break;
                 uint32_t *hp = h + ha.lds_offset[p];
-                if (__builtin_amdgcn_ballot_w64(((differ >> ha.shift[p]) & ha.mask[p]) != 0u) == 0u) {
-                    if (lane == 0) atomicAdd(&hp[(k0 >> ha.shift[p]) & ha.mask[p]], static_cast<uint32_t>(64 * U));
-                } else {
+                const uint32_t sh = ha.shift[p], m = ha.mask[p];
+                if constexpr (!CHUNKED) {
+                    if (__builtin_amdgcn_ballot_w64(((differ >> sh) & m) != 0u) == 0u) {
+                        if (lane == 0) atomicAdd(&hp[(k0 >> sh) & m], static_cast<uint32_t>(64 * U));
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < U; ++u) atomicAdd(&hp[(k[u] >> ha.shift[p]) & ha.mask[p]], 1u);
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[(k[u] >> sh) & m], 1u);
+                    }
+                } else if (p == 0) {
+                    hp += pos_chunk(ha, base) * (m + 1u);
+                    if (__builtin_amdgcn_ballot_w64(((differ >> sh) & m) != 0u) == 0u) {
+                        if (lane == 0) atomicAdd(&hp[(k0 >> sh) & m], static_cast<uint32_t>(64 * U));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[(k[u] >> sh) & m], 1u);
+                    }
+                } else {
+                    const uint32_t cs = ha.shift[p - 1] + ha.cshift[p - 1];
+                    const uint32_t cm = ha.mask[p - 1] >> ha.cshift[p - 1];
+                    const uint32_t w = 32u - __builtin_clz(m);
+                    if (__builtin_amdgcn_ballot_w64((differ & ((m << sh) | (cm << cs))) != 0u) == 0u) {
+                        if (lane == 0)
+                            atomicAdd(&hp[(((k0 >> cs) & cm) << w) | ((k0 >> sh) & m)], static_cast<uint32_t>(64 * U));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[(((k[u] >> cs) & cm) << w) | ((k[u] >> sh) & m)], 1u);
+                    }
                 }
             }
         } else {  // the ragged end of the array
@@ -223,8 +265,16 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
                 const size_t i = base + u * 64 + lane;
                 if (i >= n) continue;
                 const uint32_t key = keys[i];
-                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p)
-                    atomicAdd(&h[ha.lds_offset[p] + ((key >> ha.shift[p]) & ha.mask[p])], 1u);
+                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p) {
+                    uint32_t bin = (key >> ha.shift[p]) & ha.mask[p];
+                    if constexpr (CHUNKED) {
+                        const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
+                        const uint32_t x = p == 0 ? pos_chunk(ha, i)
+                                                  : ((key >> ha.shift[p - 1]) & ha.mask[p - 1]) >> ha.cshift[p - 1];
+                        bin |= x << w;
+                    }
+                    atomicAdd(&h[ha.lds_offset[p] + bin], 1u);
+                }
             }
         }
     }
@@ -236,30 +286,228 @@ __global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict_
         if (c == 0) continue;
         uint32_t p = 0;
         while (p + 1 < ha.num_passes && i >= ha.lds_offset[p + 1]) ++p;
-        atomicAdd(&hist[p * kMaxRadix + (i - ha.lds_offset[p])], c);
+        const uint32_t local = i - ha.lds_offset[p];
+        if constexpr (CHUNKED) {
+            const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
+            atomicAdd(&hist[(p * kChunks + (local >> w)) * kChunkRadix + (local & ha.mask[p])], c);
+        } else {
+            atomicAdd(&hist[p * kMaxRadix + local], c);
+        }
     }
+}
+
+template <int BLOCK, int C, bool CHUNKED = false>
+__global__ __launch_bounds__(BLOCK) void k_histogram(const uint32_t *__restrict__ keys, uint32_t n,
+                                                     HistArgs ha, uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_h[];
+    histogram_body<BLOCK, C, CHUNKED>(keys, n, ha, hist, s_h);
+}
+
+// The histogram of a sort that may count per chunk: per chunk (CC copies,
+// args hc) if the probe chose it (*mode != 0), else plain (CP copies, hp).
+template <int BLOCK, int CP, int CC>
+__global__ __launch_bounds__(BLOCK) void k_histogram_auto(const uint32_t *__restrict__ keys, uint32_t n,
+                                                          HistArgs hp, HistArgs hc, const uint32_t *__restrict__ mode,
+                                                          uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_h[];
+    if (*mode != 0u)
+        histogram_body<BLOCK, CC, true>(keys, n, hc, hist, s_h);
+    else
+        histogram_body<BLOCK, CP, false>(keys, n, hp, hist, s_h);
+}
+
+// Chooses, for one sort, between per-chunk counts with one lookback chain
+// per chunk (*mode = 1) and plain counts with one chain per pass (*mode =
+// 0), from kProbeSamples keys in evenly spaced runs.  Per-chunk counts leave
+// room for only two LDS copies per histogram block, so a frequent (chunk,
+// digit) bin serialises its atomics; and when one chunk of pass p > 0 (a
+// range of digit p - 1) holds most items, its tiles are claimed by every XCD
+// in turn and the pass gains nothing.  Either is a reason for one chain: a bin above 1/64 of
+// the samples (unless the pass's digit is constant: batches of equal digits
+// are counted with one add), or a chunk above 1/4 (unless digit p - 1 is
+// constant: then the pass has a single chunk and loses nothing).
+constexpr uint32_t kProbeSamples = 16384;  // 256 runs of 64 consecutive keys
+
+template <typename T, typename F>
+__device__ __forceinline__ T wave_reduce(T v, F op) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restrict__ keys, uint32_t n, HistArgs ha,
+                                                       uint32_t *__restrict__ mode) {
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int RUNS = static_cast<int>(kProbeSamples / 64);
+    constexpr int PER = RUNS / WAVES;  // runs per wave = keys per lane
+    __shared__ uint32_t s_tab[kChunks * kChunkRadix];
+    __shared__ uint32_t s_chunk[kChunks];
+    __shared__ uint32_t s_lo[kMaxPasses], s_hi[kMaxPasses];
+    __shared__ uint32_t s_max, s_bad;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    // runs of consecutive keys: a few hundred pages touched, not thousands
+    uint32_t k[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint64_t start = static_cast<uint64_t>(wave * PER + j) * n / RUNS;
+        k[j] = keys[min(start + lane, static_cast<uint64_t>(n) - 1u)];
+    }
+    if (tid < kMaxPasses) {
+        s_lo[tid] = ~0u;
+        s_hi[tid] = 0u;
+    }
+    if (tid == 0) s_bad = 0u;
+    __syncthreads();
+    for (uint32_t p = 0; p < ha.num_passes; ++p) {
+        uint32_t lo = ~0u, hi = 0u;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t d = (k[j] >> ha.shift[p]) & ha.mask[p];
+            lo = min(lo, d);
+            hi = max(hi, d);
+        }
+        lo = wave_reduce(lo, [](uint32_t x, uint32_t y) { return min(x, y); });
+        hi = wave_reduce(hi, [](uint32_t x, uint32_t y) { return max(x, y); });
+        if (lane == 0) {
+            atomicMin(&s_lo[p], lo);
+            atomicMax(&s_hi[p], hi);
+        }
+    }
+    for (uint32_t p = 0; p < ha.num_passes; ++p) {
+        for (uint32_t i = tid; i < kChunks * kChunkRadix; i += BLOCK) s_tab[i] = 0u;
+        if (tid < kChunks) s_chunk[tid] = 0u;
+        if (tid == 0) s_max = 0u;
+        __syncthreads();
+        const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t x = p == 0 ? 0u : ((k[j] >> ha.shift[p - 1]) & ha.mask[p - 1]) >> ha.cshift[p - 1];
+            atomicAdd(&s_tab[(x << w) | ((k[j] >> ha.shift[p]) & ha.mask[p])], 1u);
+        }
+        __syncthreads();
+        uint32_t m = 0;
+        for (uint32_t i = tid; i < (kChunks << w); i += BLOCK) {
+            const uint32_t c = s_tab[i];
+            m = max(m, c);
+            if (c != 0u) atomicAdd(&s_chunk[i >> w], c);
+        }
+        m = wave_reduce(m, [](uint32_t x, uint32_t y) { return max(x, y); });
+        if (lane == 0) atomicMax(&s_max, m);
+        __syncthreads();
+        if (tid == 0) {
+            if (s_lo[p] != s_hi[p] && s_max > kProbeSamples / 64) s_bad = 1u;
+            if (p > 0 && s_lo[p - 1] != s_hi[p - 1]) {
+                uint32_t mc = 0;
+                for (int x = 0; x < kChunks; ++x) mc = max(mc, s_chunk[x]);
+                if (mc > kProbeSamples / 4) s_bad = 1u;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *mode = s_bad ? 0u : 1u;
 }
 
 // ---------------------------------------------------------------------------
 // planning: exclusive prefix sums, pass skipping, buffer assignment
 // ---------------------------------------------------------------------------
 
+// The chunk fields of pass p's plan (see k_plan), written in place.
+// prev_start[x]: where chunk x's first digit of pass p - 1 starts.
+__device__ inline void plan_chunks(const PlanArgs &a, bool chunked, const uint32_t *prev_start,
+                                   const uint32_t *base, uint32_t p, PassPlan *pp) {
+    uint32_t cs[kChunks + 1];
+#pragma unroll
+    for (int x = 0; x <= kChunks; ++x) cs[x] = a.n;
+    cs[0] = 0u;
+    pp->nchunks = 1;
+    pp->cbase = base + p * kMaxRadix;
+    if (a.chunk_ctr != nullptr && a.tile != 0u && chunked) {
+        pp->nchunks = kChunks;
+        pp->cbase = a.cbase + p * kChunks * kChunkRadix;
+        if (p == 0) {
+#pragma unroll
+            for (int x = 1; x < kChunks; ++x) cs[x] = min(a.pos_bound[x], a.n);
+        } else {
+            const uint32_t w = a.width[p - 1];
+            const uint32_t nch = 1u << (w > 3u ? 3u : w);
+#pragma unroll
+            for (uint32_t x = 1; x < kChunks; ++x)
+                if (x < nch) cs[x] = prev_start[x];
+        }
+    }
+    uint32_t t = 0;
+#pragma unroll
+    for (int x = 0; x < kChunks; ++x) {
+        pp->cstart[x] = cs[x];
+        pp->ctile[x] = t;
+        if (a.tile != 0u && cs[x + 1] > cs[x])  // tiles of the global grid that meet [cs[x], cs[x + 1])
+            t += static_cast<uint32_t>((static_cast<uint64_t>(cs[x + 1]) + a.tile - 1u) / a.tile - cs[x] / a.tile);
+    }
+    pp->cstart[kChunks] = a.n;
+    pp->ctile[kChunks] = t;
+}
+
 // One block of 256 threads; thread t covers bins [8t, 8t + 8) of a pass.
 // Also clears the tile counters of the passes and the error word after them.
+//
+// Chunks (a.chunk_ctr set): with a.chunked the histograms are per chunk (see
+// k_histogram) and every pass gets kChunks chunks: pass 0 by position, pass
+// p > 0 by the top bits of digit p - 1, so that chunk x of pass p starts
+// where digit x << cshift starts in pass p - 1's output.  (If pass p - 1 is
+// skipped its digit is constant, its output order is its input order and
+// all items fall in one chunk, so the rule holds for skipped passes too.)
+// Chunk x's output slot of digit d is the digit's start plus the counts of
+// d in chunks 0..x-1.  Without a.chunked every pass is one chunk.
 static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t *__restrict__ hist,
                                               uint32_t *__restrict__ base, SortPlan *__restrict__ plan,
                                               uint32_t *__restrict__ tile_counters, uint32_t direct) {
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_constant[kMaxPasses];
+    __shared__ uint32_t s_cstart[kMaxPasses + 1][kChunks];  // [p][x]: base of pass p - 1 at chunk x's first digit
     const uint32_t tid = threadIdx.x;
+    // the histograms are per chunk only if the sort allows it and the probe
+    // chose it (see k_chunk_probe)
+    const bool chunked = a.chunked && (a.mode == nullptr || *a.mode != 0u);
     if (tid < kMaxPasses) {
         s_constant[tid] = 0u;
         tile_counters[tid] = 0u;
     }
     if (tid == kMaxPasses) tile_counters[kMaxPasses] = 0u;  // the error word
+    if (a.chunk_ctr != nullptr)
+        for (uint32_t i = tid; i < kMaxPasses * kChunks; i += 256) a.chunk_ctr[i] = 0u;
     __syncthreads();
     for (uint32_t p = 0; p < a.num_passes; ++p) {
         const uint32_t bins = 1u << a.width[p];
+        if (chunked) {
+            // digits of at most 8 bits: thread t owns digit t, its chunk
+            // counts loaded together
+            const uint32_t d = tid;
+            uint32_t h[kChunks];
+            uint32_t c = 0;
+#pragma unroll
+            for (int x = 0; x < kChunks; ++x) {
+                h[x] = d < bins ? hist[(p * kChunks + x) * kChunkRadix + d] : 0u;
+                c += h[x];
+            }
+            if (c == a.n) s_constant[p] = 1u;  // every key has this digit
+            const uint32_t run = block_exclusive_sum<256>(c, s_wsum);
+            base[p * kMaxRadix + d] = d < bins ? run : a.n;
+            for (uint32_t i = d + 256; i < static_cast<uint32_t>(kMaxRadix); i += 256) base[p * kMaxRadix + i] = a.n;
+            if (d < bins) {
+                uint32_t r = run;
+#pragma unroll
+                for (int x = 0; x < kChunks; ++x) {
+                    a.cbase[(p * kChunks + x) * kChunkRadix + d] = r;
+                    r += h[x];
+                }
+                // pass p + 1's chunk x starts where digit x << cshift of this pass starts
+                const uint32_t cshift = a.width[p] > 3u ? a.width[p] - 3u : 0u;
+                if ((d & ((1u << cshift) - 1u)) == 0u && (d >> cshift) < kChunks) s_cstart[p + 1][d >> cshift] = run;
+            }
+            __syncthreads();  // s_wsum is reused by the next pass; s_cstart is read below
+            continue;
+        }
         uint32_t c[8];
         uint32_t sum = 0;
 #pragma unroll
@@ -296,7 +544,7 @@ static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t 
         pp.active = active[p];
         pp.shift = a.shift[p];
         pp.width = a.width[p];
-        pp.pad = 0;
+        pp.pad[0] = pp.pad[1] = 0;
         pp.src_k = src_k;
         pp.src_v = src_v;
         pp.dst_k = nullptr;
@@ -322,6 +570,7 @@ static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t 
             ++j;
         }
         plan->pass[p] = pp;
+        plan_chunks(a, chunked, s_cstart[p], base, p, &plan->pass[p]);  // in place: no indexed local copy
     }
     plan->executed = executed;
     plan->copy_back = (!direct && executed == 1) ? 1u : 0u;
@@ -346,23 +595,26 @@ constexpr int kLookbackBatch = 8;
 constexpr uint32_t kLookbackSpinLimit = 1u << 22;
 constexpr uint32_t kErrLookbackTimeout = 1u;
 
+//
+// The chain starts at tile lo (the first tile of a chunk or segment): only
+// tiles [lo, tile) are summed.
 template <typename S>
-__device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status, int32_t tile, uint32_t digit,
-                                                   int radix, uint32_t *__restrict__ error_flag) {
+__device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status, int32_t tile, int32_t lo,
+                                                   uint32_t digit, int radix, uint32_t *__restrict__ error_flag) {
     using St = Status<S>;
     uint32_t excl = 0;
     int32_t at = tile - 1;  // the nearest tile not yet accounted for
     uint32_t idle = 0, nap = 1;
-    while (at >= 0) {
+    while (at >= lo) {
         S w[kLookbackBatch];
 #pragma unroll
         for (int b = 0; b < kLookbackBatch; ++b)
-            w[b] = (at - b >= 0) ? status_load(status + static_cast<size_t>(at - b) * radix + digit) : S(0);
+            w[b] = (at - b >= lo) ? status_load(status + static_cast<size_t>(at - b) * radix + digit) : S(0);
         bool finished = false, stalled = false;
         int32_t consumed = 0;
 #pragma unroll
         for (int b = 0; b < kLookbackBatch; ++b) {
-            if (finished || stalled || at - b < 0) continue;
+            if (finished || stalled || at - b < lo) continue;
             const uint32_t f = St::flag(w[b]);
             if (f == 0u) {
                 stalled = true;  // not published yet: resume from this tile
@@ -388,9 +640,89 @@ __device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status,
     return excl;
 }
 
-// One block per tile of BLOCK * IPT consecutive items, claimed in order from
-// an atomic counter (so a block only ever waits on tiles claimed before it,
-// by blocks that are already running).  Wave w of the tile owns items
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// The XCD this wave runs on (0..7 on the MI355X).
+__device__ __forceinline__ uint32_t xcd_id() {
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+    return x;
+}
+
+// Claims an index for the block (called by one thread).  Chunk x owns the
+// indices [bound[x], bound[x + 1]) and hands them out in order from its
+// counter ctr[x]; the block tries the chunk of its own XCD first, then the
+// next chunk with indices left.  Returns kNoTile once every chunk is
+// exhausted.  Only the order within a chunk matters for progress: a block
+// waits only on indices claimed before it, whichever XCD they run on.
+__device__ __forceinline__ uint32_t claim_chunked(const uint32_t *__restrict__ bound, uint32_t nch,
+                                                  uint32_t *__restrict__ ctr, uint32_t &chunk) {
+    const uint32_t x0 = xcd_id() % nch;
+    {
+        // the atomic goes out with the loads of the chunk's bounds (one
+        // round trip): a claim past the end of a chunk is simply dropped
+        const uint32_t k = atomicAdd(ctr + x0, 1u);
+        const uint32_t b0 = bound[x0], size = bound[x0 + 1] - b0;
+        if (k < size) {
+            chunk = x0;
+            return b0 + k;
+        }
+    }
+    if (nch == 1u) return kNoTile;
+    // The own chunk is exhausted: read every counter at once rather than
+    // spend one atomic (a memory round trip) per full chunk.  Counters only
+    // grow, so a chunk seen full stays full.
+    uint32_t full = 0;
+#pragma unroll
+    for (int y = 0; y < kChunks; ++y) {
+        if (y >= static_cast<int>(nch)) break;
+        const uint32_t used = __hip_atomic_load(ctr + y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (used >= bound[y + 1] - bound[y]) full |= 1u << y;
+    }
+    for (uint32_t q = 1; q < nch; ++q) {
+        const uint32_t x = (x0 + q) % nch;
+        if ((full >> x) & 1u) continue;
+        const uint32_t k = atomicAdd(ctr + x, 1u);
+        if (k < bound[x + 1] - bound[x]) {
+            chunk = x;
+            return bound[x] + k;
+        }
+    }
+    return kNoTile;
+}
+
+// Claims a tile of a pass (one thread): its lookback index, the lookback
+// index of its chunk's first tile, its chunk, its first input item and its
+// item count; tile = kNoTile once every chunk is exhausted.  The chunk tables
+// are read from the plan in global memory: indexing a by-value copy with a
+// run-time chunk would put it in scratch memory.
+template <int TILE>
+__device__ __forceinline__ void claim_tile(const PassPlan *__restrict__ pp, uint32_t *chunk_counter, uint32_t &tile,
+                                           uint32_t &first, uint32_t &chunk, uint32_t &lo, uint32_t &valid) {
+    uint32_t x = 0;
+    tile = claim_chunked(pp->ctile, pp->nchunks, chunk_counter, x);
+    if (tile == kNoTile) return;
+    const uint32_t t0 = pp->ctile[x];
+    const uint32_t c0 = pp->cstart[x], c1 = pp->cstart[x + 1];
+    const uint64_t g = c0 / TILE + (tile - t0);  // tile of the global grid
+    const uint64_t b = max(static_cast<uint64_t>(c0), g * TILE);
+    const uint64_t e = min(static_cast<uint64_t>(c1), (g + 1) * TILE);
+    first = t0;
+    chunk = x;
+    lo = static_cast<uint32_t>(b);
+    valid = static_cast<uint32_t>(e - b);
+}
+
+// One block per tile of BLOCK * IPT consecutive items.  The pass's input is
+// split into chunks (see PassPlan); a block claims the next tile of the
+// chunk of the XCD it runs on, or of the next chunk with tiles left once
+// that one is exhausted.  Tiles of a chunk are claimed in order from the
+// chunk's counter, so a block only ever waits on tiles claimed before it,
+// by blocks that are already running, whichever XCD they run on.  The tiles
+// of a chunk are the global grid of TILE-item tiles cut at the chunk's
+// ends, so only a chunk's first and last tile can be partial.  The grid
+// needs ctile[nchunks] blocks; surplus blocks find every chunk exhausted
+// and exit.  Wave w of the tile owns items
 // [w * 64 * IPT, (w + 1) * 64 * IPT) of it and lane l holds item j * 64 + l
 // of that range in slot j, so slot-by-slot, lane-by-lane processing follows
 // input order, which makes the ranking stable.
@@ -407,8 +739,7 @@ __device__ __forceinline__ uint32_t lookback_digit(const S *__restrict__ status,
 // counterpart), kept to measure what the staging buys.
 template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
-                                                    const uint32_t *__restrict__ pass_base, S *__restrict__ status,
-                                                    uint32_t *__restrict__ tile_counter,
+                                                    S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                                     uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
@@ -429,7 +760,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
     __shared__ uint32_t s_gbase[RADIX];
     __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_first, s_chunk, s_lo, s_valid;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -441,13 +772,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
     uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
 
     for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;  // this wave's counters
-    if (tid == 0) s_tile = atomicAdd(tile_counter + pass, 1u);
+    if (tid == 0) claim_tile<TILE>(plan->pass + pass, chunk_counter, s_tile, s_first, s_chunk, s_lo, s_valid);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const size_t tile_base = static_cast<size_t>(tile) * TILE;
-    if (tile_base >= n) return;  // only if the tile counter was not cleared
-    const uint32_t valid = static_cast<uint32_t>(min(static_cast<size_t>(TILE), n - tile_base));
+    if (tile == kNoTile) return;
+    const int32_t first = static_cast<int32_t>(s_first);
+    const size_t tile_base = s_lo;
+    const uint32_t valid = s_valid;
     const bool full = valid == static_cast<uint32_t>(TILE);
+    const uint32_t *pass_base = pp.cbase + s_chunk * kChunkRadix;
 
     // ---- load (each slot of a wave is 256 consecutive bytes).  In a full
     // tile the values are loaded halfway through the ranking below, which
@@ -510,10 +843,14 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
                 s_whist[w * RADIX + d] = run;
                 run += c;
             }
+            // a partial tile's empty slots ranked as the last digit: they
+            // are not items (a chunk's first tile can be partial and still
+            // have successors that add this count)
+            if (d == RADIX - 1) run -= TILE - valid;
             tcount[r] = run;
             tsum += run;
             status_store(status + static_cast<size_t>(tile) * RADIX + d,
-                         St::make(tile == 0 ? kFlagIncl : kFlagAgg, run));
+                         St::make(static_cast<int32_t>(tile) == first ? kFlagIncl : kFlagAgg, run));
         }
     }
     const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
@@ -549,8 +886,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t d = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), d, RADIX, error_flag);
-            if (tile != 0)
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), first, d, RADIX, error_flag);
+            if (static_cast<int32_t>(tile) != first)
                 status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
             // LDS slot i of digit d goes to output slot s_gbase[d] + i
             s_gbase[d] = pass_base[d] + excl - dexcl[r];
@@ -560,8 +897,22 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
 
     // ---- scatter: consecutive LDS slots of one digit go to consecutive
     // output addresses.  The clamp to n - 1 costs one op and keeps a logic
-    // error from ever turning into a store outside the array.
-    if constexpr (STAGE) {
+    // error from ever turning into a store outside the array.  A full tile
+    // needs no per-slot guard, so the LDS reads of all slots are issued
+    // together (a guard per slot serialises them: 1 % slower passes).
+    if (STAGE && full) {
+        uint32_t sk[IPT], sp[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j)
+            sp[j] = min(s_gbase[__builtin_amdgcn_ubfe(sk[j], shift, width)] + j * BLOCK + tid, n - 1u);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            store_g<NT>(gelem<SMALL>(pp.dst_k, sp[j]), sk[j]);
+            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, sp[j]), s_stage_v[j * BLOCK + tid]);
+        }
+    } else if constexpr (STAGE) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const uint32_t i = j * BLOCK + tid;

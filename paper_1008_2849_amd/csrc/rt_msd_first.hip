@@ -54,6 +54,9 @@ MsdLayout make_msd_layout(size_t n, bool with_values) {
     }
     r.flags = RT_FLAG_NO_SKIP | (t.flags & RT_FLAG_NT_STORES);
     r.with_values = with_values;
+    // the partition pass runs in XCD chunks by position when the probe agrees
+    r.chunked = n >= kChunkMinItems;
+    r.probe = r.chunked;
     M.part = make_layout(n, r, true);
     size_t off = align256(M.part.total);
     M.tk = off;

@@ -135,12 +135,32 @@ static __global__ __launch_bounds__(1024) void k_seg_tiles(const SegDesc *__rest
 }
 
 // tile_seg[t] = the list entry that tile t belongs to (first_tile is
-// strictly increasing: every listed segment has at least one tile).
+// strictly increasing: every listed segment has at least one tile).  Block 0
+// also cuts the tile list into nchunks (1 or kChunks) chunks of about equal
+// tile counts at segment ends (a segment's tiles stay on one XCD).
 static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__restrict__ first_tile,
-                                                     const SegHeader *__restrict__ h,
-                                                     uint32_t *__restrict__ tile_seg) {
+                                                     SegHeader *__restrict__ h,
+                                                     uint32_t *__restrict__ tile_seg, uint32_t nchunks) {
     const uint32_t count = h->count[kSegLarge];
     const uint32_t total = h->total_tiles;
+    if (blockIdx.x == 0 && threadIdx.x <= kChunks) {
+        const uint32_t x = threadIdx.x;
+        uint32_t at = total;
+        if (x == 0) {
+            at = 0;
+        } else if (x < nchunks && count > 0) {
+            // the first segment start at or after x / kChunks of the tiles
+            const uint32_t target = static_cast<uint32_t>(static_cast<uint64_t>(x) * total / nchunks);
+            uint32_t lo = 0, hi = count;  // first_tile[count] = total
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (first_tile[mid] >= target) hi = mid;
+                else lo = mid + 1;
+            }
+            at = first_tile[lo];
+        }
+        h->chunk_start[x] = at;
+    }
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256) {
         uint32_t lo = 0, hi = count - 1;  // the last entry with first_tile <= t
         while (lo < hi) {
@@ -389,54 +409,12 @@ static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restri
 // tiled segments: one counting-sort pass over every listed segment
 // ---------------------------------------------------------------------------
 
-// The sum of one digit's counts over tiles [lo, tile) (see lookback_digit).
-template <typename S>
-__device__ __forceinline__ uint32_t seg_lookback_digit(const S *__restrict__ status, int32_t tile, int32_t lo,
-                                                       uint32_t digit, uint32_t *__restrict__ error_flag) {
-    using St = Status<S>;
-    uint32_t excl = 0;
-    int32_t at = tile - 1;
-    uint32_t idle = 0, nap = 1;
-    while (at >= lo) {
-        S w[kLookbackBatch];
-#pragma unroll
-        for (int b = 0; b < kLookbackBatch; ++b)
-            w[b] = (at - b >= lo) ? status_load(status + static_cast<size_t>(at - b) * kSegRadix + digit) : S(0);
-        bool finished = false, stalled = false;
-        int32_t consumed = 0;
-#pragma unroll
-        for (int b = 0; b < kLookbackBatch; ++b) {
-            if (finished || stalled || at - b < lo) continue;
-            const uint32_t f = St::flag(w[b]);
-            if (f == 0u) {
-                stalled = true;
-            } else {
-                excl += St::count(w[b]);
-                ++consumed;
-                if (f == kFlagIncl) finished = true;
-            }
-        }
-        if (finished) break;
-        at -= consumed;
-        if (stalled && consumed == 0) {
-            backoff(nap);
-            nap = nap < 16 ? nap * 2 : 16;
-            if (++idle > kLookbackSpinLimit) {
-                atomicOr(error_flag, kErrLookbackTimeout);
-                break;
-            }
-        } else {
-            nap = 1;
-        }
-    }
-    return excl;
-}
-
-// One block per tile (claimed in order from *tile_counter, as in
-// k_onesweep).  The tile's segment runs pass `pass` (or its own d.pass when
-// pass < 0): even passes read k/v and write tk/tv, odd passes the reverse,
-// so four passes leave the result in k/v and three in tk/tv.  Status words:
-// one per tile and digit, zeroed before the launch.
+// One block per tile, claimed as in k_onesweep from nchunks chunks of whole
+// segments (chunk_counter: the launch's kChunks counters, zeroed before it;
+// chunk bounds from k_seg_tilemap with the same nchunks).  The tile's segment runs pass `pass`
+// (or its own d.pass when pass < 0): even passes read k/v and write tk/tv,
+// odd passes the reverse, so four passes leave the result in k/v and three
+// in tk/tv.  Status words: one per tile and digit, zeroed before the launch.
 template <int BLOCK, int IPT, bool VALS, typename S>
 __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
                                                         const uint32_t *__restrict__ list,
@@ -444,8 +422,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
                                                         const uint32_t *__restrict__ tile_seg,
                                                         const SegHeader *__restrict__ h, int pass,
                                                         const uint32_t *__restrict__ base, S *__restrict__ status,
-                                                        uint32_t *__restrict__ tile_counter,
-                                                        uint32_t *__restrict__ error_flag) {
+                                                        uint32_t *__restrict__ chunk_counter,
+                                                        uint32_t *__restrict__ error_flag, uint32_t nchunks) {
     constexpr int RADIX = kSegRadix;
     constexpr int WAVES = BLOCK / 64;
     constexpr int TILE = BLOCK * IPT;
@@ -471,10 +449,13 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
     uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
 
     for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
-    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    if (tid == 0) {
+        uint32_t x = 0;
+        s_tile = claim_chunked(h->chunk_start, nchunks, chunk_counter, x);
+    }
     __syncthreads();
     const uint32_t tile = s_tile;
-    if (tile >= h->total_tiles) return;
+    if (tile >= h->total_tiles) return;  // kNoTile too
     const uint32_t e = tile_seg[tile];
     const SegDesc d = descs[list[e]];
     const uint32_t first = first_tile[e];
@@ -576,8 +557,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t dg = tid * R + r;
-            const uint32_t excl = seg_lookback_digit<S>(status, static_cast<int32_t>(tile),
-                                                        static_cast<int32_t>(first), dg, error_flag);
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), static_cast<int32_t>(first),
+                                                    dg, kSegRadix, error_flag);
             if (tile != first)
                 status_store(status + static_cast<size_t>(tile) * RADIX + dg, St::make(kFlagIncl, excl + tcount[r]));
             s_gbase[dg] = pbase[dg] + excl - dexcl[r];
@@ -585,12 +566,26 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
     }
     __syncthreads();
 
+    if (full) {  // no per-slot guard: the LDS reads of all slots issue together
+        uint32_t sk[IPT], sq[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j)
+            sq[j] = min(s_gbase[__builtin_amdgcn_ubfe(sk[j], shift, kSegBits)] + j * BLOCK + tid, n - 1u);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            *gelem<SMALL>(dst_k, sq[j]) = sk[j];
+            if constexpr (VALS) *gelem<SMALL>(dst_v, sq[j]) = s_stage_v[j * BLOCK + tid];
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t i = j * BLOCK + tid;
         const uint32_t k = s_stage_k[i];
         const uint32_t q = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, kSegBits)] + i, n - 1u);
-        if (full || i < valid) {
+        if (i < valid) {
             *gelem<SMALL>(dst_k, q) = k;
             if constexpr (VALS) *gelem<SMALL>(dst_v, q) = s_stage_v[i];
         }

@@ -434,7 +434,7 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_hlist, d_first_h, d_hh, stride,
                            m.max_tiles);
         hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
-                           d_hh, d_seg_h);
+                           d_hh, d_seg_h, 1u);
         hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_descs,
                            d_hlist, d_first_h, d_seg_h, d_hh, d_hist);
         hipLaunchKernelGGL(k_seg_plan, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
@@ -445,20 +445,22 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
                            d_status, P.tiles * kSegRadix);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_hp, stride,
                            m.max_tiles);
+        // XCD chunks when the step's tiled requests are long (see seg_chunk_count)
+        const uint32_t nchunks = seg_chunk_count(P.tiles * kSegTile, P.tiled);
         hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p,
-                           d_hp, d_seg_p);
-        uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, tile_ctr) / 4;
+                           d_hp, d_seg_p, nchunks);
+        uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, chunk_ctr) / 4;
         uint32_t *err = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, error) / 4;
         // a server holds one value layout (checked at submit), so one
         // kernel flavour serves every request of the step
         if (P.vals)
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
-                               ctr, err);
+                               ctr, err, nchunks);
         else
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
-                               ctr, err);
+                               ctr, err, nchunks);
     }
     for (uint32_t c = 0; c < s->classes.count; ++c)  // small requests, whole in LDS
         if (P.small[c])

@@ -132,8 +132,17 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
                              bits_class_of(r.width[p]), r.block, r.ipt);
     r.flags = c.flags;
     r.with_values = with_values != 0;
-    if (r.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER))
+    if (r.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER |
+                                         RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS))
         return set_error(RT_ERR_INVALID_ARG, "unknown flags 0x%x", r.flags);
+    if ((r.flags & RT_FLAG_ONE_CHAIN) && (r.flags & RT_FLAG_CHUNKS))
+        return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
+    // per-chunk counts need digits of at most 8 bits (kChunkRadix); below
+    // kChunkMinItems the sample would cost more than chunks can save
+    const bool forced = (r.flags & RT_FLAG_CHUNKS) != 0;
+    r.chunked = !(r.flags & RT_FLAG_ONE_CHAIN) && (forced || n >= kChunkMinItems);
+    for (uint32_t p = 0; p < r.num_passes; ++p) r.chunked = r.chunked && r.width[p] <= 8;
+    r.probe = r.chunked && !forced;
     if ((r.flags & RT_FLAG_DIRECT_SCATTER) && (r.flags & RT_FLAG_NT_STORES))
         return set_error(RT_ERR_UNSUPPORTED, "RT_FLAG_DIRECT_SCATTER with RT_FLAG_NT_STORES is not built");
     *out = r;
@@ -151,20 +160,27 @@ Layout make_layout(size_t n, const Resolved &r, bool direct) {
     const size_t tile = static_cast<size_t>(r.block) * r.ipt;
     const size_t tiles = (n + tile - 1) / tile;
     L.tiles = static_cast<uint32_t>(tiles);
+    L.grid_tiles = static_cast<uint32_t>(tiles + (r.chunked ? kChunks - 1 : 0));
     L.wide_status = n >= (static_cast<size_t>(1) << 30);
     const size_t sw = L.wide_status ? 8 : 4;
-    // the histograms and the lookback words are adjacent: one fill clears both
+    // the histograms and the lookback words are adjacent: one fill clears
+    // both.  Per-chunk histograms (kMaxPasses * kChunks * kChunkRadix words)
+    // fit the plain ones' space.
+    static_assert(kChunks * kChunkRadix <= kMaxRadix, "per-chunk histograms must fit the plain ones' space");
     size_t off = 0;
     L.hist = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
     L.status = off;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         L.status_pass[p] = off - L.status;
-        off += tiles * (static_cast<size_t>(1) << (r.width[p] <= 8 ? 8 : 11)) * sw;
+        off += L.grid_tiles * (static_cast<size_t>(1) << (r.width[p] <= 8 ? 8 : 11)) * sw;
     }
     off = align256(off);
     L.status_bytes = off - L.status;
-    L.ctr = off;     off += align256(sizeof(uint32_t) * (kMaxPasses + 1));  // tile counters, error word
+    // tile counters of the passes, the error word, kChunks tile counters per
+    // pass, the probe's choice
+    L.ctr = off;     off += align256(sizeof(uint32_t) * (kMaxPasses + 2 + kMaxPasses * kChunks));
     L.base = off;    off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.cbase = off;   off += align256(sizeof(uint32_t) * kMaxPasses * kChunks * kChunkRadix);
     L.plan = off;    off += align256(sizeof(SortPlan));
     L.t1k = L.t1v = L.t2k = L.t2v = 0;
     if (!direct) {
@@ -260,15 +276,15 @@ void prof_mark(hipStream_t stream, uint32_t kind) { prof_record(stream, kind); }
 
 template <int BITS, int BLOCK, int IPT>
 static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStream_t stream, const SortPlan *plan,
-                              int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr,
-                              uint32_t kind) {
-    const dim3 grid(L.tiles), block(BLOCK);
+                              int pass, uint32_t n, void *status, uint32_t *ctr, uint32_t kind) {
+    const dim3 grid(L.grid_tiles), block(BLOCK);
     uint32_t *err = ctr + kMaxPasses;
+    uint32_t *chunk_ctr = ctr + kMaxPasses + 1 + pass * kChunks;
     const bool nt = (flags & RT_FLAG_NT_STORES) != 0;
     const bool stage = (flags & RT_FLAG_DIRECT_SCATTER) == 0;
 #define RT_OS(V, NTV, S, STG)                                                                                      \
-    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG>), grid, block, 0, stream, plan, pass, n, base, \
-                       static_cast<S *>(status), ctr, err)
+    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG>), grid, block, 0, stream, plan, pass, n, \
+                       static_cast<S *>(status), chunk_ctr, err)
     if (!stage) {  // resolve_config rules out the non-temporal form here
         if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, false); else RT_OS(false, false, uint64_t, false); }
         else               { if (vals) RT_OS(true, false, uint32_t, false); else RT_OS(false, false, uint32_t, false); }
@@ -284,28 +300,40 @@ static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStr
 }
 
 static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, uint32_t flags,
-                        hipStream_t stream, const SortPlan *plan, int pass, uint32_t n, const uint32_t *base,
-                        void *status, uint32_t *ctr, uint32_t kind) {
-#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                     \
-    if (bits_class == B && block == BLK && ipt == I) {                                                 \
-        launch_pass_shape<B, BLK, I>(L, vals, flags, stream, plan, pass, n, base, status, ctr, kind); \
-        return;                                                                                        \
+                        hipStream_t stream, const SortPlan *plan, int pass, uint32_t n, void *status,
+                        uint32_t *ctr, uint32_t kind) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                               \
+    if (bits_class == B && block == BLK && ipt == I) {                                           \
+        launch_pass_shape<B, BLK, I>(L, vals, flags, stream, plan, pass, n, status, ctr, kind); \
+        return;                                                                                  \
     }
     RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
 #undef RT_SHAPE_LAUNCH
 }
 
-static HistArgs hist_args(const Resolved &r) {
+// Input items of pass 0's chunk x: [bound[x], bound[x + 1]), whole tiles,
+// kChunks nearly equal shares of the tile grid.
+static void pos_bounds(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]) {
+    const uint64_t tile = static_cast<uint64_t>(r.block) * r.ipt;
+    const uint64_t tiles = (n + tile - 1) / tile;
+    for (int x = 0; x <= kChunks; ++x) bound[x] = static_cast<uint32_t>(std::min<uint64_t>(n, x * tiles / kChunks * tile));
+    bound[kChunks] = static_cast<uint32_t>(n);
+}
+
+// chunked: per-chunk counts (see k_histogram), for sorts with r.chunked.
+static HistArgs hist_args(const Resolved &r, size_t n, bool chunked) {
     HistArgs ha{};
     ha.num_passes = r.num_passes;
     uint32_t off = 0;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         ha.shift[p] = r.shift[p];
         ha.mask[p] = (1u << r.width[p]) - 1u;
+        ha.cshift[p] = r.width[p] > 3 ? r.width[p] - 3 : 0;
         ha.lds_offset[p] = off;
-        off += 1u << r.width[p];
+        off += (chunked ? kChunks : 1) << r.width[p];
     }
     ha.total_bins = off;
+    if (chunked) pos_bounds(n, r, ha.pos_bound);
     return ha;
 }
 
@@ -324,38 +352,83 @@ static int hist_copies(uint32_t bins) {
     return c;
 }
 
-template <int C>
+template <int C, bool CHUNKED>
 static void launch_histogram_copies(const uint32_t *keys, uint32_t n, const HistArgs &ha, uint32_t *hist,
                                     hipStream_t stream) {
     constexpr int kBlock = 512;
     const size_t lds = static_cast<size_t>(C) * (ha.total_bins + 1) * sizeof(uint32_t);
     static std::once_flag once;  // dynamic LDS above 64 KiB must be allowed
     std::call_once(once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram<kBlock, C>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram<kBlock, C, CHUNKED>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
     });
     // about 8K keys per block (one batch per wave) for small n, at most four
     // blocks per CU for large n
     const uint32_t grid = grid_for(n, 8192, static_cast<uint32_t>(device_cu_count()) * 4);
-    hipLaunchKernelGGL((k_histogram<kBlock, C>), dim3(grid), dim3(kBlock), lds, stream, keys, n, ha, hist);
+    hipLaunchKernelGGL((k_histogram<kBlock, C, CHUNKED>), dim3(grid), dim3(kBlock), lds, stream, keys, n, ha,
+                       hist);
 }
 
-// hist_zeroed: the caller has cleared the counters already.
-void launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream,
-                       bool hist_zeroed) {
-    const HistArgs ha = hist_args(r);
+template <bool CHUNKED>
+static void launch_histogram_kernel(const uint32_t *keys, uint32_t n, const HistArgs &ha, uint32_t *hist,
+                                    hipStream_t stream) {
+    switch (hist_copies(ha.total_bins)) {
+        case 16: launch_histogram_copies<16, CHUNKED>(keys, n, ha, hist, stream); break;
+        case 8: launch_histogram_copies<8, CHUNKED>(keys, n, ha, hist, stream); break;
+        case 4: launch_histogram_copies<4, CHUNKED>(keys, n, ha, hist, stream); break;
+        case 2: launch_histogram_copies<2, CHUNKED>(keys, n, ha, hist, stream); break;
+        default: launch_histogram_copies<1, CHUNKED>(keys, n, ha, hist, stream); break;
+    }
+}
+
+template <int CC>
+static void launch_histogram_auto_copies(const uint32_t *keys, uint32_t n, const HistArgs &hp, const HistArgs &hc,
+                                         const uint32_t *mode, uint32_t *hist, hipStream_t stream) {
+    constexpr int kBlock = 512, kCP = 16;
+    const size_t lds = std::max(static_cast<size_t>(kCP) * (hp.total_bins + 1),
+                                static_cast<size_t>(CC) * (hc.total_bins + 1)) * sizeof(uint32_t);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram_auto<kBlock, kCP, CC>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    });
+    const uint32_t grid = grid_for(n, 8192, static_cast<uint32_t>(device_cu_count()) * 4);
+    hipLaunchKernelGGL((k_histogram_auto<kBlock, kCP, CC>), dim3(grid), dim3(kBlock), lds, stream, keys, n, hp, hc,
+                       mode, hist);
+}
+
+// hist_zeroed: the caller has cleared the counters already.  chunked: the
+// per-chunk counts of a sort with r.chunked, in place of the plain ones;
+// with mode set (r.probe) the probe kernel chooses between the two and
+// writes its choice to *mode.  Returns whether it did (else the counts are
+// per chunk exactly when chunked is set).
+bool launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint32_t *hist, hipStream_t stream,
+                       bool hist_zeroed, bool chunked, uint32_t *mode) {
+    const HistArgs ha = hist_args(r, n, chunked);
     if (!hist_zeroed) {
         hipLaunchKernelGGL(k_fill_zero, dim3(16), dim3(256), 0, stream, hist,
                            static_cast<size_t>(r.num_passes) * kMaxRadix);
         prof_mark(stream, RT_KIND_FILL);
     }
-    switch (hist_copies(ha.total_bins)) {
-        case 16: launch_histogram_copies<16>(keys, n, ha, hist, stream); break;
-        case 8: launch_histogram_copies<8>(keys, n, ha, hist, stream); break;
-        case 4: launch_histogram_copies<4>(keys, n, ha, hist, stream); break;
-        default: launch_histogram_copies<2>(keys, n, ha, hist, stream); break;
+    const HistArgs hp = hist_args(r, n, false);
+    const bool probe = chunked && mode != nullptr && hist_copies(hp.total_bins) == 16;
+    if (probe) {
+        hipLaunchKernelGGL(k_chunk_probe<1024>, dim3(1), dim3(1024), 0, stream, keys, n, ha, mode);
+        prof_mark(stream, RT_KIND_PROBE);
+        switch (hist_copies(ha.total_bins)) {
+            case 16: launch_histogram_auto_copies<16>(keys, n, hp, ha, mode, hist, stream); break;
+            case 8: launch_histogram_auto_copies<8>(keys, n, hp, ha, mode, hist, stream); break;
+            case 4: launch_histogram_auto_copies<4>(keys, n, hp, ha, mode, hist, stream); break;
+            case 2: launch_histogram_auto_copies<2>(keys, n, hp, ha, mode, hist, stream); break;
+            default: launch_histogram_auto_copies<1>(keys, n, hp, ha, mode, hist, stream); break;
+        }
+    } else if (chunked) {
+        launch_histogram_kernel<true>(keys, n, ha, hist, stream);
+    } else {
+        launch_histogram_kernel<false>(keys, n, ha, hist, stream);
     }
     prof_mark(stream, RT_KIND_HISTOGRAM);
+    return probe;
 }
 
 // The whole sort (direct == false) or one explicit pass (direct == true,
@@ -376,7 +449,8 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(fill_words, 256 * 16, 4096)), dim3(256), 0, stream, hist,
                        fill_words);
     prof_mark(stream, RT_KIND_FILL);
-    launch_histograms(keys, n, r, hist, stream, true);
+    uint32_t *mode = ctr + kMaxPasses + 1 + kMaxPasses * kChunks;
+    const bool probed = launch_histograms(keys, n, r, hist, stream, true, r.chunked, r.probe ? mode : nullptr);
 
     PlanArgs a{};
     a.num_passes = r.num_passes;
@@ -386,6 +460,12 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     }
     a.no_skip = (r.flags & RT_FLAG_NO_SKIP) ? 1u : 0u;
     a.n = n;
+    a.tile = static_cast<uint32_t>(r.block * r.ipt);
+    a.chunked = r.chunked ? 1u : 0u;
+    if (r.chunked) pos_bounds(n, r, a.pos_bound);
+    a.cbase = reinterpret_cast<uint32_t *>(ws + L.cbase);
+    a.chunk_ctr = ctr + kMaxPasses + 1;
+    a.mode = probed ? mode : nullptr;
     a.user_k = keys;
     a.user_v = r.with_values ? vals : nullptr;
     if (direct) {
@@ -402,8 +482,7 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
 
     for (uint32_t p = 0; p < r.num_passes; ++p)
         launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, r.flags, stream, plan,
-                    static_cast<int>(p), n, base + p * kMaxRadix, status + L.status_pass[p], ctr,
-                    pass_kind + p);
+                    static_cast<int>(p), n, status + L.status_pass[p], ctr, pass_kind + p);
 
     if (!direct && (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP))) {
         const uint32_t grid_c = grid_for(n, 256 * 8, static_cast<uint32_t>(device_cu_count()) * 8);
@@ -496,7 +575,7 @@ extern "C" rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const r
     rt_status s = resolve_config(cfg, n < 2 ? 2 : n, 0, &r);
     if (s != RT_OK) return s;
     prof_begin(stream);
-    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream, false);
+    launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream, false, false, nullptr);
     return finish_call(stream, "rt_digit_histograms");
 }
 

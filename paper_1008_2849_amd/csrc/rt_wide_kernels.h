@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t d = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), d, RADIX, error_flag);
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), 0, d, RADIX, error_flag);
             if (tile != 0)
                 status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
             s_gbase[d] = pass_base[d] + excl - dexcl[r];
@@ -257,13 +257,28 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
     }
     __syncthreads();
 
-    // scatter; the clamp keeps a logic error from storing outside the array
+    // scatter; the clamp keeps a logic error from storing outside the array.
+    // A full tile needs no per-slot guard, so its LDS reads issue together.
+    if (full) {
+        uint64_t sk[IPT];
+        uint32_t sp[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) sp[j] = min(s_gbase[digit64(sk[j], shift, mask)] + j * BLOCK + tid, n - 1u);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            dst_k[sp[j]] = sk[j];
+            if constexpr (VALS) dst_v[sp[j]] = s_stage_v[j * BLOCK + tid];
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t i = j * BLOCK + tid;
         const uint64_t k = s_stage_k[i];
         const uint32_t p = min(s_gbase[digit64(k, shift, mask)] + i, n - 1u);
-        if (full || i < valid) {
+        if (i < valid) {
             dst_k[p] = k;
             if constexpr (VALS) dst_v[p] = s_stage_v[i];
         }

@@ -82,6 +82,8 @@ def test_config_validation(so):
     assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
     c.flags = 0x100  # unknown
     assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    c.flags = _lib.RT_FLAG_ONE_CHAIN | _lib.RT_FLAG_CHUNKS  # exclude each other
+    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
 
 
 def test_workspace_bytes(so):

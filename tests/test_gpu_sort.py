@@ -12,7 +12,8 @@ import pytest
 import oracle
 import paper_1008_2849_amd as rts
 from paper_1008_2849_amd import inputs
-from paper_1008_2849_amd.api import Config, FLAG_DIRECT_SCATTER, FLAG_NO_SKIP, FLAG_NT_STORES
+from paper_1008_2849_amd.api import (Config, FLAG_CHUNKS, FLAG_DIRECT_SCATTER, FLAG_NO_SKIP, FLAG_NT_STORES,
+                                     FLAG_ONE_CHAIN)
 from gpu_util import announce, sync, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -149,6 +150,79 @@ def test_direct_scatter_configs(widths, shape):
     cfg = Config(widths, shape[0], shape[1], FLAG_DIRECT_SCATTER)
     assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {shape}")
     assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k, None, widths), f"keys {widths} {shape}")
+
+
+@pytest.mark.parametrize("dist", list(_dist_cases(8).keys()))
+def test_chunk_flags(dist):
+    """XCD chunks forced at a size below the default's threshold, and one
+    lookback chain per pass, both give the oracle's result, with and without
+    pass skipping, keys only and pairs."""
+    n = 3 * TILE * 8 + 999
+    announce(f"chunk flags dist={dist} n={n}")
+    k = _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    for flags in (FLAG_CHUNKS, FLAG_CHUNKS | FLAG_NO_SKIP, FLAG_ONE_CHAIN, FLAG_ONE_CHAIN | FLAG_NO_SKIP):
+        cfg = Config((8, 8, 8, 8), 1024, 16, flags)
+        assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v), f"flags={flags} {dist}")
+    cfg = Config((8, 8, 8, 8), 1024, 16, FLAG_CHUNKS)
+    assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k), f"keys chunks {dist}")
+
+
+@pytest.mark.parametrize("dist", ["uniform", "and4", "zipf16", "top_a5", "low_byte_only", "sorted"])
+def test_probed_sizes(dist):
+    """At 2^22 items and above the default samples the keys and picks XCD
+    chunks (uniform, constant top byte) or one chain (skewed keys): the
+    result is the oracle's either way."""
+    n = (1 << 22) + 77
+    announce(f"probed dist={dist} n={n}")
+    k = inputs.uniform_keys(n, 700) if dist == "uniform" else _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), dist)
+
+
+@pytest.mark.parametrize("skip_pattern", [1, 2, 5, 6, 9, 14])
+def test_chunks_with_skipped_passes(skip_pattern):
+    """A skipped pass (constant digit) leaves the next pass a single chunk:
+    its chunks come from the skipped digit's ranges."""
+    n = 40 * TILE + 5
+    announce(f"chunks skip pattern {skip_pattern:04b} n={n}")
+    k = inputs.uniform_keys(n, 600 + skip_pattern)
+    for p in range(4):
+        if skip_pattern >> p & 1:
+            k = (k & ~np.uint32(0xFF << (8 * p))) | np.uint32((0x3C + p) << (8 * p))
+    v = inputs.index_values(n)
+    cfg = Config((8, 8, 8, 8), 1024, 16, FLAG_CHUNKS)
+    assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v), f"pattern {skip_pattern}")
+
+
+CHUNK_WIDTHS = [(1, 2, 3, 8, 8, 5, 5), (3, 3, 3, 3, 4, 8, 8), (8, 1, 7, 8, 8), (2, 6, 8, 8, 8)]
+
+
+@pytest.mark.parametrize("widths", CHUNK_WIDTHS, ids=["-".join(map(str, w)) for w in CHUNK_WIDTHS])
+@pytest.mark.parametrize("dist", ["uniform", "and2", "zipf16"])
+def test_chunks_narrow_digits(widths, dist):
+    """Digits narrower than 3 bits give their successor pass fewer than 8
+    chunks (one per digit value); the chunks of every pass still tile its
+    input once."""
+    n = 9 * 512 * 16 + 321
+    announce(f"chunks widths={widths} dist={dist} n={n}")
+    k = inputs.uniform_keys(n, 77) if dist == "uniform" else _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    cfg = Config(widths, 512, 16, FLAG_CHUNKS)
+    assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {dist}")
+    assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k, None, widths), f"keys {widths} {dist}")
+
+
+@pytest.mark.parametrize("n", [2, 1000, TILE - 1, TILE * 5 + 3, TILE * 8 - 1, TILE * 8, TILE * 8 + 1, TILE * 9 + 5,
+                               TILE * 15, TILE * 23 + 4097])
+def test_chunk_bounds_first_pass(n):
+    """Sizes around multiples of 8 tiles: the first pass's chunks by position
+    have equal or unequal tile counts, empty ones included for small n."""
+    announce(f"chunk bounds n={n}")
+    k = inputs.uniform_keys(n, 500 + n % 101)
+    v = inputs.index_values(n)
+    assert_same(gpu_sort(k, v, Config((8, 8, 8, 8), 1024, 16, FLAG_CHUNKS)), oracle.lsd_sort(k, v), f"n={n}")
+    assert_same(gpu_sort(k, v, Config((8, 8, 8, 8), 256, 16, FLAG_CHUNKS)), oracle.lsd_sort(k, v), f"4K n={n}")
 
 
 @pytest.mark.parametrize("skip_pattern", range(16))
