@@ -68,7 +68,7 @@ typedef enum rt_status {
  * that XCD, and each chunk has its own lookback chain and output start per
  * digit (from per-chunk counts taken by the upfront histogram read), so the
  * ends of neighbouring digit runs, which share cache lines, are written
- * through one L2.  By default a sort of at least 2^22 items samples its keys
+ * through one L2.  By default a sort of at least 2^25 items samples its keys
  * first and uses chunks unless they would be badly unbalanced or the
  * per-chunk counting would contend on a few frequent digits (skewed keys).
  * RT_FLAG_ONE_CHAIN: never use chunks (one lookback chain per pass).

@@ -21,7 +21,7 @@ constexpr int kMaxRadix = 1 << kMaxBits;
 // written through one L2 and leave it as whole lines.
 constexpr int kChunks = 8;
 constexpr int kChunkRadix = 256;  // row stride of the per-chunk tables (digits of at most 8 bits)
-constexpr size_t kChunkMinItems = static_cast<size_t>(1) << 22;  // smaller sorts: one chain per pass
+constexpr size_t kChunkMinItems = static_cast<size_t>(1) << 25;  // smaller sorts: one chain per pass
 
 // Source/destination of one executed counting-sort pass.  Written on the
 // device by the planning kernel once the histograms are known, so that pass

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_histogram_auto(const uint32_t *__rest
 // the samples (unless the pass's digit is constant: batches of equal digits
 // are counted with one add), or a chunk above 1/4 (unless digit p - 1 is
 // constant: then the pass has a single chunk and loses nothing).
-constexpr uint32_t kProbeSamples = 16384;  // 256 runs of 64 consecutive keys
+constexpr uint32_t kProbeSamples = 8192;  // 128 runs of 64 consecutive keys
 
 template <typename T, typename F>
 __device__ __forceinline__ T wave_reduce(T v, F op) {
@@ -390,7 +390,12 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restric
         for (uint32_t i = tid; i < (kChunks << w); i += BLOCK) {
             const uint32_t c = s_tab[i];
             m = max(m, c);
-            if (c != 0u) atomicAdd(&s_chunk[i >> w], c);
+            if (w >= 6u) {  // a wave's 64 entries share a chunk: one add per wave
+                const uint32_t t = wave_reduce(c, [](uint32_t x, uint32_t y) { return x + y; });
+                if (lane == 0) atomicAdd(&s_chunk[i >> w], t);
+            } else if (c != 0u) {
+                atomicAdd(&s_chunk[i >> w], c);
+            }
         }
         m = wave_reduce(m, [](uint32_t x, uint32_t y) { return max(x, y); });
         if (lane == 0) atomicMax(&s_max, m);

@@ -170,10 +170,10 @@ def test_chunk_flags(dist):
 
 @pytest.mark.parametrize("dist", ["uniform", "and4", "zipf16", "top_a5", "low_byte_only", "sorted"])
 def test_probed_sizes(dist):
-    """At 2^22 items and above the default samples the keys and picks XCD
+    """At 2^25 items and above the default samples the keys and picks XCD
     chunks (uniform, constant top byte) or one chain (skewed keys): the
     result is the oracle's either way."""
-    n = (1 << 22) + 77
+    n = (1 << 25) + 77
     announce(f"probed dist={dist} n={n}")
     k = inputs.uniform_keys(n, 700) if dist == "uniform" else _dist_cases(n)[dist]
     v = inputs.index_values(n)
