@@ -115,10 +115,16 @@ struct SegLayout {
 };
 
 // Chunks of a segmented pass's tile list: kChunks when the segments hold
-// kSegChunkMinTiles tiles or more on average (items / segments), else 1.
+// kSegChunkMinTiles tiles or more on average (items / segments) and there
+// are at least kSegChunkMinSegments of them, else 1.  Chunks end at segment
+// ends, so they balance only with many segments per chunk; short segments
+// (many partial tiles, short lookback chains) measured faster on one chain.
 constexpr uint32_t kSegChunkMinTiles = 16;
+constexpr uint32_t kSegChunkMinSegments = 16 * kChunks;
 inline uint32_t seg_chunk_count(size_t items, size_t segments) {
-    return segments > 0 && items / segments >= static_cast<size_t>(kSegChunkMinTiles) * kSegTile ? kChunks : 1u;
+    return segments >= kSegChunkMinSegments && items / segments >= static_cast<size_t>(kSegChunkMinTiles) * kSegTile
+               ? kChunks
+               : 1u;
 }
 
 struct SegPointers {
