@@ -154,7 +154,8 @@ rt_status rt_sort_pairs64(uint64_t *keys, uint32_t *vals, size_t n, hipStream_t 
  * tiles): digit_bits must sum to 64, each 1..RT_MAX_DIGIT_BITS; tile shapes
  * built are 1024x8 and 512x16 for digits of up to 8 bits and 512x8 for
  * wider ones (correct, but several times slower than 8-bit digits); flags:
- * 0 or RT_FLAG_NO_SKIP (anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
+ * RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN, RT_FLAG_CHUNKS (XCD chunks as for 32-bit
+ * keys; anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
  * 256-byte aligned, or NULL for the library's per-stream cache; with a
  * caller workspace the call only enqueues kernels.  Errors and stream
  * behaviour as for rt_sort_ex.

@@ -335,8 +335,8 @@ __device__ __forceinline__ T wave_reduce(T v, F op) {
     return v;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restrict__ keys, uint32_t n, HistArgs ha,
+template <int BLOCK, typename K = uint32_t>
+__global__ __launch_bounds__(BLOCK) void k_chunk_probe(const K *__restrict__ keys, uint32_t n, HistArgs ha,
                                                        uint32_t *__restrict__ mode) {
     constexpr int WAVES = BLOCK / 64;
     constexpr int RUNS = static_cast<int>(kProbeSamples / 64);
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restric
     __shared__ uint32_t s_max, s_bad;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     // runs of consecutive keys: a few hundred pages touched, not thousands
-    uint32_t k[PER];
+    K k[PER];  // 32- or 64-bit keys
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const uint64_t start = static_cast<uint64_t>(wave * PER + j) * n / RUNS;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restric
         uint32_t lo = ~0u, hi = 0u;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t d = (k[j] >> ha.shift[p]) & ha.mask[p];
+            const uint32_t d = static_cast<uint32_t>(k[j] >> ha.shift[p]) & ha.mask[p];
             lo = min(lo, d);
             hi = max(hi, d);
         }
@@ -382,8 +382,8 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const uint32_t *__restric
         const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t x = p == 0 ? 0u : ((k[j] >> ha.shift[p - 1]) & ha.mask[p - 1]) >> ha.cshift[p - 1];
-            atomicAdd(&s_tab[(x << w) | ((k[j] >> ha.shift[p]) & ha.mask[p])], 1u);
+            const uint32_t x = p == 0 ? 0u : (static_cast<uint32_t>(k[j] >> ha.shift[p - 1]) & ha.mask[p - 1]) >> ha.cshift[p - 1];
+            atomicAdd(&s_tab[(x << w) | (static_cast<uint32_t>(k[j] >> ha.shift[p]) & ha.mask[p])], 1u);
         }
         __syncthreads();
         uint32_t m = 0;

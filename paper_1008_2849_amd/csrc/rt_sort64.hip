@@ -2,6 +2,7 @@
 // checks, configuration, workspace layout, launch sequence and the C ABI.
 // The planning kernel, the lookback words and the buffer scheme are those of
 // the 32-bit sort; keys are 8 bytes and values 0, 4 or 8 bytes per item.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -60,8 +61,12 @@ rt_status resolve64(const rt_config *cfg, uint32_t value_words, Resolved *out) {
         if (cfg->block_threads) c.block_threads = cfg->block_threads;
         if (cfg->items_per_thread) c.items_per_thread = cfg->items_per_thread;
     }
-    if (c.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP))
-        return set_error(RT_ERR_UNSUPPORTED, "64-bit keys: only RT_FLAG_NO_SKIP is supported (flags 0x%x)", c.flags);
+    if (c.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS))
+        return set_error(RT_ERR_UNSUPPORTED,
+                         "64-bit keys: only RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS are supported (flags 0x%x)",
+                         c.flags);
+    if ((c.flags & RT_FLAG_ONE_CHAIN) && (c.flags & RT_FLAG_CHUNKS))
+        return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
     if (c.num_passes < 1 || c.num_passes > kMaxPasses)
         return set_error(RT_ERR_INVALID_ARG, "num_passes %u outside 1..%d", c.num_passes, kMaxPasses);
     Resolved r{};
@@ -95,12 +100,23 @@ rt_status resolve64(const rt_config *cfg, uint32_t value_words, Resolved *out) {
     return RT_OK;
 }
 
+// XCD chunks for a sort of n items (as for 32-bit keys: digits of at most 8
+// bits, the probe from kChunkMinItems items unless a flag decides).
+void chunk_mode64(size_t n, Resolved *r) {
+    const bool forced = (r->flags & RT_FLAG_CHUNKS) != 0;
+    r->chunked = !(r->flags & RT_FLAG_ONE_CHAIN) && (forced || n >= kChunkMinItems);
+    for (uint32_t p = 0; p < r->num_passes; ++p) r->chunked = r->chunked && r->width[p] <= 8;
+    r->probe = r->chunked && !forced;
+}
+
 struct Layout64 {
     size_t hist, ctr, base, plan, status, status_bytes;
     size_t status_pass[kMaxPasses];
     size_t t1k, t1v, t2k, t2v;
+    size_t cbase;
     size_t total;
     uint32_t tiles;
+    uint32_t grid_tiles;  // blocks per pass: the grid cut at up to kChunks - 1 chunk ends
     bool wide_status;
 };
 
@@ -109,20 +125,24 @@ Layout64 make_layout64(size_t n, const Resolved &r, uint32_t value_words) {
     const size_t tile = static_cast<size_t>(r.block) * r.ipt;
     const size_t tiles = (n + tile - 1) / tile;
     L.tiles = static_cast<uint32_t>(tiles);
+    L.grid_tiles = static_cast<uint32_t>(tiles + (r.chunked ? kChunks - 1 : 0));
     L.wide_status = n >= (static_cast<size_t>(1) << 30);
     const size_t sw = L.wide_status ? 8 : 4;
-    // the histograms and the lookback words are adjacent: one fill clears both
+    // the histograms (plain or per chunk) and the lookback words are
+    // adjacent: one fill clears both
     size_t off = 0;
     L.hist = off;  off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
     L.status = off;
     for (uint32_t p = 0; p < r.num_passes; ++p) {
         L.status_pass[p] = off - L.status;
-        off += tiles * (static_cast<size_t>(1) << (r.width[p] <= 8 ? 8 : 11)) * sw;
+        off += L.grid_tiles * (static_cast<size_t>(1) << (r.width[p] <= 8 ? 8 : 11)) * sw;
     }
     off = align256(off);
     L.status_bytes = off - L.status;
-    L.ctr = off;   off += align256(sizeof(uint32_t) * (kMaxPasses + 1));
+    // tile counters, the error word, kChunks tile counters per pass, the probe's choice
+    L.ctr = off;   off += align256(sizeof(uint32_t) * (kMaxPasses + 2 + kMaxPasses * kChunks));
     L.base = off;  off += align256(sizeof(uint32_t) * kMaxPasses * kMaxRadix);
+    L.cbase = off; off += align256(sizeof(uint32_t) * kMaxPasses * kChunks * kChunkRadix);
     L.plan = off;  off += align256(sizeof(SortPlan));
     const bool need_t2 = (r.num_passes & 1u) || !(r.flags & RT_FLAG_NO_SKIP);
     const size_t karr = align256(n * sizeof(uint64_t));
@@ -146,6 +166,68 @@ uint32_t grid_for(size_t items, size_t per_block, uint32_t cap) {
     return static_cast<uint32_t>(g);
 }
 
+// Histogram arguments of a 64-bit sort; chunked: per-chunk counts (tables
+// kChunks times longer, chunks of pass 0 by position).
+void pos_bounds64(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]) {
+    const uint64_t tile = static_cast<uint64_t>(r.block) * r.ipt;
+    const uint64_t tiles = (n + tile - 1) / tile;
+    for (int x = 0; x <= kChunks; ++x) bound[x] = static_cast<uint32_t>(std::min<uint64_t>(n, x * tiles / kChunks * tile));
+    bound[kChunks] = static_cast<uint32_t>(n);
+}
+
+HistArgs hist_args64(const Resolved &r, size_t n, bool chunked) {
+    HistArgs ha{};
+    ha.num_passes = r.num_passes;
+    uint32_t off = 0;
+    for (uint32_t p = 0; p < r.num_passes; ++p) {
+        ha.shift[p] = r.shift[p];
+        ha.mask[p] = (1u << r.width[p]) - 1u;
+        ha.cshift[p] = r.width[p] > 3 ? r.width[p] - 3 : 0;
+        ha.lds_offset[p] = off;
+        off += (chunked ? kChunks : 1) << r.width[p];
+    }
+    ha.total_bins = off;
+    if (chunked) pos_bounds64(n, r, ha.pos_bound);
+    return ha;
+}
+
+// lane-class copies: as many as fit in 72 KiB of padded rows, at most 8
+int copies64(uint32_t bins) {
+    int c = 8;
+    while (c > 1 && static_cast<size_t>(c) * (bins + 1) * sizeof(uint32_t) > 72 * 1024) c /= 2;
+    return c;
+}
+
+template <int C>
+void launch_histogram64_chunked(const uint64_t *keys, uint32_t n, const HistArgs &hc, uint32_t *hist,
+                                hipStream_t stream) {
+    constexpr int kBlock = 512;
+    const size_t lds = static_cast<size_t>(C) * (hc.total_bins + 1) * sizeof(uint32_t);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram64_chunked<kBlock, C>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    });
+    const uint32_t grid = grid_for(n, 4096, static_cast<uint32_t>(device_cu_count()) * 4);
+    hipLaunchKernelGGL((k_histogram64_chunked<kBlock, C>), dim3(grid), dim3(kBlock), lds, stream, keys, n, hc, hist);
+}
+
+template <int CC>
+void launch_histogram64_auto(const uint64_t *keys, uint32_t n, const HistArgs &hp, const HistArgs &hc,
+                             const uint32_t *mode, uint32_t *hist, hipStream_t stream) {
+    constexpr int kBlock = 512, kCP = 8;
+    const size_t lds = std::max(static_cast<size_t>(kCP) * (hp.total_bins + 1),
+                                static_cast<size_t>(CC) * (hc.total_bins + 1)) * sizeof(uint32_t);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_histogram64_auto<kBlock, kCP, CC>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    });
+    const uint32_t grid = grid_for(n, 4096, static_cast<uint32_t>(device_cu_count()) * 4);
+    hipLaunchKernelGGL((k_histogram64_auto<kBlock, kCP, CC>), dim3(grid), dim3(kBlock), lds, stream, keys, n, hp, hc,
+                       mode, hist);
+}
+
 template <int C>
 void launch_histogram64_copies(const uint64_t *keys, uint32_t n, const HistArgs &ha, uint32_t *hist,
                                hipStream_t stream) {
@@ -162,12 +244,13 @@ void launch_histogram64_copies(const uint64_t *keys, uint32_t n, const HistArgs 
 
 template <int BITS, int BLOCK, int IPT>
 void launch_pass64_shape(const Layout64 &L, uint32_t vw, hipStream_t stream, const SortPlan *plan, int pass,
-                         uint32_t n, const uint32_t *base, void *status, uint32_t *ctr) {
-    const dim3 grid(L.tiles), block(BLOCK);
+                         uint32_t n, void *status, uint32_t *ctr) {
+    const dim3 grid(L.grid_tiles), block(BLOCK);
     uint32_t *err = ctr + kMaxPasses;
-#define RT_OS64(V, S)                                                                                   \
-    hipLaunchKernelGGL((k_onesweep64<BITS, BLOCK, IPT, V, S>), grid, block, 0, stream, plan, pass, n, base, \
-                       static_cast<S *>(status), ctr, err)
+    uint32_t *chunk_ctr = ctr + kMaxPasses + 1 + pass * kChunks;
+#define RT_OS64(V, S)                                                                                      \
+    hipLaunchKernelGGL((k_onesweep64<BITS, BLOCK, IPT, V, S>), grid, block, 0, stream, plan, pass, n, \
+                       static_cast<S *>(status), chunk_ctr, err)
     if (L.wide_status) {
         if (vw == 2) RT_OS64(2, uint64_t); else if (vw == 1) RT_OS64(1, uint64_t); else RT_OS64(0, uint64_t);
     } else {
@@ -178,11 +261,11 @@ void launch_pass64_shape(const Layout64 &L, uint32_t vw, hipStream_t stream, con
 }
 
 void launch_pass64(int bits_class, int block, int ipt, const Layout64 &L, uint32_t vw, hipStream_t stream,
-                   const SortPlan *plan, int pass, uint32_t n, const uint32_t *base, void *status, uint32_t *ctr) {
-#define RT_SHAPE_LAUNCH(B, BLK, I)                                                          \
-    if (bits_class == B && block == BLK && ipt == I) {                                      \
-        launch_pass64_shape<B, BLK, I>(L, vw, stream, plan, pass, n, base, status, ctr);    \
-        return;                                                                             \
+                   const SortPlan *plan, int pass, uint32_t n, void *status, uint32_t *ctr) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                    \
+    if (bits_class == B && block == BLK && ipt == I) {                                \
+        launch_pass64_shape<B, BLK, I>(L, vw, stream, plan, pass, n, status, ctr);    \
+        return;                                                                       \
     }
     RT64_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
 #undef RT_SHAPE_LAUNCH
@@ -204,23 +287,38 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
                        fill_words);
     prof_mark(stream, RT_KIND_FILL);
 
-    HistArgs ha{};
-    ha.num_passes = r.num_passes;
-    uint32_t off = 0;
-    for (uint32_t p = 0; p < r.num_passes; ++p) {
-        ha.shift[p] = r.shift[p];
-        ha.mask[p] = (1u << r.width[p]) - 1u;
-        ha.lds_offset[p] = off;
-        off += 1u << r.width[p];
-    }
-    ha.total_bins = off;
-    int c = 8;  // lane-class copies: as many as fit in 64 KiB of padded rows
-    while (c > 1 && static_cast<size_t>(c) * (ha.total_bins + 1) * sizeof(uint32_t) > 72 * 1024) c /= 2;
-    switch (c) {
-        case 8: launch_histogram64_copies<8>(keys, n, ha, hist, stream); break;
-        case 4: launch_histogram64_copies<4>(keys, n, ha, hist, stream); break;
-        case 2: launch_histogram64_copies<2>(keys, n, ha, hist, stream); break;
-        default: launch_histogram64_copies<1>(keys, n, ha, hist, stream); break;
+    const HistArgs ha = hist_args64(r, n, false);
+    uint32_t *mode = ctr + kMaxPasses + 1 + kMaxPasses * kChunks;
+    uint32_t pos_bound[kChunks + 1] = {};
+    if (r.chunked) pos_bounds64(n, r, pos_bound);
+    bool probed = false;
+    if (r.chunked) {
+        const HistArgs hc = hist_args64(r, n, true);
+        if (r.probe && copies64(ha.total_bins) == 8) {
+            hipLaunchKernelGGL((k_chunk_probe<1024, uint64_t>), dim3(1), dim3(1024), 0, stream, keys, n, hc, mode);
+            prof_mark(stream, RT_KIND_PROBE);
+            switch (copies64(hc.total_bins)) {
+                case 8: launch_histogram64_auto<8>(keys, n, ha, hc, mode, hist, stream); break;
+                case 4: launch_histogram64_auto<4>(keys, n, ha, hc, mode, hist, stream); break;
+                case 2: launch_histogram64_auto<2>(keys, n, ha, hc, mode, hist, stream); break;
+                default: launch_histogram64_auto<1>(keys, n, ha, hc, mode, hist, stream); break;
+            }
+            probed = true;
+        } else {
+            switch (copies64(hc.total_bins)) {
+                case 8: launch_histogram64_chunked<8>(keys, n, hc, hist, stream); break;
+                case 4: launch_histogram64_chunked<4>(keys, n, hc, hist, stream); break;
+                case 2: launch_histogram64_chunked<2>(keys, n, hc, hist, stream); break;
+                default: launch_histogram64_chunked<1>(keys, n, hc, hist, stream); break;
+            }
+        }
+    } else {
+        switch (copies64(ha.total_bins)) {
+            case 8: launch_histogram64_copies<8>(keys, n, ha, hist, stream); break;
+            case 4: launch_histogram64_copies<4>(keys, n, ha, hist, stream); break;
+            case 2: launch_histogram64_copies<2>(keys, n, ha, hist, stream); break;
+            default: launch_histogram64_copies<1>(keys, n, ha, hist, stream); break;
+        }
     }
     prof_mark(stream, RT_KIND_HISTOGRAM);
 
@@ -232,6 +330,12 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
     }
     a.no_skip = (r.flags & RT_FLAG_NO_SKIP) ? 1u : 0u;
     a.n = n;
+    a.tile = static_cast<uint32_t>(r.block * r.ipt);
+    a.chunked = r.chunked ? 1u : 0u;
+    for (int x = 0; x <= kChunks; ++x) a.pos_bound[x] = pos_bound[x];
+    a.cbase = reinterpret_cast<uint32_t *>(ws + L.cbase);
+    a.chunk_ctr = ctr + kMaxPasses + 1;
+    a.mode = probed ? mode : nullptr;
     a.user_k = reinterpret_cast<uint32_t *>(keys);
     a.user_v = vw ? vals : nullptr;
     a.t1_k = reinterpret_cast<uint32_t *>(ws + L.t1k);
@@ -243,7 +347,7 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
 
     for (uint32_t p = 0; p < r.num_passes; ++p)
         launch_pass64(bits_class_of(r.width[p]), r.block, r.ipt, L, vw, stream, plan, static_cast<int>(p), n,
-                      base + p * kMaxRadix, status + L.status_pass[p], ctr);
+                      status + L.status_pass[p], ctr);
 
     if (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP)) {
         const uint32_t grid_c = grid_for(2 * static_cast<size_t>(n), 256 * 8, cus * 8);
@@ -285,6 +389,7 @@ extern "C" size_t rt_workspace_bytes64(size_t n, uint32_t value_bytes, const rt_
     if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8) return 0;
     Resolved r;
     if (resolve64(cfg, value_bytes / 4, &r) != RT_OK) return 0;
+    chunk_mode64(n, &r);
     return make_layout64(n, r, value_bytes / 4).total;
 }
 
@@ -295,6 +400,7 @@ extern "C" rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_byt
     const uint32_t vw = value_bytes / 4;
     Resolved r;
     s = resolve64(cfg, vw, &r);
+    if (s == RT_OK) chunk_mode64(n, &r);
     if (s != RT_OK) return s;
     const Layout64 L = make_layout64(n, r, vw);
     void *ws = workspace;

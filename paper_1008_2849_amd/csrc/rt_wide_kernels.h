@@ -37,13 +37,15 @@ __device__ __forceinline__ uint32_t digit64(uint64_t key, uint32_t shift, uint32
 
 // As k_histogram: C lane-class copies of every pass's counters in padded LDS
 // rows, and a wave batch of 64 * U keys that shares a pass's digit counted
-// with one add.  hist[p * kMaxRadix + d] must start at zero.
-template <int BLOCK, int C>
-__global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restrict__ keys, uint32_t n, HistArgs ha,
-                                                       uint32_t *__restrict__ hist) {
+// with one add.  hist[p * kMaxRadix + d] must start at zero.  CHUNKED: the
+// per-chunk counts of k_histogram's CHUNKED form, for the XCD chunks of the
+// 64-bit passes (a wave batch of 512 keys never straddles a chunk of pass 0:
+// the bounds are multiples of the 8K tile).
+template <int BLOCK, int C, bool CHUNKED>
+__device__ __forceinline__ void histogram64_body(const uint64_t *__restrict__ keys, uint32_t n, const HistArgs &ha,
+                                                 uint32_t *__restrict__ hist, uint32_t *s_h) {
     constexpr int WAVES = BLOCK / 64;
     constexpr int U = 8;
-    extern __shared__ uint32_t s_h[];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
@@ -69,11 +71,26 @@ __global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restric
             for (int p = 0; p < kMaxPasses; ++p) {
                 if (p >= static_cast<int>(ha.num_passes)) break;
                 uint32_t *hp = h + ha.lds_offset[p];
-                if (__builtin_amdgcn_ballot_w64(digit64(differ, ha.shift[p], ha.mask[p]) != 0u) == 0u) {
-                    if (lane == 0) atomicAdd(&hp[digit64(k0, ha.shift[p], ha.mask[p])], static_cast<uint32_t>(64 * U));
-                } else {
+                const uint32_t sh = ha.shift[p], m = ha.mask[p];
+                if (!CHUNKED || p == 0) {
+                    if constexpr (CHUNKED) hp += pos_chunk(ha, base) * (m + 1u);
+                    if (__builtin_amdgcn_ballot_w64(digit64(differ, sh, m) != 0u) == 0u) {
+                        if (lane == 0) atomicAdd(&hp[digit64(k0, sh, m)], static_cast<uint32_t>(64 * U));
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < U; ++u) atomicAdd(&hp[digit64(k[u], ha.shift[p], ha.mask[p])], 1u);
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[digit64(k[u], sh, m)], 1u);
+                    }
+                } else {
+                    const uint32_t cs = ha.shift[p - 1] + ha.cshift[p - 1];
+                    const uint32_t cm = ha.mask[p - 1] >> ha.cshift[p - 1];
+                    const uint32_t w = 32u - __builtin_clz(m);
+                    if (__builtin_amdgcn_ballot_w64((digit64(differ, sh, m) | digit64(differ, cs, cm)) != 0u) == 0u) {
+                        if (lane == 0)
+                            atomicAdd(&hp[(digit64(k0, cs, cm) << w) | digit64(k0, sh, m)], static_cast<uint32_t>(64 * U));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) atomicAdd(&hp[(digit64(k[u], cs, cm) << w) | digit64(k[u], sh, m)], 1u);
+                    }
                 }
             }
         } else {
@@ -82,8 +99,16 @@ __global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restric
                 const size_t i = base + u * 64 + lane;
                 if (i >= n) continue;
                 const uint64_t key = keys[i];
-                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p)
-                    atomicAdd(&h[ha.lds_offset[p] + digit64(key, ha.shift[p], ha.mask[p])], 1u);
+                for (int p = 0; p < static_cast<int>(ha.num_passes); ++p) {
+                    uint32_t bin = digit64(key, ha.shift[p], ha.mask[p]);
+                    if constexpr (CHUNKED) {
+                        const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
+                        const uint32_t x = p == 0 ? pos_chunk(ha, i)
+                                                  : digit64(key, ha.shift[p - 1], ha.mask[p - 1]) >> ha.cshift[p - 1];
+                        bin |= x << w;
+                    }
+                    atomicAdd(&h[ha.lds_offset[p] + bin], 1u);
+                }
             }
         }
     }
@@ -95,16 +120,49 @@ __global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restric
         if (c == 0) continue;
         uint32_t p = 0;
         while (p + 1 < ha.num_passes && i >= ha.lds_offset[p + 1]) ++p;
-        atomicAdd(&hist[p * kMaxRadix + (i - ha.lds_offset[p])], c);
+        const uint32_t local = i - ha.lds_offset[p];
+        if constexpr (CHUNKED) {
+            const uint32_t w = 32u - __builtin_clz(ha.mask[p]);
+            atomicAdd(&hist[(p * kChunks + (local >> w)) * kChunkRadix + (local & ha.mask[p])], c);
+        } else {
+            atomicAdd(&hist[p * kMaxRadix + local], c);
+        }
     }
+}
+
+template <int BLOCK, int C>
+__global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restrict__ keys, uint32_t n, HistArgs ha,
+                                                       uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_h[];
+    histogram64_body<BLOCK, C, false>(keys, n, ha, hist, s_h);
+}
+
+template <int BLOCK, int C>
+__global__ __launch_bounds__(BLOCK) void k_histogram64_chunked(const uint64_t *__restrict__ keys, uint32_t n,
+                                                               HistArgs ha, uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_h[];
+    histogram64_body<BLOCK, C, true>(keys, n, ha, hist, s_h);
+}
+
+// Per-chunk counts (CC copies, args hc) if the probe chose them, else plain
+// counts (CP copies, hp): see k_histogram_auto.
+template <int BLOCK, int CP, int CC>
+__global__ __launch_bounds__(BLOCK) void k_histogram64_auto(const uint64_t *__restrict__ keys, uint32_t n, HistArgs hp,
+                                                            HistArgs hc, const uint32_t *__restrict__ mode,
+                                                            uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_h[];
+    if (*mode != 0u)
+        histogram64_body<BLOCK, CC, true>(keys, n, hc, hist, s_h);
+    else
+        histogram64_body<BLOCK, CP, false>(keys, n, hp, hist, s_h);
 }
 
 // ---------------------------------------------------------------------------
 // onesweep counting-sort pass over 64-bit keys
 // ---------------------------------------------------------------------------
 
-// The structure of k_onesweep: tiles claimed in order from an atomic
-// counter; wave w owns items [w * 64 * IPT, (w + 1) * 64 * IPT) of the tile
+// The structure of k_onesweep: tiles claimed in XCD chunks (claim_tile);
+// wave w owns items [w * 64 * IPT, (w + 1) * 64 * IPT) of the tile
 // and lane l holds item j * 64 + l in slot j, so the ballot ranking follows
 // input order (stable); per-digit tile counts are published as the tile's
 // aggregate, the tile is staged by digit in LDS, the lookback gives each
@@ -113,8 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_histogram64(const uint64_t *__restric
 // as 64-bit keys and VW-word values.
 template <int BITS, int BLOCK, int IPT, int VW, typename S>
 __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict__ plan, int pass, uint32_t n,
-                                                      const uint32_t *__restrict__ pass_base, S *__restrict__ status,
-                                                      uint32_t *__restrict__ tile_counter,
+                                                      S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                                       uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
@@ -135,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
     __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
     __shared__ uint32_t s_gbase[RADIX];
     __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_first, s_chunk, s_lo, s_valid;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -151,13 +208,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
     g_v *dst_v = (g_v *)pp.dst_v;
 
     for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
-    if (tid == 0) s_tile = atomicAdd(tile_counter + pass, 1u);
+    if (tid == 0) claim_tile<TILE>(plan->pass + pass, chunk_counter, s_tile, s_first, s_chunk, s_lo, s_valid);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const size_t tile_base = static_cast<size_t>(tile) * TILE;
-    if (tile_base >= n) return;
-    const uint32_t valid = static_cast<uint32_t>(min(static_cast<size_t>(TILE), n - tile_base));
+    if (tile == kNoTile) return;
+    const int32_t first = static_cast<int32_t>(s_first);
+    const size_t tile_base = s_lo;
+    const uint32_t valid = s_valid;
     const bool full = valid == static_cast<uint32_t>(TILE);
+    const uint32_t *pass_base = pp.cbase + s_chunk * kChunkRadix;
 
     uint64_t key[IPT];
     V val[VALS ? IPT : 1];
@@ -213,10 +272,11 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
                 s_whist[w * RADIX + d] = run;
                 run += c;
             }
+            if (d == RADIX - 1) run -= TILE - valid;  // a partial tile's empty slots are not items
             tcount[r] = run;
             tsum += run;
             status_store(status + static_cast<size_t>(tile) * RADIX + d,
-                         St::make(tile == 0 ? kFlagIncl : kFlagAgg, run));
+                         St::make(static_cast<int32_t>(tile) == first ? kFlagIncl : kFlagAgg, run));
         }
     }
     const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
@@ -249,8 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t d = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), 0, d, RADIX, error_flag);
-            if (tile != 0)
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), first, d, RADIX, error_flag);
+            if (static_cast<int32_t>(tile) != first)
                 status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
             s_gbase[d] = pass_base[d] + excl - dexcl[r];
         }

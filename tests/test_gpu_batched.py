@@ -86,6 +86,26 @@ def test_skewed_segments(kind):
     check(run_batched(keys, v, off), oracle.lsd_sort_segmented(keys, v, off), kind)
 
 
+@pytest.mark.parametrize("kind", ["uniform", "and4"])
+def test_long_segments_in_xcd_chunks(kind):
+    """At least 128 segments of at least 16 tiles on average: the tiled
+    passes split the tile list into XCD chunks at segment ends, with
+    segments of uneven length (a few much longer ones) and a one-item and an
+    empty segment among them."""
+    rng = np.random.default_rng(7)
+    sizes = [int(x) for x in rng.integers(200_000, 400_000, size=136)]
+    sizes[5] = 2_000_003   # one long segment: chunks of uneven tile counts
+    sizes[70] = 1
+    sizes[71] = 0
+    sizes[100] = 16384 * 16
+    off = offsets_of(sizes)
+    n = int(off[-1])
+    announce(f"batched XCD chunks {kind} segments={len(sizes)} n={n}")
+    k = inputs.uniform_keys(n, 900) if kind == "uniform" else inputs.and_keys(n, 4, 901)
+    v = inputs.index_values(n)
+    check(run_batched(k, v, off), oracle.lsd_sort_segmented(k, v, off), kind)
+
+
 def test_batched_workload_mix_reduced():
     """The batched workload's size mix (log-uniform 2^6..2^20, capped) at a
     2^22 total, so the oracle checks every segment."""

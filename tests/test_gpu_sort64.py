@@ -14,7 +14,7 @@ import pytest
 import oracle
 import paper_1008_2849_amd as rts
 from paper_1008_2849_amd import inputs
-from paper_1008_2849_amd.api import Config, FLAG_NO_SKIP
+from paper_1008_2849_amd.api import Config, FLAG_CHUNKS, FLAG_NO_SKIP, FLAG_ONE_CHAIN
 from gpu_util import announce, sync
 
 pytestmark = pytest.mark.gpu
@@ -107,6 +107,34 @@ def test_distributions(dist):
     v = values(n, 4)
     check(gpu_sort64(k, v), oracle.lsd_sort64(k, v), dist)
     check(gpu_sort64(k), oracle.lsd_sort64(k), dist + " keys only")
+
+
+@pytest.mark.parametrize("dist", list(_dists(16).keys()))
+def test_chunk_flags(dist):
+    """XCD chunks forced at a size below the default's threshold (8 chunks of
+    uneven tile counts, chunk ends inside tiles), and one chain, both give
+    the oracle's result, with 4- and 8-byte values."""
+    n = 23 * TILE + 4097
+    announce(f"64-bit keys chunk flags dist={dist} n={n}")
+    k = _dists(n)[dist]
+    want4 = oracle.lsd_sort64(k, values(n, 4))
+    for flags in (FLAG_CHUNKS, FLAG_CHUNKS | FLAG_NO_SKIP, FLAG_ONE_CHAIN):
+        cfg = Config((8,) * 8, 1024, 8, flags)
+        check(gpu_sort64(k, values(n, 4), cfg), want4, f"{dist} flags={flags}")
+    cfg = Config((8,) * 8, 512, 16, FLAG_CHUNKS)
+    v8 = values(n, 8)
+    check(gpu_sort64(k, v8, cfg), oracle.lsd_sort64(k, v8), f"{dist} 8-byte values")
+
+
+@pytest.mark.parametrize("dist", ["uniform", "and2", "dict16"])
+def test_probed_size(dist):
+    """At 2^25 items the default samples the keys and picks chunks (uniform)
+    or one chain (skewed); the result is the oracle's either way."""
+    n = (1 << 25) + 33
+    announce(f"64-bit keys probed dist={dist} n={n}")
+    k = inputs.keys64("uniform", n, 740) if dist == "uniform" else _dists(n)[dist]
+    v = values(n, 4)
+    check(gpu_sort64(k, v), oracle.lsd_sort64(k, v), dist)
 
 
 CONFIGS = [((8,) * 8, 1024, 8), ((8,) * 8, 512, 16), ((11, 11, 11, 11, 10, 10), 512, 8),
