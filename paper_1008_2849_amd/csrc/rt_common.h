@@ -52,6 +52,14 @@ rt_status finish_call(hipStream_t stream, const char *what);
 int device_cu_count();
 
 bool shape_supported(int bits_class, int block, int ipt);
+
+// Histogram arguments of a sort (32- or 64-bit keys) and the first pass's
+// positional XCD chunks: chunk x reads input items [bound[x], bound[x + 1]),
+// whole tiles, kChunks nearly equal shares of the tile grid.  chunked:
+// per-chunk counts (see k_histogram).
+struct HistArgs;
+void pos_bounds(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]);
+HistArgs hist_args(const Resolved &r, size_t n, bool chunked);
 rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolved *out);
 Layout make_layout(size_t n, const Resolved &r, bool direct);
 rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);

@@ -313,7 +313,7 @@ static void launch_pass(int bits_class, int block, int ipt, const Layout &L, boo
 
 // Input items of pass 0's chunk x: [bound[x], bound[x + 1]), whole tiles,
 // kChunks nearly equal shares of the tile grid.
-static void pos_bounds(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]) {
+void pos_bounds(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]) {
     const uint64_t tile = static_cast<uint64_t>(r.block) * r.ipt;
     const uint64_t tiles = (n + tile - 1) / tile;
     for (int x = 0; x <= kChunks; ++x) bound[x] = static_cast<uint32_t>(std::min<uint64_t>(n, x * tiles / kChunks * tile));
@@ -321,7 +321,7 @@ static void pos_bounds(size_t n, const Resolved &r, uint32_t bound[kChunks + 1])
 }
 
 // chunked: per-chunk counts (see k_histogram), for sorts with r.chunked.
-static HistArgs hist_args(const Resolved &r, size_t n, bool chunked) {
+HistArgs hist_args(const Resolved &r, size_t n, bool chunked) {
     HistArgs ha{};
     ha.num_passes = r.num_passes;
     uint32_t off = 0;

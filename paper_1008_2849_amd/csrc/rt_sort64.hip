@@ -166,31 +166,6 @@ uint32_t grid_for(size_t items, size_t per_block, uint32_t cap) {
     return static_cast<uint32_t>(g);
 }
 
-// Histogram arguments of a 64-bit sort; chunked: per-chunk counts (tables
-// kChunks times longer, chunks of pass 0 by position).
-void pos_bounds64(size_t n, const Resolved &r, uint32_t bound[kChunks + 1]) {
-    const uint64_t tile = static_cast<uint64_t>(r.block) * r.ipt;
-    const uint64_t tiles = (n + tile - 1) / tile;
-    for (int x = 0; x <= kChunks; ++x) bound[x] = static_cast<uint32_t>(std::min<uint64_t>(n, x * tiles / kChunks * tile));
-    bound[kChunks] = static_cast<uint32_t>(n);
-}
-
-HistArgs hist_args64(const Resolved &r, size_t n, bool chunked) {
-    HistArgs ha{};
-    ha.num_passes = r.num_passes;
-    uint32_t off = 0;
-    for (uint32_t p = 0; p < r.num_passes; ++p) {
-        ha.shift[p] = r.shift[p];
-        ha.mask[p] = (1u << r.width[p]) - 1u;
-        ha.cshift[p] = r.width[p] > 3 ? r.width[p] - 3 : 0;
-        ha.lds_offset[p] = off;
-        off += (chunked ? kChunks : 1) << r.width[p];
-    }
-    ha.total_bins = off;
-    if (chunked) pos_bounds64(n, r, ha.pos_bound);
-    return ha;
-}
-
 // lane-class copies: as many as fit in 72 KiB of padded rows, at most 8
 int copies64(uint32_t bins) {
     int c = 8;
@@ -287,13 +262,13 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
                        fill_words);
     prof_mark(stream, RT_KIND_FILL);
 
-    const HistArgs ha = hist_args64(r, n, false);
+    const HistArgs ha = hist_args(r, n, false);
     uint32_t *mode = ctr + kMaxPasses + 1 + kMaxPasses * kChunks;
     uint32_t pos_bound[kChunks + 1] = {};
-    if (r.chunked) pos_bounds64(n, r, pos_bound);
+    if (r.chunked) pos_bounds(n, r, pos_bound);
     bool probed = false;
     if (r.chunked) {
-        const HistArgs hc = hist_args64(r, n, true);
+        const HistArgs hc = hist_args(r, n, true);
         if (r.probe && copies64(ha.total_bins) == 8) {
             hipLaunchKernelGGL((k_chunk_probe<1024, uint64_t>), dim3(1), dim3(1024), 0, stream, keys, n, hc, mode);
             prof_mark(stream, RT_KIND_PROBE);
