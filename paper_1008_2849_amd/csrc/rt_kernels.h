@@ -421,6 +421,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const K *__restrict__ key
 // prev_start[x]: where chunk x's first digit of pass p - 1 starts.
 __device__ inline void plan_chunks(const PlanArgs &a, bool chunked, const uint32_t *prev_start,
                                    const uint32_t *base, uint32_t p, PassPlan *pp) {
+    if (!pp->active) return;  // the pass kernel returns before reading them
     uint32_t cs[kChunks + 1];
 #pragma unroll
     for (int x = 0; x <= kChunks; ++x) cs[x] = a.n;
@@ -447,7 +448,7 @@ __device__ inline void plan_chunks(const PlanArgs &a, bool chunked, const uint32
         pp->cstart[x] = cs[x];
         pp->ctile[x] = t;
         if (a.tile != 0u && cs[x + 1] > cs[x])  // tiles of the global grid that meet [cs[x], cs[x + 1])
-            t += static_cast<uint32_t>((static_cast<uint64_t>(cs[x + 1]) + a.tile - 1u) / a.tile - cs[x] / a.tile);
+            t += (cs[x + 1] - 1u) / a.tile + 1u - cs[x] / a.tile;
     }
     pp->cstart[kChunks] = a.n;
     pp->ctile[kChunks] = t;
