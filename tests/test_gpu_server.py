@@ -71,6 +71,27 @@ def test_caller_arrays_sorted_in_place():
         assert e.value.status == RT_ERR_NOT_FOUND
 
 
+def test_many_long_requests_in_xcd_chunks():
+    """At least 128 tiled requests of 16 tiles or more in flight: a step's
+    tile list is cut into XCD chunks at request ends.  Every result is the
+    oracle's, keys uniform and low-entropy alike."""
+    announce("server long requests in XCD chunks")
+    rng = np.random.default_rng(11)
+    sizes = [int(x) for x in rng.integers(262_144, 360_000, size=136)]
+    staged = []  # device copies first, so that the submissions follow each other closely
+    for i, n in enumerate(sizes):
+        keys = inputs.and_keys(n, 4, 60 + i) if i % 3 == 0 else inputs.uniform_keys(n, 60 + i)
+        vals = inputs.index_values(n)
+        staged.append((keys, vals, to_dev(keys), to_dev(vals)))
+    sync()
+    with Server(hbm_budget_bytes=2 << 30, max_active=160) as srv:
+        cases = [(srv.submit(kd, vd), keys, vals, kd, vd) for keys, vals, kd, vd in staged]
+        for t, keys, vals, kd, vd in cases:
+            srv.wait(t)
+            wk, wv = oracle.lsd_sort(keys, vals)
+            assert np.array_equal(to_host(kd), wk) and np.array_equal(to_host(vd), wv)
+
+
 def test_budget_admission_waits_and_rejects():
     import torch
     announce("server budget")
