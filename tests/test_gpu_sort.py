@@ -180,6 +180,16 @@ def test_probed_sizes(dist):
     assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), dist)
 
 
+def test_probed_keys_only_tuned_shape():
+    """Keys only at 2^25 items with the tuned shape (1024 x 12 tiles, two
+    blocks per CU) in XCD chunks: the oracle's result."""
+    rts.load_default_tuning()
+    n = (1 << 25) + 5
+    announce(f"probed keys only n={n}")
+    k = inputs.uniform_keys(n, 703)
+    assert_same(gpu_sort(k), oracle.lsd_sort(k), "keys only")
+
+
 @pytest.mark.parametrize("skip_pattern", [1, 2, 5, 6, 9, 14])
 def test_chunks_with_skipped_passes(skip_pattern):
     """A skipped pass (constant digit) leaves the next pass a single chunk:
