@@ -368,14 +368,17 @@ def test_copy_probe():
     assert torch.equal(c[1:n], a[1:])
 
 
-def test_graph_capture_single_sort_replays():
+@pytest.mark.parametrize("n,dist", [(3 * TILE + 1234, "uniform"), ((1 << 25) + 1234, "uniform"),
+                                    ((1 << 25) + 1234, "and4")])
+def test_graph_capture_single_sort_replays(n, dist):
     """rt_sort_ex with a caller workspace only enqueues kernels: captured
     once into a graph, each replay sorts its fresh input like the eager call
-    (fills are kernels, never memsets, so replays after the first are sound)."""
+    (fills are kernels, never memsets, so replays after the first are sound).
+    At 2^25 items the probe and the XCD chunks (uniform) or one chain (AND-4)
+    run inside the graph too."""
     import torch
-    n = 3 * TILE + 1234
-    announce(f"graph capture single sort n={n}")
-    k_h = inputs.uniform_keys(n, 81)
+    announce(f"graph capture single sort n={n} {dist}")
+    k_h = inputs.uniform_keys(n, 81) if dist == "uniform" else inputs.and_keys(n, 4, 82)
     v_h = inputs.index_values(n)
     want = oracle.lsd_sort(k_h, v_h)
     k0, v0 = to_dev(k_h), to_dev(v_h)
