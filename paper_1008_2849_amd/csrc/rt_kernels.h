@@ -387,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_probe(const K *__restrict__ key
         }
         __syncthreads();
         uint32_t m = 0;
-        for (uint32_t i = tid; i < (kChunks << w); i += BLOCK) {
+        for (uint32_t i = tid; i < (static_cast<uint32_t>(kChunks) << w); i += BLOCK) {
             const uint32_t c = s_tab[i];
             m = max(m, c);
             if (w >= 6u) {  // a wave's 64 entries share a chunk: one add per wave
