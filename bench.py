@@ -503,6 +503,8 @@ def main() -> int:
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the write-combining leg (the paper's Table 1 configurations)")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
+    ap.add_argument("--no-xcd-compare", action="store_true",
+                    help="skip re-timing the headline sort on one lookback chain per pass")
     ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
                     "of single-array throughput), replayed open loop; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -623,6 +625,32 @@ def main() -> int:
     copy_gbps = 2 * big_src.numel() * 4 / float(np.median(cm)) / 1e6 if cm else None
     del big_src, big_dst
 
+    # the same sort on one lookback chain per pass (RT_FLAG_ONE_CHAIN), for
+    # what the XCD chunks buy, on fresh copies of the same input
+    from paper_1008_2849_amd._lib import RT_FLAG_ONE_CHAIN
+    oc_cfg = rts.Config(cfg.digit_bits, cfg.block_threads, cfg.items_per_thread, cfg.flags | RT_FLAG_ONE_CHAIN)
+    oc_n = 0 if args.no_xcd_compare else min(5, K + W)
+    for i in range(oc_n):
+        slots[i][0].copy_(k0)
+        if v0 is not None:
+            slots[i][1].copy_(v0)
+    oc_ws = ws if ws.numel() >= rts.workspace_bytes(n, vals_on, oc_cfg) else torch.empty(
+        rts.workspace_bytes(n, vals_on, oc_cfg), dtype=torch.uint8, device=dev)
+    xcd = None
+    if oc_n:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(oc_n):
+            rts.sort_ex(slots[i][0], slots[i][1], oc_cfg, oc_ws)
+        torch.cuda.synchronize()
+        oc_ms = 1e3 * (time.perf_counter() - t0) / oc_n
+        oc_same = bool(torch.equal(slots[0][0], ko)) and (vo is None or bool(torch.equal(slots[0][1], vo)))
+        xcd = {"chunked_ms_per_sort": round(ms_per_step, 4), "one_chain_ms_per_sort": round(oc_ms, 4),
+               "speedup": round(oc_ms / ms_per_step, 4), "one_chain_output_equal": oc_same,
+               "note": "same input and configuration with RT_FLAG_ONE_CHAIN (one lookback chain per pass)"}
+        log(f"one chain per pass: {oc_ms:.3f} ms/sort; XCD chunks {oc_ms / ms_per_step:.3f}x faster")
+    del oc_ws
+
     digest = kernel_source_digest()
     traffic = traffic_from_profiles(digest)
 
@@ -711,6 +739,7 @@ def main() -> int:
         "copy_peak_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
         "parity_properties_ok": props,
+        "xcd_chunks": xcd,
         "transfer_inclusive": pcie,
         "msd_first": msd_first,
         "sort64": sort64,
