@@ -14,9 +14,11 @@
  *    by the caller; the library never frees them.  Any 4-byte alignment works.
  *  - Every sort call is stream-ordered: it enqueues kernels on `stream` and
  *    returns; results are valid once the stream has synchronised.  No call
- *    synchronises the host, except that with the environment variable
- *    RT_DEBUG_SYNC=1 each call waits for its own work and reports kernel
- *    errors.
+ *    synchronises the host, except a call with RT_FLAG_VALIDATE (which waits
+ *    for its own work and reports device-side errors) and, with the
+ *    environment variable RT_DEBUG_SYNC=1, every call.  The library's own
+ *    workspace grows in stream order (hipMallocAsync / hipFreeAsync on the
+ *    call's stream), so growing it does not wait either.
  *  - Argument errors are reported synchronously, before any device work.
  *    n = 0 and n = 1 are valid and do nothing.  n >= 2^32 is RT_ERR_TOO_LARGE.
  *  - The result is in place from the caller's view.  The library keeps a
@@ -56,7 +58,13 @@ typedef enum rt_status {
 /* rt_config.flags */
 #define RT_FLAG_NO_SKIP 0x1u   /* run every pass, even when its digit is constant */
 #define RT_FLAG_NT_STORES 0x2u /* scatter with non-temporal stores */
-#define RT_FLAG_VALIDATE 0x4u  /* batched, MSD-first: wait for the sort and report device errors */
+/* Wait for the sort and report device-side errors as RT_ERR_HIP: a
+ * lookback wait that gave up (the bounded wait of the onesweep pass; the
+ * output is then wrong) and, for batched sorts, malformed segment offsets.
+ * Without it these errors leave a flag in the workspace that no call reads
+ * (RT_DEBUG_SYNC=1 reads it too).  Accepted by every sort call with flags or
+ * a config. */
+#define RT_FLAG_VALIDATE 0x4u
 /* Write every item straight from registers to its output slot instead of
  * staging the tile by digit in LDS first: the counting-sort pass without
  * write-combining (Section 2's technique switched off, the paper's "VM
@@ -112,20 +120,22 @@ rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream);
 rt_status rt_sort_pairs(uint32_t *keys, uint32_t *vals, size_t n, hipStream_t stream);
 
 /*
- * Bytes of workspace rt_sort_ex needs for n items (with_values 0 or 1)
+ * Bytes of workspace rt_sort_pairs_ex needs for n items (with_values 0 or 1)
  * under cfg (NULL = tuned default).  Returns 0 for n < 2.
  */
 size_t rt_workspace_bytes(size_t n, int with_values, const rt_config *cfg);
 
 /*
  * Explicit form: cfg (NULL = tuned default) and a caller-owned device
- * workspace of at least rt_workspace_bytes() bytes (NULL = library cache).
- * vals may be NULL (keys only).  With a caller workspace the call issues
- * kernel launches only, so it may be captured into a HIP graph; concurrent
- * calls must not share a workspace.
+ * workspace of at least rt_workspace_bytes() bytes, 256-byte aligned (NULL =
+ * library cache).  vals may be NULL (keys only).  With a caller workspace and
+ * no RT_FLAG_VALIDATE the call issues kernel launches only, so it may be
+ * captured into a HIP graph; concurrent calls must not share a workspace.
+ * With RT_FLAG_VALIDATE in cfg->flags the call waits for the sort and
+ * returns RT_ERR_HIP if a pass's lookback gave up.
  */
-rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
-                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+rt_status rt_sort_pairs_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * 64-bit keys
@@ -155,10 +165,10 @@ rt_status rt_sort_pairs64(uint64_t *keys, uint32_t *vals, size_t n, hipStream_t 
  * built are 1024x8 and 512x16 for digits of up to 8 bits and 512x8 for
  * wider ones (correct, but several times slower than 8-bit digits); flags:
  * RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN, RT_FLAG_CHUNKS (XCD chunks as for 32-bit
- * keys; anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
+ * keys), RT_FLAG_VALIDATE (anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
  * 256-byte aligned, or NULL for the library's per-stream cache; with a
  * caller workspace the call only enqueues kernels.  Errors and stream
- * behaviour as for rt_sort_ex.
+ * behaviour as for rt_sort_pairs_ex.
  */
 rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_bytes, size_t n, const rt_config *cfg,
                        void *workspace, size_t workspace_bytes, hipStream_t stream);
@@ -220,14 +230,14 @@ rt_status rt_sort_batched_ex(uint32_t *keys, uint32_t *vals, const uint32_t *seg
 size_t rt_msd_first_workspace_bytes(size_t n, int with_values);
 
 /*
- * Sorts n keys (and values) in place like rt_sort_ex, by Section 4's
+ * Sorts n keys (and values) in place like rt_sort_pairs_ex, by Section 4's
  * "reverse sorting" as Algorithm 2 arranges it on one processing element:
  * one counting-sort pass on the most significant 8-bit digit moves the
  * items into a temporary array of the workspace, partitioned into 256 MSD
  * buckets whose starts are the exclusive prefix sum of the MSD histogram;
  * then each bucket is sorted on its own by LSD passes over digits 0, 1
  * and 2, the last of which writes the caller's arrays.  The result equals
- * rt_sort_ex's bit for bit (a stable sort has one result); passes are never
+ * rt_sort_pairs_ex's bit for bit (a stable sort has one result); passes are never
  * skipped, so keys whose top byte is constant still pay the partition pass.
  * Buckets of at most 16384 items are sorted whole in LDS.
  *
@@ -251,7 +261,7 @@ rt_status rt_sort_msd_first(uint32_t *keys, uint32_t *vals, size_t n, uint32_t f
  * counting step for every digit at once).  hist: device
  * u32[num_passes * 2^RT_MAX_DIGIT_BITS]; pass p's 2^digit_bits[p] counters
  * start at offset p * 2^RT_MAX_DIGIT_BITS; the whole array is overwritten.
- * cfg as for rt_sort_ex (NULL = tuned default).
+ * cfg as for rt_sort_pairs_ex (NULL = tuned default).
  */
 rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const rt_config *cfg,
                               uint32_t *hist, hipStream_t stream);
@@ -313,13 +323,19 @@ typedef struct rt_server rt_server;
 rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_active, rt_server **out);
 
 /*
- * Submit a request whose key/value arrays already live on the device
- * (caller-owned, not touched by the caller until rt_server_wait returns).
- * The sorted result replaces keys/vals.  vals may be NULL.  A request whose
- * footprint exceeds the whole budget is RT_ERR_BUDGET.
+ * Submit a request whose key/value arrays already live on the device.
+ * keys, vals: the input, device u32[n] (vals may be NULL: keys only).
+ * out_keys, out_vals: where the sorted result goes, device u32[n]; NULL
+ * (or the input arrays themselves) sorts in place.  An out-of-place request
+ * copies its input into its outputs on the device when it is admitted and
+ * never writes the input; inputs and outputs must then not overlap, and
+ * out_vals must be given when vals is.  Every array is caller-owned and must
+ * stay untouched by the caller until rt_server_wait (or rt_server_wait_any)
+ * has reported the request.  A request whose footprint exceeds the whole
+ * budget is RT_ERR_BUDGET.
  */
-rt_status rt_server_submit(rt_server *s, uint32_t *keys, uint32_t *vals, size_t n,
-                           uint64_t *ticket);
+rt_status rt_server_submit(rt_server *s, const uint32_t *keys, const uint32_t *vals, uint32_t *out_keys,
+                           uint32_t *out_vals, size_t n, uint64_t *ticket);
 
 /*
  * Submit a request whose input the server generates on the device at
@@ -358,11 +374,14 @@ rt_status rt_server_release(rt_server *s, uint64_t ticket);
 /*
  * Latency percentiles (us) over completed requests and throughput
  * (completed items / (last completion - first admission), Gkeys/s).
- * Any output pointer may be NULL.  peak_bytes: high-water mark of budgeted
- * device memory.
+ * Any output pointer may be NULL.
  */
-rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
-                          uint64_t *completed, size_t *peak_bytes);
+rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s);
+
+/* As rt_server_stats, plus the number of completed requests and the
+ * high-water mark of budgeted device memory (peak_bytes). */
+rt_status rt_server_stats_ex(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
+                             uint64_t *completed, size_t *peak_bytes);
 
 /* One request of an arrival trace for rt_server_replay: a generated input
  * of n key/value pairs (as rt_server_submit_generated), arriving

@@ -92,7 +92,7 @@ SIGNATURES = {
     "rt_sort_keys": (ctypes.c_int, [vp, sz, vp]),
     "rt_sort_pairs": (ctypes.c_int, [vp, vp, sz, vp]),
     "rt_workspace_bytes": (sz, [sz, ctypes.c_int, ctypes.POINTER(RtConfig)]),
-    "rt_sort_ex": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
+    "rt_sort_pairs_ex": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
     "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
     "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),
@@ -108,13 +108,14 @@ SIGNATURES = {
     "rt_copy": (ctypes.c_int, [vp, vp, sz, vp]),
     "rt_generate": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtGenParams), u32, vp]),
     "rt_server_create": (ctypes.c_int, [sz, u32, ctypes.POINTER(vp)]),
-    "rt_server_submit": (ctypes.c_int, [vp, vp, vp, sz, ctypes.POINTER(u64)]),
+    "rt_server_submit": (ctypes.c_int, [vp, vp, vp, vp, vp, sz, ctypes.POINTER(u64)]),
     "rt_server_submit_generated": (ctypes.c_int, [vp, ctypes.POINTER(RtGenParams), sz, ctypes.POINTER(u64)]),
     "rt_server_wait": (ctypes.c_int, [vp, u64, i64, dblp]),
     "rt_server_wait_any": (ctypes.c_int, [vp, i64, ctypes.POINTER(u64), dblp]),
     "rt_server_fetch": (ctypes.c_int, [vp, u64, vp, vp]),
     "rt_server_release": (ctypes.c_int, [vp, u64]),
-    "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),
+    "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp]),
+    "rt_server_stats_ex": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),
     "rt_server_replay": (ctypes.c_int, [vp, vp, sz, dblp, dblp]),
     "rt_server_destroy": (ctypes.c_int, [vp]),
     "rt_profile_start": (ctypes.c_int, [u32]),

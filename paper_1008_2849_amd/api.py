@@ -19,6 +19,7 @@ FLAG_NT_STORES = _lib.RT_FLAG_NT_STORES
 FLAG_DIRECT_SCATTER = _lib.RT_FLAG_DIRECT_SCATTER
 FLAG_ONE_CHAIN = _lib.RT_FLAG_ONE_CHAIN
 FLAG_CHUNKS = _lib.RT_FLAG_CHUNKS
+FLAG_VALIDATE = _lib.RT_FLAG_VALIDATE
 MAX_DIGIT_BITS = _lib.RT_MAX_DIGIT_BITS
 MAX_PASSES = _lib.RT_MAX_PASSES
 
@@ -123,8 +124,8 @@ def sort_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, strea
     if workspace is not None:
         ws_ptr = workspace.data_ptr()
         ws_bytes = workspace.numel() * workspace.element_size()
-    check(lib().rt_sort_ex(_ptr(keys), _ptr(vals), keys.numel(), p, ws_ptr, ws_bytes, _stream(stream)),
-          "rt_sort_ex")
+    check(lib().rt_sort_pairs_ex(_ptr(keys), _ptr(vals), keys.numel(), p, ws_ptr, ws_bytes, _stream(stream)),
+          "rt_sort_pairs_ex")
 
 
 def _check_tensor64(t, name: str, dtypes):

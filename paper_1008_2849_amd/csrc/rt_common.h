@@ -63,6 +63,8 @@ HistArgs hist_args(const Resolved &r, size_t n, bool chunked);
 rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolved *out);
 Layout make_layout(size_t n, const Resolved &r, bool direct);
 rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out);
+// Waits for the stream, then copies one u32 of device memory to *out.
+rt_status read_device_word(const void *word, hipStream_t stream, uint32_t *out, const char *what);
 // The whole sort (direct == false) or one explicit pass (direct == true:
 // keys/vals read, direct_out_* written).  Pass p's timing mark has kind
 // pass_kind + p.  After the plan kernel, the workspace's base table holds

@@ -32,8 +32,10 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <string>
 #include <unordered_map>
+#include <tuple>
 #include <vector>
 
 #include "rt_common.h"
@@ -104,6 +106,9 @@ struct Request {
     bool with_values = false;
     rt_gen_params gen{};
     uint32_t *k = nullptr, *v = nullptr;    // input, then the sorted result
+    // out-of-place caller requests: the input, copied into k/v when the
+    // request is admitted (NULL: sorted in place)
+    const uint32_t *in_k = nullptr, *in_v = nullptr;
     uint32_t *tk = nullptr, *tv = nullptr;  // temporaries
     size_t data_off = 0, data_bytes = 0;    // arena: generated input/result
     size_t tmp_off = 0, tmp_bytes = 0;      // arena: temporaries
@@ -316,6 +321,8 @@ struct StepPlan {
     size_t tiles = 0;
     uint32_t fresh_tiled = 0, tiled = 0, small[kSegMaxClasses] = {0, 0, 0, 0}, gen = 0, gen_chunks = 0;
     bool vals = false;
+    // device copies of out-of-place inputs into their outputs: (dst, src, bytes)
+    std::vector<std::tuple<void *, const void *, size_t>> copies;
 };
 
 StepPlan build_step(rt_server *s, StepSlot &slot) {
@@ -344,6 +351,10 @@ StepPlan build_step(rt_server *s, StepSlot &slot) {
         d.n = static_cast<uint32_t>(r->n);
         d.pass = r->pass;
         d.row = r->row;
+        if (r->fresh && r->in_k != nullptr && r->n > 0) {
+            P.copies.emplace_back(r->k, r->in_k, r->n * sizeof(uint32_t));
+            if (r->with_values) P.copies.emplace_back(r->v, r->in_v, r->n * sizeof(uint32_t));
+        }
         if (r->fresh && r->generated && r->n > 0) {
             GenDesc &g = gen[P.gen++];
             g.k = r->k;
@@ -425,6 +436,10 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(want, cap)));
     };
 
+    for (const auto &c : P.copies) {  // out-of-place inputs into their outputs
+        e = hipMemcpyAsync(std::get<0>(c), std::get<1>(c), std::get<2>(c), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: input copy: %s", hipGetErrorString(e));
+    }
     if (P.gen)  // inputs of the fresh generated requests
         hipLaunchKernelGGL(k_srv_generate, dim3(P.gen_chunks), dim3(256), 0, st,
                            reinterpret_cast<const GenDesc *>(dm + m.gen), P.gen);
@@ -658,22 +673,42 @@ static rt_status check_request_size(rt_server *s, size_t n, bool generated, bool
     return RT_OK;
 }
 
-extern "C" rt_status rt_server_submit(rt_server *s, uint32_t *keys, uint32_t *vals, size_t n, uint64_t *ticket) {
+// Whether two u32 arrays of n items share any byte.
+static bool overlap(const void *a, const void *b, size_t n) {
+    if (a == nullptr || b == nullptr || n == 0) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    const uintptr_t bytes = n * sizeof(uint32_t);
+    return x < y + bytes && y < x + bytes;
+}
+
+extern "C" rt_status rt_server_submit(rt_server *s, const uint32_t *keys, const uint32_t *vals, uint32_t *out_keys,
+                                      uint32_t *out_vals, size_t n, uint64_t *ticket) {
     if (s == nullptr || ticket == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: NULL argument");
     if (n > 0 && keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: keys is NULL");
-    if ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(vals)) & 3u)
+    // no output arrays (or the inputs themselves): sorted in place
+    const bool in_place = out_keys == nullptr || out_keys == keys;
+    if (in_place && out_vals != nullptr && out_vals != vals)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: out_vals given for an in-place request");
+    if (!in_place && vals != nullptr && out_vals == nullptr)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: out_vals is NULL for an out-of-place request");
+    uint32_t *k = in_place ? const_cast<uint32_t *>(keys) : out_keys;
+    uint32_t *v = vals == nullptr ? nullptr : (in_place ? const_cast<uint32_t *>(vals) : out_vals);
+    if ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(vals) | reinterpret_cast<uintptr_t>(k) |
+         reinterpret_cast<uintptr_t>(v)) & 3u)
         return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: arrays must be 4-byte aligned");
-    if (vals != nullptr && n > 0) {
-        const uintptr_t k0 = reinterpret_cast<uintptr_t>(keys), v0 = reinterpret_cast<uintptr_t>(vals);
-        const uintptr_t bytes = n * sizeof(uint32_t);
-        if (k0 < v0 + bytes && v0 < k0 + bytes) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: keys and values overlap");
-    }
+    if (overlap(k, v, n)) return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: keys and values overlap");
+    if (!in_place && (overlap(keys, k, n) || overlap(keys, v, n) || overlap(vals, k, n) || overlap(vals, v, n)))
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_submit: inputs and outputs overlap");
     rt_status st = check_request_size(s, n, false, vals != nullptr, "rt_server_submit");
     if (st != RT_OK) return st;
     std::unique_ptr<Request> r(new Request());
     r->n = n;
-    r->k = keys;
-    r->v = vals;
+    r->k = k;
+    r->v = v;
+    if (!in_place) {
+        r->in_k = keys;
+        r->in_v = vals;
+    }
     r->with_values = vals != nullptr;
     return enqueue(s, std::move(r), ticket);
 }
@@ -800,8 +835,8 @@ extern "C" rt_status rt_server_release(rt_server *s, uint64_t ticket) {
     return drop_generated(s, it);
 }
 
-extern "C" rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
-                                     uint64_t *completed, size_t *peak_bytes) {
+extern "C" rt_status rt_server_stats_ex(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
+                                        uint64_t *completed, size_t *peak_bytes) {
     if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_stats: server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     std::vector<double> l = s->latencies;
@@ -820,6 +855,10 @@ extern "C" rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_u
     if (completed) *completed = l.size();
     if (peak_bytes) *peak_bytes = s->peak;
     return RT_OK;
+}
+
+extern "C" rt_status rt_server_stats(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s) {
+    return rt_server_stats_ex(s, p50_us, p99_us, gkeys_per_s, nullptr, nullptr);
 }
 
 extern "C" rt_status rt_server_replay(rt_server *s, const rt_replay_request *reqs, size_t count, double *latency_us,

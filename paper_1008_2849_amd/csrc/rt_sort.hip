@@ -133,7 +133,7 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
     r.flags = c.flags;
     r.with_values = with_values != 0;
     if (r.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER |
-                                         RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS))
+                                         RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS | RT_FLAG_VALIDATE))
         return set_error(RT_ERR_INVALID_ARG, "unknown flags 0x%x", r.flags);
     if ((r.flags & RT_FLAG_ONE_CHAIN) && (r.flags & RT_FLAG_CHUNKS))
         return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
@@ -220,25 +220,33 @@ rt_status cached_workspace(size_t bytes, hipStream_t stream, void **out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     CacheEntry &c = g_ws[{dev, stream}];
     if (c.bytes < bytes) {
+        // Stream-ordered growth: the old buffer is freed, and the new one
+        // allocated, in the stream's order, behind the work that may still
+        // use the old one, so the host never waits.
         if (c.ptr != nullptr) {
-            // earlier work on this stream may still use the old buffer
-            e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return set_error(RT_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-            (void)hipFree(c.ptr);
+            e = hipFreeAsync(c.ptr, stream);
+            if (e != hipSuccess) return set_error(RT_ERR_HIP, "hipFreeAsync: %s", hipGetErrorString(e));
             c.ptr = nullptr;
             c.bytes = 0;
         }
         void *p = nullptr;
-        e = hipMalloc(&p, bytes);
+        e = hipMallocAsync(&p, bytes, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return set_error(RT_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) for the workspace: %s", bytes,
+            return set_error(RT_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu) for the workspace: %s", bytes,
                              hipGetErrorString(e));
         }
         c.ptr = p;
         c.bytes = bytes;
     }
     *out = c.ptr;
+    return RT_OK;
+}
+
+rt_status read_device_word(const void *word, hipStream_t stream, uint32_t *out, const char *what) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(out, word, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
     return RT_OK;
 }
 
@@ -516,9 +524,9 @@ static rt_status check_ranges(const uint32_t *keys, const uint32_t *vals, size_t
     return RT_OK;
 }
 
-extern "C" rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+extern "C" rt_status rt_sort_pairs_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
                                 void *workspace, size_t workspace_bytes, hipStream_t stream) {
-    rt_status s = check_ranges(keys, vals, n, "rt_sort_ex");
+    rt_status s = check_ranges(keys, vals, n, "rt_sort_pairs_ex");
     if (s != RT_OK || n < 2) return s;
     Resolved r;
     s = resolve_config(cfg, n, vals != nullptr, &r);
@@ -527,35 +535,35 @@ extern "C" rt_status rt_sort_ex(uint32_t *keys, uint32_t *vals, size_t n, const 
     void *ws = workspace;
     if (ws != nullptr) {
         if (workspace_bytes < L.total)
-            return set_error(RT_ERR_INVALID_ARG, "rt_sort_ex: workspace of %zu bytes, %zu needed",
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_pairs_ex: workspace of %zu bytes, %zu needed",
                              workspace_bytes, L.total);
         if (reinterpret_cast<uintptr_t>(ws) & 255u)
-            return set_error(RT_ERR_INVALID_ARG, "rt_sort_ex: workspace must be 256-byte aligned");
+            return set_error(RT_ERR_INVALID_ARG, "rt_sort_pairs_ex: workspace must be 256-byte aligned");
     } else {
         s = cached_workspace(L.total, stream, &ws);
         if (s != RT_OK) return s;
     }
     launch_sort(keys, vals, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws), false, nullptr, nullptr,
                 stream);
-    s = finish_call(stream, "rt_sort_ex");
-    if (s == RT_OK && debug_sync_enabled()) {  // the stream has drained: read the error word
+    s = finish_call(stream, "rt_sort_pairs_ex");
+    if (s == RT_OK && ((r.flags & RT_FLAG_VALIDATE) || debug_sync_enabled())) {
+        // wait for the sort and read its error word (a lookback that gave up)
         uint32_t err = 0;
-        hipError_t e = hipMemcpy(&err, static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses,
-                                 sizeof err, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_sort_ex: %s", hipGetErrorString(e));
-        if (err) return set_error(RT_ERR_HIP, "rt_sort_ex: device error word 0x%x", err);
+        s = read_device_word(static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses, stream, &err,
+                             "rt_sort_pairs_ex");
+        if (s == RT_OK && err) return set_error(RT_ERR_HIP, "rt_sort_pairs_ex: device error word 0x%x", err);
     }
     return s;
 }
 
 extern "C" rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream) {
-    return rt_sort_ex(keys, nullptr, n, nullptr, nullptr, 0, stream);
+    return rt_sort_pairs_ex(keys, nullptr, n, nullptr, nullptr, 0, stream);
 }
 
 extern "C" rt_status rt_sort_pairs(uint32_t *keys, uint32_t *vals, size_t n, hipStream_t stream) {
     if (vals == nullptr && n >= 2 && n < (static_cast<size_t>(1) << 32))
         return set_error(RT_ERR_INVALID_ARG, "rt_sort_pairs: vals is NULL (use rt_sort_keys)");
-    return rt_sort_ex(keys, vals, n, nullptr, nullptr, 0, stream);
+    return rt_sort_pairs_ex(keys, vals, n, nullptr, nullptr, 0, stream);
 }
 
 extern "C" size_t rt_workspace_bytes(size_t n, int with_values, const rt_config *cfg) {

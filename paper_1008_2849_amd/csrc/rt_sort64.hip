@@ -61,9 +61,10 @@ rt_status resolve64(const rt_config *cfg, uint32_t value_words, Resolved *out) {
         if (cfg->block_threads) c.block_threads = cfg->block_threads;
         if (cfg->items_per_thread) c.items_per_thread = cfg->items_per_thread;
     }
-    if (c.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS))
+    if (c.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS | RT_FLAG_VALIDATE))
         return set_error(RT_ERR_UNSUPPORTED,
-                         "64-bit keys: only RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS are supported (flags 0x%x)",
+                         "64-bit keys: only RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN, RT_FLAG_CHUNKS and RT_FLAG_VALIDATE "
+                         "are supported (flags 0x%x)",
                          c.flags);
     if ((c.flags & RT_FLAG_ONE_CHAIN) && (c.flags & RT_FLAG_CHUNKS))
         return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
@@ -392,12 +393,11 @@ extern "C" rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_byt
     launch_sort64(keys, static_cast<uint32_t *>(vals), vw, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws),
                   stream);
     s = finish_call(stream, "rt_sort64_ex");
-    if (s == RT_OK && debug_sync_enabled()) {
+    if (s == RT_OK && ((r.flags & RT_FLAG_VALIDATE) || debug_sync_enabled())) {
         uint32_t err = 0;
-        hipError_t e = hipMemcpy(&err, static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses, sizeof err,
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_sort64_ex: %s", hipGetErrorString(e));
-        if (err) return set_error(RT_ERR_HIP, "rt_sort64_ex: device error word 0x%x", err);
+        s = read_device_word(static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses, stream, &err,
+                             "rt_sort64_ex");
+        if (s == RT_OK && err) return set_error(RT_ERR_HIP, "rt_sort64_ex: device error word 0x%x", err);
     }
     return s;
 }

@@ -30,15 +30,19 @@ class Server:
             raise RuntimeError("server is closed")
         return self._h
 
-    def submit(self, keys, vals=None) -> int:
-        """Sort device tensors keys (and vals) in place; returns a ticket.
-        The tensors must stay alive and untouched until wait() returns."""
-        for t, name in ((keys, "keys"), (vals, "vals")):
+    def submit(self, keys, vals=None, out_keys=None, out_vals=None) -> int:
+        """Sort device tensors keys (and vals); returns a ticket.  The result
+        replaces the inputs, or goes to out_keys / out_vals when given (the
+        inputs are then only read).  Every tensor must stay alive and
+        untouched until a wait reports the request."""
+        for t, name in ((keys, "keys"), (vals, "vals"), (out_keys, "out_keys"), (out_vals, "out_vals")):
             if t is not None and (not t.is_cuda or t.element_size() != 4 or not t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous 4-byte device tensor")
+            if t is not None and t.numel() != keys.numel():
+                raise ValueError(f"{name} differs in length from keys")
         ticket = ctypes.c_uint64()
-        check(lib().rt_server_submit(self.handle, _ptr(keys), _ptr(vals), keys.numel(), ctypes.byref(ticket)),
-              "rt_server_submit")
+        check(lib().rt_server_submit(self.handle, _ptr(keys), _ptr(vals), _ptr(out_keys), _ptr(out_vals),
+                                     keys.numel(), ctypes.byref(ticket)), "rt_server_submit")
         return ticket.value
 
     def submit_generated(self, params: RtGenParams, n: int) -> int:
@@ -99,8 +103,8 @@ class Server:
         """(p50 us, p99 us, Gkeys/s, completed requests, peak budgeted bytes)."""
         p50, p99, gk = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         done, peak = ctypes.c_uint64(), ctypes.c_size_t()
-        check(lib().rt_server_stats(self.handle, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(gk),
-                                    ctypes.byref(done), ctypes.byref(peak)), "rt_server_stats")
+        check(lib().rt_server_stats_ex(self.handle, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(gk),
+                                       ctypes.byref(done), ctypes.byref(peak)), "rt_server_stats_ex")
         return p50.value, p99.value, gk.value, done.value, peak.value
 
     def close(self) -> None:

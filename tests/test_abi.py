@@ -21,9 +21,68 @@ def header_functions():
 
 def test_header_declares_the_entry_points():
     names = header_functions()
-    for must in ("rt_sort_keys", "rt_sort_pairs", "rt_sort_pairs_batched", "rt_sort_ex",
+    for must in ("rt_sort_keys", "rt_sort_pairs", "rt_sort_pairs_batched", "rt_sort_pairs_ex",
                  "rt_server_create", "rt_server_submit", "rt_server_wait", "rt_server_stats"):
         assert must in names
+
+
+def header_prototypes():
+    """name -> list of parameter types (names dropped, spaces normalised)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b[a-z_0-9 ]*?[\s*]+(rt_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        params = []
+        for p in m.group(2).split(","):
+            p = " ".join(p.replace("*", " * ").split())
+            toks = p.split(" ")
+            if toks == ["void"]:
+                continue
+            if len(toks) > 1 and toks[-1] != "*":
+                toks = toks[:-1]  # drop the parameter name
+            params.append(" ".join(toks))
+        out[m.group(1)] = params
+    return out
+
+
+# The boundary the task's design table asks for, call by call: the
+# parameter types each call takes there, and how the header maps it.
+# "exact": same name and parameter types.  Any other tag names a departure
+# that DESIGN.md's boundary table must list with its reason.
+SPEC_8B = {
+    "rt_sort_keys": (["uint32_t *", "size_t", "hipStream_t"], "exact"),
+    "rt_sort_pairs": (["uint32_t *", "uint32_t *", "size_t", "hipStream_t"], "exact"),
+    "rt_sort_pairs_batched": (["uint32_t *", "uint32_t *", "const uint32_t *", "uint32_t", "hipStream_t"],
+                              "max_total"),
+    "rt_workspace_bytes": (["size_t", "int", "const rt_config *"], "exact"),
+    "rt_sort_pairs_ex": (["uint32_t *", "uint32_t *", "size_t", "const rt_config *", "void *", "size_t",
+                          "hipStream_t"], "exact"),
+    "rt_load_tuning": (["const char *"], "exact"),
+    "rt_status_string": (["rt_status"], "exact"),
+    "rt_last_error": ([], "exact"),
+    "rt_server_create": (["size_t", "uint32_t", "rt_server * *"], "exact"),
+    "rt_server_submit": (["rt_server *", "const uint32_t *", "const uint32_t *", "uint32_t *", "uint32_t *",
+                          "size_t", "uint64_t *"], "exact"),
+    "rt_server_submit_generated": (["rt_server *", "uint32_t", "uint64_t", "size_t", "uint64_t *"],
+                                   "generator_params"),
+    "rt_server_wait": (["rt_server *", "uint64_t", "int64_t", "double *"], "exact"),
+    "rt_server_stats": (["rt_server *", "double *", "double *", "double *"], "exact"),
+    "rt_server_destroy": (["rt_server *"], "exact"),
+}
+
+
+def test_every_boundary_call_maps_to_the_header():
+    protos = header_prototypes()
+    design = open(os.path.join(ROOT, "DESIGN.md")).read()
+    for name, (params, how) in SPEC_8B.items():
+        assert name in protos, name
+        if how == "exact":
+            assert protos[name] == params, (name, protos[name])
+        else:  # a departure: documented with its reason in the boundary table
+            assert protos[name] != params, name
+            assert f"`{how}`" in design, (name, how)
+    # the departures, as they stand
+    assert protos["rt_sort_pairs_batched"] == SPEC_8B["rt_sort_pairs_batched"][0][:4] + ["size_t", "hipStream_t"]
+    assert protos["rt_server_submit_generated"] == ["rt_server *", "const rt_gen_params *", "size_t", "uint64_t *"]
 
 
 def test_library_exports_every_declared_symbol():
@@ -60,6 +119,18 @@ def test_argument_errors_are_synchronous(so):
     assert so.rt_sort_pairs(None, None, 1, None) == _lib.RT_OK
 
 
+def test_validate_flag_is_accepted_everywhere(so):
+    """RT_FLAG_VALIDATE (wait and report device errors) is a valid flag of
+    the single-array, 64-bit and batched sorts: their configurations with it
+    resolve (a refused configuration sizes no workspace)."""
+    c = _lib.RtConfig()
+    c.flags = _lib.RT_FLAG_VALIDATE
+    assert so.rt_workspace_bytes(1 << 20, 1, ctypes.byref(c)) > 0
+    assert so.rt_workspace_bytes64(1 << 20, 4, ctypes.byref(c)) > 0
+    c.flags = 0x400  # not a flag
+    assert so.rt_workspace_bytes(1 << 20, 1, ctypes.byref(c)) == 0
+
+
 def test_config_validation(so):
     fake_k, fake_v = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
     for bits, want in [((8, 8, 8), _lib.RT_ERR_INVALID_ARG),        # sums to 24
@@ -70,20 +141,20 @@ def test_config_validation(so):
         c.num_passes = len(bits)
         for i, b in enumerate(bits[:8]):
             c.digit_bits[i] = b
-        assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == want, bits
+        assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == want, bits
     c = _lib.RtConfig()
     c.num_passes = 4
     for i in range(4):
         c.digit_bits[i] = 8
     c.block_threads, c.items_per_thread = 128, 7
-    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+    assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
     c.block_threads, c.items_per_thread = 1024, 16
     c.flags = _lib.RT_FLAG_DIRECT_SCATTER | _lib.RT_FLAG_NT_STORES  # not built
-    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+    assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
     c.flags = 0x100  # unknown
-    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
     c.flags = _lib.RT_FLAG_ONE_CHAIN | _lib.RT_FLAG_CHUNKS  # exclude each other
-    assert so.rt_sort_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_INVALID_ARG
 
 
 def test_workspace_bytes(so):
@@ -272,7 +343,7 @@ def test_server_argument_errors(so):
     assert so.rt_server_create(1000, 8, ctypes.byref(out)) == _lib.RT_ERR_INVALID_ARG  # budget below 1 MiB
     assert so.rt_server_create(1 << 30, 8, None) == _lib.RT_ERR_INVALID_ARG
     t = ctypes.c_uint64()
-    assert so.rt_server_submit(None, None, None, 0, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_submit(None, None, None, None, None, 0, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_submit_generated(None, None, 10, ctypes.byref(t)) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_wait(None, 1, 0, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_replay(None, None, 0, None, None) == _lib.RT_ERR_INVALID_ARG
@@ -280,7 +351,8 @@ def test_server_argument_errors(so):
     assert so.rt_server_wait_any(None, 0, ctypes.byref(t), None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_fetch(None, 1, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_release(None, 1) == _lib.RT_ERR_INVALID_ARG
-    assert so.rt_server_stats(None, None, None, None, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_stats(None, None, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_stats_ex(None, None, None, None, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_destroy(None) == _lib.RT_OK
 
 

@@ -71,6 +71,31 @@ def test_caller_arrays_sorted_in_place():
         assert e.value.status == RT_ERR_NOT_FOUND
 
 
+def test_caller_arrays_sorted_out_of_place():
+    """Requests with output arrays: each result lands in its outputs, equal
+    to the oracle's sort of that input alone, and the inputs are untouched
+    (keys only and pairs, small and tiled requests in one mix)."""
+    import torch
+    announce("server caller-owned arrays, out of place")
+    with Server(hbm_budget_bytes=32 << 20, max_active=16) as srv:
+        cases = []
+        for i, n in enumerate([3, 16384, 16385, 70_000, 250_000, 1000]):
+            keys = inputs.zipf16_keys(n, 70 + i) if i % 2 else inputs.uniform_keys(n, 70 + i)
+            vals = inputs.index_values(n) if i != 5 else None
+            kd, vd = to_dev(keys), (to_dev(vals) if vals is not None else None)
+            ok = torch.empty_like(kd)
+            ov = torch.empty_like(vd) if vd is not None else None
+            cases.append((srv.submit(kd, vd, ok, ov), keys, vals, kd, vd, ok, ov))
+        for t, keys, vals, kd, vd, ok, ov in cases:
+            srv.wait(t)
+            wk, wv = oracle.lsd_sort(keys, vals)
+            assert np.array_equal(to_host(ok), wk), len(keys)
+            if vals is not None:
+                assert np.array_equal(to_host(ov), wv), len(keys)
+                assert np.array_equal(to_host(vd), vals)
+            assert np.array_equal(to_host(kd), keys)  # the input is only read
+
+
 def test_many_long_requests_in_xcd_chunks():
     """At least 128 tiled requests of 16 tiles or more in flight: a step's
     tile list is cut into XCD chunks at request ends.  Every result is the

@@ -138,6 +138,27 @@ def test_flags(flags, dist):
     assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k), f"keys flags={flags} {dist}")
 
 
+@pytest.mark.parametrize("n", [100_003, 3 * TILE * 8 + 77])
+def test_validated_sort(n):
+    """RT_FLAG_VALIDATE waits for the sort and reads its device error word:
+    a correct sort returns RT_OK (no exception) with the oracle's result,
+    through the library's workspace and a caller workspace, in XCD chunks
+    and on one chain."""
+    import torch
+    from paper_1008_2849_amd.api import FLAG_VALIDATE
+    announce(f"validated sort n={n}")
+    k = inputs.uniform_keys(n, 91)
+    v = inputs.index_values(n)
+    want = oracle.lsd_sort(k, v)
+    for extra in (FLAG_CHUNKS, FLAG_ONE_CHAIN):
+        cfg = Config((8, 8, 8, 8), 1024, 16, FLAG_VALIDATE | extra)
+        assert_same(gpu_sort(k, v, cfg), want, f"validate {extra}")
+        kd, vd = to_dev(k), to_dev(v)
+        ws = torch.empty(rts.workspace_bytes(n, True, cfg), dtype=torch.uint8, device="cuda")
+        rts.sort_ex(kd, vd, cfg, ws)
+        assert_same((to_host(kd), to_host(vd)), want, f"validate {extra} caller workspace")
+
+
 @pytest.mark.parametrize("widths,shape", [((11, 11, 10), (512, 16)), ((8, 8, 8, 8), (256, 16)),
                                           ((4,) * 8, (1024, 8))])
 def test_direct_scatter_configs(widths, shape):
@@ -371,7 +392,7 @@ def test_copy_probe():
 @pytest.mark.parametrize("n,dist", [(3 * TILE + 1234, "uniform"), ((1 << 25) + 1234, "uniform"),
                                     ((1 << 25) + 1234, "and4")])
 def test_graph_capture_single_sort_replays(n, dist):
-    """rt_sort_ex with a caller workspace only enqueues kernels: captured
+    """rt_sort_pairs_ex with a caller workspace only enqueues kernels: captured
     once into a graph, each replay sorts its fresh input like the eager call
     (fills are kernels, never memsets, so replays after the first are sound).
     At 2^25 items the probe and the XCD chunks (uniform) or one chain (AND-4)
