@@ -71,17 +71,19 @@ def test_caller_arrays_sorted_in_place():
         assert e.value.status == RT_ERR_NOT_FOUND
 
 
-def test_caller_arrays_sorted_out_of_place():
+@pytest.mark.parametrize("with_values", [True, False])
+def test_caller_arrays_sorted_out_of_place(with_values):
     """Requests with output arrays: each result lands in its outputs, equal
     to the oracle's sort of that input alone, and the inputs are untouched
-    (keys only and pairs, small and tiled requests in one mix)."""
+    (small and tiled requests in one mix; a server serves pairs or keys
+    only, not both)."""
     import torch
-    announce("server caller-owned arrays, out of place")
+    announce(f"server caller-owned arrays, out of place, values={with_values}")
     with Server(hbm_budget_bytes=32 << 20, max_active=16) as srv:
         cases = []
         for i, n in enumerate([3, 16384, 16385, 70_000, 250_000, 1000]):
             keys = inputs.zipf16_keys(n, 70 + i) if i % 2 else inputs.uniform_keys(n, 70 + i)
-            vals = inputs.index_values(n) if i != 5 else None
+            vals = inputs.index_values(n) if with_values else None
             kd, vd = to_dev(keys), (to_dev(vals) if vals is not None else None)
             ok = torch.empty_like(kd)
             ov = torch.empty_like(vd) if vd is not None else None
