@@ -32,7 +32,7 @@ PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
 METRIC = "Gkeys/s and HBM GB/s per pass vs peak (2^28 pairs); batched p50/p99 latency"
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1008_2849_amd", "csrc", f)
-                  for f in ("rt_kernels.h", "rt_internal.h")]
+                  for f in ("rt_kernels.h", "rt_internal.h", "rt_common.h", "rt_sort.hip")]
 
 
 def log(msg: str) -> None:
@@ -61,16 +61,45 @@ def traffic_from_profiles(digest: str):
     return float(t.group(1))
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+class pinned_to_one_core:
+    """Runs the block on one core of this process's allowed set (restored
+    afterwards): the oracle is single-threaded, and pinning keeps the
+    scheduler from moving it between cores while it is timed."""
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0)
+        self.core = min(self.saved)
+        os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.saved)
+        return False
+
+
 def cpu_baseline(keys_h, vals_h, out_k, out_v):
-    """Time the CPU oracle (single thread) on the same input; its output also
-    checks the GPU result bit for bit."""
+    """Time the CPU oracle (single thread, pinned to one core) on the same
+    input; its output also checks the GPU result bit for bit.  Returns
+    (seconds, equal, core)."""
     import numpy as np
     import oracle
-    t0 = time.perf_counter()
-    rk, rv = oracle.lsd_sort(keys_h, vals_h)
-    dt = time.perf_counter() - t0
+    with pinned_to_one_core() as pin:
+        t0 = time.perf_counter()
+        rk, rv = oracle.lsd_sort(keys_h, vals_h)
+        dt = time.perf_counter() - t0
     same = bool(np.array_equal(rk, out_k) and (out_v is None or np.array_equal(rv, out_v)))
-    return dt, same
+    return dt, same, pin.core
 
 
 def split_calls(marks):
@@ -83,6 +112,62 @@ def split_calls(marks):
             calls[-1][0] += ms
             calls[-1][1].append((kind, ms))
     return calls
+
+
+def bench_workloads(rts, inputs, dev, names, K, W):
+    """The other single-array workloads at full size (keys only at 2^28 and
+    2^20; the skewed 2^26-pair inputs): whole-sort Gkeys/s, the mean pass
+    time and its HBM fraction, the histogram time, and the last timed
+    output against the CPU oracle (bit for bit, timed single-threaded on
+    one core: the CPU baseline of that workload)."""
+    import numpy as np
+    import torch
+    from paper_1008_2849_amd._lib import RT_KIND_HISTOGRAM, RT_KIND_PASS
+    out = []
+    for name in names:
+        w = inputs.WORKLOADS[name]
+        n = w.n
+        k_h, v_h = inputs.make_workload(w)
+        k0 = torch.from_numpy(k_h.view(np.int32)).to(dev)
+        v0 = torch.from_numpy(v_h.view(np.int32)).to(dev) if v_h is not None else None
+        tuned = rts.tuned_config(n, w.with_values)
+        slots = [(k0.clone(), None if v0 is None else v0.clone()) for _ in range(K + W)]
+        ws = torch.empty(rts.workspace_bytes(n, w.with_values, tuned), dtype=torch.uint8, device=dev)
+        for i in range(W):
+            rts.sort_ex(slots[i][0], slots[i][1], tuned, ws)
+        torch.cuda.synchronize()
+        rts.profile_start(max_marks=16 * K + 16)
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            rts.sort_ex(slots[i][0], slots[i][1], tuned, ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        marks = rts.profile_stop(capacity=16 * K + 16)
+        passes = [ms for kind, ms in marks if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+        hist = [ms for kind, ms in marks if kind == RT_KIND_HISTOGRAM]
+        ko, vo = slots[W + K - 1]
+        out_k = ko.cpu().numpy().view(np.uint32)
+        out_v = None if vo is None else vo.cpu().numpy().view(np.uint32)
+        del slots, ws
+        dt, same, core = cpu_baseline(k_h, v_h, out_k, out_v)
+        item = 8 if w.with_values else 4
+        pm = float(np.mean(passes)) if passes else float("nan")
+        gk = n / (wall / K) / 1e9
+        out.append({"workload": name, "n": n, "values": w.with_values, "Gkeys/s": round(gk, 3),
+                    "ms_per_sort": round(1e3 * wall / K, 4),
+                    "passes_per_sort": round(len(passes) / K, 2),
+                    "pass_ms": round(pm, 4), "pass_GBps": round(2 * item * n / pm / 1e6, 1),
+                    "pass_frac_of_peak": round(2 * item * n / pm / 1e6 / PEAK_HBM_GBPS, 4),
+                    "histogram_ms": round(float(np.mean(hist)), 4) if hist else None,
+                    "config": {"digit_bits": list(tuned.digit_bits), "block_threads": tuned.block_threads,
+                               "items_per_thread": tuned.items_per_thread},
+                    "matches_oracle_bit_exact": same,
+                    "cpu_oracle": {"seconds": round(dt, 4), "Gkeys/s": round(n / dt / 1e9, 5), "cores": 1,
+                                   "pinned_core": core}})
+        log(f"{name}: {out[-1]}")
+        del k0, v0, ko, vo
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(rts, inputs, dev, K, W, single_gkeys):
@@ -503,6 +588,9 @@ def main() -> int:
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the write-combining leg (the paper's Table 1 configurations)")
     ap.add_argument("--no-pcie", action="store_true", help="skip the transfer-inclusive leg")
+    ap.add_argument("--workloads", default="keys_256m_uniform,keys_1m_uniform,pairs_64m_and2,pairs_64m_and4,"
+                    "pairs_64m_and8,pairs_64m_top_a5,pairs_64m_zipf16",
+                    help="further single-array workloads timed and checked against the oracle (empty to skip)")
     ap.add_argument("--no-xcd-compare", action="store_true",
                     help="skip re-timing the headline sort on one lookback chain per pass")
     ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
@@ -626,30 +714,52 @@ def main() -> int:
     del big_src, big_dst
 
     # the same sort on one lookback chain per pass (RT_FLAG_ONE_CHAIN), for
-    # what the XCD chunks buy, on fresh copies of the same input
+    # what the XCD chunks buy: the same W warm-up and K timed sorts of fresh
+    # copies of the same input, under the same per-kernel timing marks, with
+    # the pass and histogram times of both sides
     from paper_1008_2849_amd._lib import RT_FLAG_ONE_CHAIN
-    oc_cfg = rts.Config(cfg.digit_bits, cfg.block_threads, cfg.items_per_thread, cfg.flags | RT_FLAG_ONE_CHAIN)
-    oc_n = 0 if args.no_xcd_compare else min(5, K + W)
-    for i in range(oc_n):
-        slots[i][0].copy_(k0)
-        if v0 is not None:
-            slots[i][1].copy_(v0)
-    oc_ws = ws if ws.numel() >= rts.workspace_bytes(n, vals_on, oc_cfg) else torch.empty(
-        rts.workspace_bytes(n, vals_on, oc_cfg), dtype=torch.uint8, device=dev)
     xcd = None
-    if oc_n:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(oc_n):
+    if not args.no_xcd_compare:
+        oc_cfg = rts.Config(cfg.digit_bits, cfg.block_threads, cfg.items_per_thread, cfg.flags | RT_FLAG_ONE_CHAIN)
+        ref = (ko.clone(), None if vo is None else vo.clone())
+        for k, v in slots:
+            k.copy_(k0)
+            if v is not None:
+                v.copy_(v0)
+        oc_ws = ws if ws.numel() >= rts.workspace_bytes(n, vals_on, oc_cfg) else torch.empty(
+            rts.workspace_bytes(n, vals_on, oc_cfg), dtype=torch.uint8, device=dev)
+        for i in range(W):
             rts.sort_ex(slots[i][0], slots[i][1], oc_cfg, oc_ws)
         torch.cuda.synchronize()
-        oc_ms = 1e3 * (time.perf_counter() - t0) / oc_n
-        oc_same = bool(torch.equal(slots[0][0], ko)) and (vo is None or bool(torch.equal(slots[0][1], vo)))
+        rts.profile_start(max_marks=16 * K + 16)
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            rts.sort_ex(slots[i][0], slots[i][1], oc_cfg, oc_ws)
+        torch.cuda.synchronize()
+        oc_ms = 1e3 * (time.perf_counter() - t0) / K
+        oc_marks = rts.profile_stop(capacity=16 * K + 16)
+        last = slots[W + K - 1]
+        oc_same = bool(torch.equal(last[0], ref[0])) and (ref[1] is None or bool(torch.equal(last[1], ref[1])))
+        # the headline output stays where the later legs expect it
+        slots[W + K - 1][0].copy_(ref[0])
+        if ref[1] is not None:
+            slots[W + K - 1][1].copy_(ref[1])
+        del ref
+
+        def kind_ms(mk, lo, hi):
+            v = [ms for kind, ms in mk if lo <= kind < hi]
+            return round(float(np.mean(v)), 4) if v else None
+
         xcd = {"chunked_ms_per_sort": round(ms_per_step, 4), "one_chain_ms_per_sort": round(oc_ms, 4),
                "speedup": round(oc_ms / ms_per_step, 4), "one_chain_output_equal": oc_same,
+               "chunked_pass_ms": kind_ms(marks, RT_KIND_PASS, RT_KIND_PASS + 8),
+               "one_chain_pass_ms": kind_ms(oc_marks, RT_KIND_PASS, RT_KIND_PASS + 8),
+               "chunked_histogram_ms": kind_ms(marks, RT_KIND_HISTOGRAM, RT_KIND_HISTOGRAM + 1),
+               "one_chain_histogram_ms": kind_ms(oc_marks, RT_KIND_HISTOGRAM, RT_KIND_HISTOGRAM + 1),
+               "timing": f"both sides: {W} warm-up then {K} timed sorts with per-kernel timing marks",
                "note": "same input and configuration with RT_FLAG_ONE_CHAIN (one lookback chain per pass)"}
         log(f"one chain per pass: {oc_ms:.3f} ms/sort; XCD chunks {oc_ms / ms_per_step:.3f}x faster")
-    del oc_ws
+        del oc_ws
 
     digest = kernel_source_digest()
     traffic = traffic_from_profiles(digest)
@@ -659,11 +769,13 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out_k = ko.cpu().numpy().view(np.uint32)
         out_v = None if vo is None else vo.cpu().numpy().view(np.uint32)
-        log("timing the CPU oracle on the same input (single thread)")
-        dt, same = cpu_baseline(keys_h, vals_h, out_k, out_v)
+        log("timing the CPU oracle on the same input (single thread, one core)")
+        dt, same, core = cpu_baseline(keys_h, vals_h, out_k, out_v)
         cpu = {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole workload: {wl.name} at n={n} (seed {wl.seed}), "
-                         f"one sort, {dt:.1f} s, host has {os.cpu_count()} logical CPUs",
+               "sample": f"the whole workload: {wl.name} at n={n} (seed {wl.seed}), one sort, {dt:.1f} s, "
+                         f"single thread pinned to core {core}",
+               "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+               "allowed_cpus": len(os.sched_getaffinity(0)),
                "matches_gpu_bit_exact": same}
         log(f"oracle {dt:.1f}s, GPU output {'==' if same else '!='} oracle")
 
@@ -681,6 +793,13 @@ def main() -> int:
         msd_first = bench_msd_first(rts, dev, k0, v0, slots, K, W, gkeys, ref[0], ref[1])
         del ref
         log(f"msd_first: {msd_first}")
+
+    workloads = []
+    if args.workloads and args.workload == "pairs_256m_uniform":
+        slots = ws = None  # the headline's copies and workspace (its output stays in ko / vo)
+        torch.cuda.empty_cache()
+        log("further workloads: " + args.workloads)
+        workloads = bench_workloads(rts, inputs, dev, [x for x in args.workloads.split(",") if x], K, W)
 
     batched = None
     if not args.no_batched and args.workload == "pairs_256m_uniform":
@@ -744,6 +863,7 @@ def main() -> int:
         "msd_first": msd_first,
         "sort64": sort64,
         "write_combining": table1,
+        "workloads": workloads,
         "batched": batched,
         "serving": serving,
         "kernel_source_digest": digest,
@@ -751,6 +871,7 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     ok = props and (cpu is None or cpu["matches_gpu_bit_exact"])
     ok = ok and (batched is None or batched["parity_properties_ok"])
+    ok = ok and all(w_["matches_oracle_bit_exact"] for w_ in workloads)
     ok = ok and all(not s.get("failures") for s in serving)
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])

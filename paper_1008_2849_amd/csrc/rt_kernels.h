@@ -79,18 +79,28 @@ __device__ __forceinline__ g_u32 *gelem(uint32_t *base, size_t i) {
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (no LDS
+// round trip): shifts by 1, 2, 4 and 8 lanes inside each row of 16, then
+// row 0's total into row 1 and row 2's into row 3 (row_bcast:15), then the
+// total of rows 0-1 into rows 2-3 (row_bcast:31).  A lane whose source lies
+// outside its row adds the old value 0.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xa, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // Exclusive prefix sum of v over the block; every thread must call it.
 template <int BLOCK>
 __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_wsum) {
     constexpr int WAVES = BLOCK / 64;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const uint32_t x = wave_inclusive_sum(v);
     if (lane == 63) s_wsum[wave] = x;
     __syncthreads();
     uint32_t before = 0;
@@ -98,14 +108,6 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_
     for (int w = 0; w < WAVES; ++w)
         if (w < wave) before += s_wsum[w];
     return before + x - v;
-}
-
-template <bool NT>
-__device__ __forceinline__ void store_g(g_u32 *p, uint32_t v) {
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
 }
 
 // Sleep roughly `rounds` * 64 clocks (s_sleep takes an immediate).
@@ -719,124 +721,192 @@ __device__ __forceinline__ void claim_tile(const PassPlan *__restrict__ pp, uint
     valid = static_cast<uint32_t>(e - b);
 }
 
-// One block per tile of BLOCK * IPT consecutive items.  The pass's input is
-// split into chunks (see PassPlan); a block claims the next tile of the
-// chunk of the XCD it runs on, or of the next chunk with tiles left once
-// that one is exhausted.  Tiles of a chunk are claimed in order from the
-// chunk's counter, so a block only ever waits on tiles claimed before it,
-// by blocks that are already running, whichever XCD they run on.  The tiles
-// of a chunk are the global grid of TILE-item tiles cut at the chunk's
-// ends, so only a chunk's first and last tile can be partial.  The grid
-// needs ctile[nchunks] blocks; surplus blocks find every chunk exhausted
-// and exit.  Wave w of the tile owns items
-// [w * 64 * IPT, (w + 1) * 64 * IPT) of it and lane l holds item j * 64 + l
-// of that range in slot j, so slot-by-slot, lane-by-lane processing follows
-// input order, which makes the ranking stable.
-//
-// Phases: load keys and values -> rank every item inside its wave (ballot
-// match + per-wave digit counters in LDS) -> per-digit tile counts,
-// published as this tile's aggregate -> tile-local digit offsets -> gather
-// keys and values by digit in LDS -> lookback for the global offset of each
-// digit -> write every digit run to consecutive output addresses.
+// ---------------------------------------------------------------------------
+// the onesweep counting-sort pass over one tile: one body for 32-bit keys,
+// 64-bit keys and segments
+// ---------------------------------------------------------------------------
+
+// Global view of element i of an array of T in address space 1 (global
+// instructions with a uniform base).  SMALL: the byte offset i * sizeof(T)
+// fits in 32 bits, so it is formed in 32-bit arithmetic.
+template <typename T, bool SMALL>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *base, size_t i) {
+    typedef const __attribute__((address_space(1))) T gt;
+    if constexpr (SMALL)
+        return (gt *)((const g_char *)base + static_cast<uint32_t>(i * sizeof(T)));
+    else
+        return (gt *)base + i;
+}
+template <typename T, bool SMALL>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *base, size_t i) {
+    typedef __attribute__((address_space(1))) T gt;
+    if constexpr (SMALL)
+        return (gt *)((g_char *)base + static_cast<uint32_t>(i * sizeof(T)));
+    else
+        return (gt *)base + i;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void store_t(__attribute__((address_space(1))) T *p, T v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// The pass's digit of a key: bits [shift, shift + width) (width <= 11).
+__device__ __forceinline__ uint32_t key_digit(uint32_t key, uint32_t shift, uint32_t width) {
+    return __builtin_amdgcn_ubfe(key, shift, width);
+}
+__device__ __forceinline__ uint32_t key_digit(uint64_t key, uint32_t shift, uint32_t width) {
+    return static_cast<uint32_t>(key >> shift) & ((1u << width) - 1u);
+}
+
+// One tile of a counting-sort pass, as its kernel has claimed it.  Items
+// are read from src at [item0, item0 + valid) and written to dst; base[d] is
+// the output slot, in dst, of the first item of digit d that this tile's
+// lookback chain (its XCD chunk, or its segment) holds.  Lookback index
+// `tile` waits on the chain's tiles [first, tile).  Every store is clamped
+// to [0, bound).
+template <typename K, typename V>
+struct TileJob {
+    const K *src_k;
+    const V *src_v;
+    K *dst_k;
+    V *dst_v;
+    const uint32_t *base;
+    size_t item0;
+    uint32_t shift, width;
+    uint32_t tile, first;
+    uint32_t valid;
+    uint32_t bound;
+};
+
+// LDS of one onesweep block: the tile staged by digit, per-wave digit
+// counters (then offsets) with a 64-word scratch row per wave that absorbs
+// the counter writes of non-leader lanes, each digit's output slot, the
+// block scan's wave sums, and the claimed tile (broadcast by thread 0).
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS>
+struct OnesweepLds {
+    static constexpr int RADIX = 1 << BITS;
+    static constexpr int WAVES = BLOCK / 64;
+    static constexpr int TILE = BLOCK * IPT;
+    K stage_k[TILE];
+    V stage_v[VALS ? TILE : 1];
+    uint32_t whist[WAVES * RADIX + WAVES * 64];
+    uint32_t gbase[RADIX];
+    uint32_t wsum[WAVES];
+    uint32_t claim[6];
+};
+
+// Stable rank of a wave's items, slot by slot and lane by lane (input
+// order): rnk[j] = the wave's count of the digit before slot j plus the
+// lanes below with that digit, from 8-bit (or BITS-bit) ballot matching.
+// The first lane of each digit advances the wave's counter; the others
+// write their private scratch word, so no atomics are needed.  mbcnt and
+// bcnt add the counter while they count.  A partial tile's empty slots take
+// the last digit, so they rank behind every item.  With VALS and FULL the
+// tile's values are loaded halfway through (after the keys, which the
+// ranking waits on first).
+template <int BITS, int IPT, typename K, typename V, bool VALS, bool SMALL, bool FULL>
+__device__ __forceinline__ void rank_items(const K (&key)[IPT], V (&val)[VALS ? IPT : 1], uint32_t (&rnk)[IPT],
+                                           uint32_t *wh, uint32_t *scratch, uint32_t shift, uint32_t width,
+                                           uint32_t valid, uint32_t wslot0, const V *src_v, size_t item0) {
+    constexpr uint32_t RADIX = 1u << BITS;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        uint32_t d = key_digit(key[j], shift, width);
+        if (!FULL && wslot0 + j * 64 >= valid) d = RADIX - 1;
+        uint32_t lo, hi;
+        match_digit<BITS>(d, lo, hi);
+        const uint32_t cnt = wh[d];
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, cnt));
+        rnk[j] = r;
+        uint32_t *dst = r == cnt ? wh + d : scratch;
+        // popcount(lo) + popcount(hi) + cnt in two ops: v_bcnt adds its
+        // second operand
+        uint32_t t;
+        asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(t) : "v"(lo), "v"(cnt));
+        asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(t) : "v"(hi), "v"(t));
+        *dst = t;
+        compiler_fence();
+        if constexpr (VALS && FULL) {
+            if (j == IPT / 2 - 1) {
+#pragma unroll
+                for (int q = 0; q < IPT; ++q) val[q] = *gptr<V, SMALL>(src_v, item0 + wslot0 + q * 64);
+            }
+        }
+    }
+}
+
+// One tile of a pass.  Wave w owns items [w * 64 * IPT, (w + 1) * 64 * IPT)
+// of the tile and lane l holds item j * 64 + l of that range in slot j, so
+// slot-by-slot, lane-by-lane processing follows input order (stability).
+// Phases: load the keys (each slot of a wave is 64 consecutive items) ->
+// rank every item inside its wave -> per-digit tile counts, published as
+// the tile's aggregate -> tile-local digit offsets -> gather keys and
+// values by digit in LDS -> lookback for the global offset of each digit ->
+// write every digit run to consecutive output addresses.
 //
 // STAGE = false drops the gather: every item is written straight from its
 // registers to its output slot, so a wave's stores scatter over the digit
 // runs.  This is the pass without write-combining (the paper's "VM only"
 // counterpart), kept to measure what the staging buys.
-template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true>
-__global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
-                                                    S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
-                                                    uint32_t *__restrict__ error_flag) {
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE,
+          bool SMALL>
+__device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
+                                              OnesweepLds<BITS, BLOCK, IPT, K, V, VALS> &lds,
+                                              S *__restrict__ status, uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
     constexpr int TILE = BLOCK * IPT;
     constexpr int WAVE_ITEMS = 64 * IPT;
     constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;  // digits per owning thread
     constexpr int DT = RADIX / R;                            // owning threads
-    constexpr bool SMALL = sizeof(S) == 4;                    // n < 2^30
     using St = Status<S>;
-
-    const PassPlan pp = plan->pass[pass];
-    if (!pp.active) return;
-
-    __shared__ uint32_t s_stage_k[TILE];
-    __shared__ uint32_t s_stage_v[VALS ? TILE : 1];
-    // per-wave digit counters, then a 64-word scratch row per wave that
-    // absorbs the counter writes of non-leader lanes
-    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile, s_first, s_chunk, s_lo, s_valid;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t wave = tid >> 6;
-    const uint32_t shift = pp.shift;
-    const uint32_t width = pp.width;
-    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;  // tile index of this lane's slot 0
-    uint32_t *wh = s_whist + wave * RADIX;
-    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
-
-    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;  // this wave's counters
-    if (tid == 0) claim_tile<TILE>(plan->pass + pass, chunk_counter, s_tile, s_first, s_chunk, s_lo, s_valid);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile == kNoTile) return;
-    const int32_t first = static_cast<int32_t>(s_first);
-    const size_t tile_base = s_lo;
-    const uint32_t valid = s_valid;
+    const uint32_t shift = job.shift, width = job.width, valid = job.valid;
     const bool full = valid == static_cast<uint32_t>(TILE);
-    const uint32_t *pass_base = pp.cbase + s_chunk * kChunkRadix;
+    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;  // tile index of this lane's slot 0
+    uint32_t *wh = lds.whist + wave * RADIX;
+    uint32_t *scratch = lds.whist + WAVES * RADIX + wave * 64 + lane;
 
-    // ---- load (each slot of a wave is 256 consecutive bytes).  In a full
-    // tile the values are loaded halfway through the ranking below, which
-    // needs only the keys: the tile's key loads then do not queue behind its
-    // value loads (2 % faster passes than loading both here).
-    uint32_t key[IPT];
-    uint32_t val[VALS ? IPT : 1];
+    // ---- load the keys (a partial tile: its values too)
+    K key[IPT];
+    V val[VALS ? IPT : 1];
     if (full) {
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) key[j] = *gelem<SMALL>(pp.src_k, tile_base + wslot0 + j * 64);
+        for (int j = 0; j < IPT; ++j) key[j] = *gptr<K, SMALL>(job.src_k, job.item0 + wslot0 + j * 64);
     } else {
 #pragma unroll
         for (int j = 0; j < IPT; ++j)
-            key[j] = (wslot0 + j * 64 < valid) ? *gelem<SMALL>(pp.src_k, tile_base + wslot0 + j * 64) : 0u;
+            key[j] = (wslot0 + j * 64 < valid) ? *gptr<K, SMALL>(job.src_k, job.item0 + wslot0 + j * 64) : K(0);
         if constexpr (VALS) {
 #pragma unroll
             for (int j = 0; j < IPT; ++j)
-                val[j] = (wslot0 + j * 64 < valid) ? *gelem<SMALL>(pp.src_v, tile_base + wslot0 + j * 64) : 0u;
+                val[j] = (wslot0 + j * 64 < valid) ? *gptr<V, SMALL>(job.src_v, job.item0 + wslot0 + j * 64) : V(0);
         }
     }
 
-    // ---- stable rank inside the wave, per-wave digit counts in LDS.
-    // Items past the end take the last digit, so they rank behind every real
-    // item of the tile and are never written.
+    // ---- stable rank inside the wave, per-wave digit counts in LDS
     uint32_t rnk[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
-        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
-        uint32_t lo, hi;
-        match_digit<BITS>(d, lo, hi);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const uint32_t cnt = wh[d];
-        rnk[j] = cnt + below;
-        // the first lane of each digit advances the counter; the others
-        // write their private scratch word instead
-        uint32_t *dst = below == 0 ? wh + d : scratch;
-        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
-        compiler_fence();
-        if constexpr (VALS) {
-            if (full && j == IPT / 2 - 1) {
-#pragma unroll
-                for (int q = 0; q < IPT; ++q) val[q] = *gelem<SMALL>(pp.src_v, tile_base + wslot0 + q * 64);
-            }
-        }
-    }
+    if (full)
+        rank_items<BITS, IPT, K, V, VALS, SMALL, true>(key, val, rnk, wh, scratch, shift, width, valid, wslot0,
+                                                      job.src_v, job.item0);
+    else
+        rank_items<BITS, IPT, K, V, VALS, SMALL, false>(key, val, rnk, wh, scratch, shift, width, valid, wslot0,
+                                                       job.src_v, job.item0);
     __syncthreads();
 
-    // ---- per digit: counts of earlier waves, tile count, publish aggregate
+    // ---- per digit: counts of earlier waves (kept in registers), the tile
+    // count, published as the tile's aggregate (inclusive at once for a
+    // chain's first tile); after the block scan each wave's counter becomes
+    // the digit's LDS offset for that wave, written once
     uint32_t tcount[R];
+    uint32_t wrun[R][WAVES];
     uint32_t tsum = 0;
     if (tid < DT) {
 #pragma unroll
@@ -845,21 +915,20 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
             uint32_t run = 0;
 #pragma unroll
             for (int w = 0; w < WAVES; ++w) {
-                const uint32_t c = s_whist[w * RADIX + d];
-                s_whist[w * RADIX + d] = run;
-                run += c;
+                wrun[r][w] = run;
+                run += lds.whist[w * RADIX + d];
             }
             // a partial tile's empty slots ranked as the last digit: they
-            // are not items (a chunk's first tile can be partial and still
+            // are not items (a chain's first tile can be partial and still
             // have successors that add this count)
             if (d == RADIX - 1) run -= TILE - valid;
             tcount[r] = run;
             tsum += run;
-            status_store(status + static_cast<size_t>(tile) * RADIX + d,
-                         St::make(static_cast<int32_t>(tile) == first ? kFlagIncl : kFlagAgg, run));
+            status_store(status + static_cast<size_t>(job.tile) * RADIX + d,
+                         St::make(job.tile == job.first ? kFlagIncl : kFlagAgg, run));
         }
     }
-    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
+    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, lds.wsum);
     uint32_t dexcl[R];
     if (tid < DT) {
         uint32_t run = texcl;
@@ -868,77 +937,134 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__
             const uint32_t d = tid * R + r;
             dexcl[r] = run;
 #pragma unroll
-            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + d] += run;
+            for (int w = 0; w < WAVES; ++w) lds.whist[w * RADIX + d] = wrun[r][w] + run;
             run += tcount[r];
         }
     }
     __syncthreads();
 
     // ---- gather keys and values by digit in LDS (tile rank = digit start +
-    // earlier waves + rank inside the wave)
+    // earlier waves + rank inside the wave): the GPU form of software
+    // write-combining, each digit's run now contiguous
     if constexpr (STAGE) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
+            uint32_t d = key_digit(key[j], shift, width);
             if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
             const uint32_t r = wh[d] + rnk[j];
-            s_stage_k[r] = key[j];
-            if constexpr (VALS) s_stage_v[r] = val[j];
+            lds.stage_k[r] = key[j];
+            if constexpr (VALS) lds.stage_v[r] = val[j];
         }
     }
 
-    // ---- lookback: the count of each digit in all earlier tiles
+    // ---- lookback: the count of each digit in the chain's earlier tiles
     if (tid < DT) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t d = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), first, d, RADIX, error_flag);
-            if (static_cast<int32_t>(tile) != first)
-                status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
-            // LDS slot i of digit d goes to output slot s_gbase[d] + i
-            s_gbase[d] = pass_base[d] + excl - dexcl[r];
+            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(job.tile),
+                                                    static_cast<int32_t>(job.first), d, RADIX, error_flag);
+            if (job.tile != job.first)
+                status_store(status + static_cast<size_t>(job.tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
+            // LDS slot i of digit d goes to output slot gbase[d] + i
+            lds.gbase[d] = job.base[d] + excl - dexcl[r];
         }
     }
     __syncthreads();
 
     // ---- scatter: consecutive LDS slots of one digit go to consecutive
-    // output addresses.  The clamp to n - 1 costs one op and keeps a logic
-    // error from ever turning into a store outside the array.  A full tile
-    // needs no per-slot guard, so the LDS reads of all slots are issued
-    // together (a guard per slot serialises them: 1 % slower passes).
+    // output addresses.  The clamp costs one op and keeps a logic error from
+    // ever turning into a store outside the array.  A full tile needs no
+    // per-slot guard, so the LDS reads of all slots are issued together.
+    const uint32_t last = job.bound - 1u;
     if (STAGE && full) {
-        uint32_t sk[IPT], sp[IPT];
+        K sk[IPT];
+        uint32_t sp[IPT];
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
+        for (int j = 0; j < IPT; ++j) sk[j] = lds.stage_k[j * BLOCK + tid];
 #pragma unroll
         for (int j = 0; j < IPT; ++j)
-            sp[j] = min(s_gbase[__builtin_amdgcn_ubfe(sk[j], shift, width)] + j * BLOCK + tid, n - 1u);
+            sp[j] = min(lds.gbase[key_digit(sk[j], shift, width)] + j * BLOCK + tid, last);
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            store_g<NT>(gelem<SMALL>(pp.dst_k, sp[j]), sk[j]);
-            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, sp[j]), s_stage_v[j * BLOCK + tid]);
+            store_t<NT, K>(gptr<K, SMALL>(job.dst_k, sp[j]), sk[j]);
+            if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, sp[j]), lds.stage_v[j * BLOCK + tid]);
         }
     } else if constexpr (STAGE) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const uint32_t i = j * BLOCK + tid;
-            const uint32_t k = s_stage_k[i];
-            const uint32_t p = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, width)] + i, n - 1u);
-            if (full || i < valid) {
-                store_g<NT>(gelem<SMALL>(pp.dst_k, p), k);
-                if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), s_stage_v[i]);
+            const K k = lds.stage_k[i];
+            const uint32_t p = min(lds.gbase[key_digit(k, shift, width)] + i, last);
+            if (i < valid) {
+                store_t<NT, K>(gptr<K, SMALL>(job.dst_k, p), k);
+                if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, p), lds.stage_v[i]);
             }
         }
     } else {  // each item from its registers: output slot = digit start + tile rank
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             if (!full && wslot0 + j * 64 >= valid) continue;
-            const uint32_t d = __builtin_amdgcn_ubfe(key[j], shift, width);
-            const uint32_t p = min(s_gbase[d] + wh[d] + rnk[j], n - 1u);
-            store_g<NT>(gelem<SMALL>(pp.dst_k, p), key[j]);
-            if constexpr (VALS) store_g<NT>(gelem<SMALL>(pp.dst_v, p), val[j]);
+            const uint32_t d = key_digit(key[j], shift, width);
+            const uint32_t p = min(lds.gbase[d] + wh[d] + rnk[j], last);
+            store_t<NT, K>(gptr<K, SMALL>(job.dst_k, p), key[j]);
+            if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, p), val[j]);
         }
     }
+}
+
+// One block per tile of BLOCK * IPT consecutive items of a single-array
+// pass (keys K, values V).  The pass's input is split into chunks (see
+// PassPlan); a block claims the next tile of the chunk of the XCD it runs
+// on, or of the next chunk with tiles left once that one is exhausted.
+// Tiles of a chunk are claimed in order from the chunk's counter, so a
+// block only ever waits on tiles claimed before it, by blocks that are
+// already running, whichever XCD they run on.  The tiles of a chunk are the
+// global grid of TILE-item tiles cut at the chunk's ends, so only a chunk's
+// first and last tile can be partial.  The grid needs ctile[nchunks]
+// blocks; surplus blocks find every chunk exhausted and exit.  The plan's
+// pointers are reinterpreted as K keys and V values.
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE>
+__device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V, VALS> &lds,
+                                              const SortPlan *__restrict__ plan, int pass, uint32_t n,
+                                              S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
+                                              uint32_t *__restrict__ error_flag) {
+    constexpr int TILE = BLOCK * IPT;
+    constexpr uint32_t RADIX = 1u << BITS;
+    // byte offsets fit in 32 bits (the 32-bit status words serve n < 2^30)
+    constexpr bool SMALL = sizeof(S) == 4 && sizeof(K) == 4 && sizeof(V) == 4;
+    const PassPlan *pp = plan->pass + pass;
+    if (!pp->active) return;
+    // this wave's digit counters start at zero
+    for (uint32_t i = threadIdx.x & 63u; i < RADIX; i += 64) lds.whist[(threadIdx.x >> 6) * RADIX + i] = 0u;
+    if (threadIdx.x == 0)
+        claim_tile<TILE>(pp, chunk_counter, lds.claim[0], lds.claim[1], lds.claim[2], lds.claim[3], lds.claim[4]);
+    __syncthreads();
+    if (lds.claim[0] == kNoTile) return;
+    TileJob<K, V> job;
+    job.src_k = reinterpret_cast<const K *>(pp->src_k);
+    job.src_v = reinterpret_cast<const V *>(pp->src_v);
+    job.dst_k = reinterpret_cast<K *>(pp->dst_k);
+    job.dst_v = reinterpret_cast<V *>(pp->dst_v);
+    job.base = pp->cbase + lds.claim[2] * kChunkRadix;
+    job.item0 = lds.claim[3];
+    job.shift = pp->shift;
+    job.width = pp->width;
+    job.tile = lds.claim[0];
+    job.first = lds.claim[1];
+    job.valid = lds.claim[4];
+    job.bound = n;
+    onesweep_tile<BITS, BLOCK, IPT, K, V, VALS, NT, S, STAGE, SMALL>(job, lds, status, error_flag);
+}
+
+// The pass over 32-bit keys (with 32-bit values when VALS).
+template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true>
+__global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
+                                                    S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
+                                                    uint32_t *__restrict__ error_flag) {
+    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS> lds;
+    onesweep_pass<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, NT, S, STAGE>(lds, plan, pass, n, status,
+                                                                           chunk_counter, error_flag);
 }
 
 // ---------------------------------------------------------------------------

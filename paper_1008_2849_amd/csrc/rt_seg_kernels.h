@@ -411,10 +411,12 @@ static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restri
 
 // One block per tile, claimed as in k_onesweep from nchunks chunks of whole
 // segments (chunk_counter: the launch's kChunks counters, zeroed before it;
-// chunk bounds from k_seg_tilemap with the same nchunks).  The tile's segment runs pass `pass`
-// (or its own d.pass when pass < 0): even passes read k/v and write tk/tv,
-// odd passes the reverse, so four passes leave the result in k/v and three
-// in tk/tv.  Status words: one per tile and digit, zeroed before the launch.
+// chunk bounds from k_seg_tilemap with the same nchunks), then the pass body
+// of onesweep_tile on it.  The tile's segment runs pass `pass` (or its own
+// d.pass when pass < 0): even passes read k/v and write tk/tv, odd passes the
+// reverse, so four passes leave the result in k/v and three in tk/tv.  The
+// segment's lookback chain starts at its first tile.  Status words: one per
+// tile and digit, zeroed before the launch.
 template <int BLOCK, int IPT, bool VALS, typename S>
 __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
                                                         const uint32_t *__restrict__ list,
@@ -424,172 +426,39 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
                                                         const uint32_t *__restrict__ base, S *__restrict__ status,
                                                         uint32_t *__restrict__ chunk_counter,
                                                         uint32_t *__restrict__ error_flag, uint32_t nchunks) {
-    constexpr int RADIX = kSegRadix;
-    constexpr int WAVES = BLOCK / 64;
     constexpr int TILE = BLOCK * IPT;
     static_assert(TILE == kSegTile, "tiles of the pass and of the tile map differ");
-    constexpr int WAVE_ITEMS = 64 * IPT;
-    constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;
-    constexpr int DT = RADIX / R;
     constexpr bool SMALL = sizeof(S) == 4;  // every segment below 2^30 items
-    using St = Status<S>;
+    __shared__ OnesweepLds<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS> lds;
 
-    __shared__ uint32_t s_stage_k[TILE];
-    __shared__ uint32_t s_stage_v[VALS ? TILE : 1];
-    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile;
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u;
-    const uint32_t wave = tid >> 6;
-    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;
-    uint32_t *wh = s_whist + wave * RADIX;
-    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
-
-    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
-    if (tid == 0) {
+    for (uint32_t i = threadIdx.x & 63u; i < static_cast<uint32_t>(kSegRadix); i += 64)
+        lds.whist[(threadIdx.x >> 6) * kSegRadix + i] = 0u;
+    if (threadIdx.x == 0) {
         uint32_t x = 0;
-        s_tile = claim_chunked(h->chunk_start, nchunks, chunk_counter, x);
+        lds.claim[0] = claim_chunked(h->chunk_start, nchunks, chunk_counter, x);
     }
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = lds.claim[0];
     if (tile >= h->total_tiles) return;  // kNoTile too
     const uint32_t e = tile_seg[tile];
     const SegDesc d = descs[list[e]];
     const uint32_t first = first_tile[e];
     const uint32_t p = pass >= 0 ? static_cast<uint32_t>(pass) : d.pass;
-    const uint32_t shift = p * kSegBits;
-    const uint32_t *src_k = (p & 1u) ? d.tk : d.k;
-    const uint32_t *src_v = (p & 1u) ? d.tv : d.v;
-    uint32_t *dst_k = (p & 1u) ? d.k : d.tk;
-    uint32_t *dst_v = (p & 1u) ? d.v : d.tv;
-    const uint32_t n = d.n;
-    const uint32_t tile_base = (tile - first) * TILE;
-    const uint32_t valid = min(static_cast<uint32_t>(TILE), n - tile_base);
-    const bool full = valid == static_cast<uint32_t>(TILE);
-
-    uint32_t key[IPT];
-    uint32_t val[VALS ? IPT : 1];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t i = wslot0 + j * 64;
-        key[j] = (full || i < valid) ? *gelem<SMALL>(src_k, tile_base + i) : 0u;
-    }
-    if constexpr (VALS) {  // a full tile loads its values halfway through the ranking
-        if (!full) {
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t i = wslot0 + j * 64;
-                val[j] = i < valid ? *gelem<SMALL>(src_v, tile_base + i) : 0u;
-            }
-        }
-    }
-
-    uint32_t rnk[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
-        if (!full && wslot0 + j * 64 >= valid) dg = RADIX - 1;
-        uint32_t lo, hi;
-        match_digit<kSegBits>(dg, lo, hi);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const uint32_t cnt = wh[dg];
-        rnk[j] = cnt + below;
-        uint32_t *dst = below == 0 ? wh + dg : scratch;
-        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
-        compiler_fence();
-        if constexpr (VALS) {
-            if (full && j == IPT / 2 - 1) {
-#pragma unroll
-                for (int q = 0; q < IPT; ++q) val[q] = *gelem<SMALL>(src_v, tile_base + wslot0 + q * 64);
-            }
-        }
-    }
-    __syncthreads();
-
-    uint32_t tcount[R];
-    uint32_t tsum = 0;
-    if (tid < DT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t dg = tid * R + r;
-            uint32_t run = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint32_t c = s_whist[w * RADIX + dg];
-                s_whist[w * RADIX + dg] = run;
-                run += c;
-            }
-            tcount[r] = run;
-            tsum += run;
-            status_store(status + static_cast<size_t>(tile) * RADIX + dg,
-                         St::make(tile == first ? kFlagIncl : kFlagAgg, run));
-        }
-    }
-    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
-    uint32_t dexcl[R];
-    if (tid < DT) {
-        uint32_t run = texcl;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t dg = tid * R + r;
-            dexcl[r] = run;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + dg] += run;
-            run += tcount[r];
-        }
-    }
-    __syncthreads();
-
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
-        if (!full && wslot0 + j * 64 >= valid) dg = RADIX - 1;
-        const uint32_t r = wh[dg] + rnk[j];
-        s_stage_k[r] = key[j];
-        if constexpr (VALS) s_stage_v[r] = val[j];
-    }
-
-    const uint32_t *pbase = base + (static_cast<size_t>(d.row) * kSegPasses + p) * RADIX;
-    if (tid < DT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t dg = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), static_cast<int32_t>(first),
-                                                    dg, kSegRadix, error_flag);
-            if (tile != first)
-                status_store(status + static_cast<size_t>(tile) * RADIX + dg, St::make(kFlagIncl, excl + tcount[r]));
-            s_gbase[dg] = pbase[dg] + excl - dexcl[r];
-        }
-    }
-    __syncthreads();
-
-    if (full) {  // no per-slot guard: the LDS reads of all slots issue together
-        uint32_t sk[IPT], sq[IPT];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j)
-            sq[j] = min(s_gbase[__builtin_amdgcn_ubfe(sk[j], shift, kSegBits)] + j * BLOCK + tid, n - 1u);
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            *gelem<SMALL>(dst_k, sq[j]) = sk[j];
-            if constexpr (VALS) *gelem<SMALL>(dst_v, sq[j]) = s_stage_v[j * BLOCK + tid];
-        }
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t i = j * BLOCK + tid;
-        const uint32_t k = s_stage_k[i];
-        const uint32_t q = min(s_gbase[__builtin_amdgcn_ubfe(k, shift, kSegBits)] + i, n - 1u);
-        if (i < valid) {
-            *gelem<SMALL>(dst_k, q) = k;
-            if constexpr (VALS) *gelem<SMALL>(dst_v, q) = s_stage_v[i];
-        }
-    }
+    TileJob<uint32_t, uint32_t> job;
+    job.src_k = (p & 1u) ? d.tk : d.k;
+    job.src_v = (p & 1u) ? d.tv : d.v;
+    job.dst_k = (p & 1u) ? d.k : d.tk;
+    job.dst_v = (p & 1u) ? d.v : d.tv;
+    job.base = base + (static_cast<size_t>(d.row) * kSegPasses + p) * kSegRadix;
+    job.item0 = static_cast<size_t>(tile - first) * TILE;
+    job.shift = p * kSegBits;
+    job.width = kSegBits;
+    job.tile = tile;
+    job.first = first;
+    job.valid = min(static_cast<uint32_t>(TILE), d.n - (tile - first) * static_cast<uint32_t>(TILE));
+    job.bound = d.n;
+    onesweep_tile<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS, false, S, true, SMALL>(job, lds, status,
+                                                                                        error_flag);
 }
 
 }  // namespace rt

@@ -161,188 +161,16 @@ __global__ __launch_bounds__(BLOCK) void k_histogram64_auto(const uint64_t *__re
 // onesweep counting-sort pass over 64-bit keys
 // ---------------------------------------------------------------------------
 
-// The structure of k_onesweep: tiles claimed in XCD chunks (claim_tile);
-// wave w owns items [w * 64 * IPT, (w + 1) * 64 * IPT) of the tile
-// and lane l holds item j * 64 + l in slot j, so the ballot ranking follows
-// input order (stable); per-digit tile counts are published as the tile's
-// aggregate, the tile is staged by digit in LDS, the lookback gives each
-// digit's offset among earlier tiles, and consecutive LDS slots of a digit
-// go to consecutive output addresses.  The plan's pointers are reinterpreted
-// as 64-bit keys and VW-word values.
+// The pass over 64-bit keys with values of VW 32-bit words (0, 1 or 2):
+// the single-array pass of k_onesweep on wider items.
 template <int BITS, int BLOCK, int IPT, int VW, typename S>
 __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                                       S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                                       uint32_t *__restrict__ error_flag) {
-    constexpr int RADIX = 1 << BITS;
-    constexpr int WAVES = BLOCK / 64;
-    constexpr int TILE = BLOCK * IPT;
-    constexpr int WAVE_ITEMS = 64 * IPT;
-    constexpr int R = RADIX >= BLOCK ? RADIX / BLOCK : 1;
-    constexpr int DT = RADIX / R;
-    constexpr bool VALS = VW > 0;
     typedef typename ValWord<VW>::type V;
-    typedef __attribute__((address_space(1))) V g_v;
-    using St = Status<S>;
-
-    const PassPlan pp = plan->pass[pass];
-    if (!pp.active) return;
-
-    __shared__ uint64_t s_stage_k[TILE];
-    __shared__ V s_stage_v[VALS ? TILE : 1];
-    __shared__ uint32_t s_whist[WAVES * RADIX + WAVES * 64];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ uint32_t s_wsum[WAVES];
-    __shared__ uint32_t s_tile, s_first, s_chunk, s_lo, s_valid;
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u;
-    const uint32_t wave = tid >> 6;
-    const uint32_t shift = pp.shift;
-    const uint32_t mask = (1u << pp.width) - 1u;
-    const uint32_t wslot0 = wave * WAVE_ITEMS + lane;
-    uint32_t *wh = s_whist + wave * RADIX;
-    uint32_t *scratch = s_whist + WAVES * RADIX + wave * 64 + lane;
-    const g_u64 *src_k = (const g_u64 *)pp.src_k;
-    g_u64 *dst_k = (g_u64 *)pp.dst_k;
-    const g_v *src_v = (const g_v *)pp.src_v;
-    g_v *dst_v = (g_v *)pp.dst_v;
-
-    for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
-    if (tid == 0) claim_tile<TILE>(plan->pass + pass, chunk_counter, s_tile, s_first, s_chunk, s_lo, s_valid);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile == kNoTile) return;
-    const int32_t first = static_cast<int32_t>(s_first);
-    const size_t tile_base = s_lo;
-    const uint32_t valid = s_valid;
-    const bool full = valid == static_cast<uint32_t>(TILE);
-    const uint32_t *pass_base = pp.cbase + s_chunk * kChunkRadix;
-
-    uint64_t key[IPT];
-    V val[VALS ? IPT : 1];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t i = wslot0 + j * 64;
-        key[j] = (full || i < valid) ? src_k[tile_base + i] : 0ull;
-    }
-    if constexpr (VALS) {  // a full tile loads its values halfway through the ranking
-        if (!full) {
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t i = wslot0 + j * 64;
-                val[j] = i < valid ? src_v[tile_base + i] : V(0);
-            }
-        }
-    }
-
-    // stable rank inside the wave; items past the end take the last digit
-    uint32_t rnk[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t d = digit64(key[j], shift, mask);
-        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
-        uint32_t lo, hi;
-        match_digit<BITS>(d, lo, hi);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const uint32_t cnt = wh[d];
-        rnk[j] = cnt + below;
-        uint32_t *dst = below == 0 ? wh + d : scratch;
-        *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
-        compiler_fence();
-        if constexpr (VALS) {
-            if (full && j == IPT / 2 - 1) {
-#pragma unroll
-                for (int q = 0; q < IPT; ++q) val[q] = src_v[tile_base + wslot0 + q * 64];
-            }
-        }
-    }
-    __syncthreads();
-
-    // per digit: earlier waves' counts, tile count, publish the aggregate
-    uint32_t tcount[R];
-    uint32_t tsum = 0;
-    if (tid < DT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t d = tid * R + r;
-            uint32_t run = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint32_t c = s_whist[w * RADIX + d];
-                s_whist[w * RADIX + d] = run;
-                run += c;
-            }
-            if (d == RADIX - 1) run -= TILE - valid;  // a partial tile's empty slots are not items
-            tcount[r] = run;
-            tsum += run;
-            status_store(status + static_cast<size_t>(tile) * RADIX + d,
-                         St::make(static_cast<int32_t>(tile) == first ? kFlagIncl : kFlagAgg, run));
-        }
-    }
-    const uint32_t texcl = block_exclusive_sum<BLOCK>(tid < DT ? tsum : 0u, s_wsum);
-    uint32_t dexcl[R];
-    if (tid < DT) {
-        uint32_t run = texcl;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t d = tid * R + r;
-            dexcl[r] = run;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) s_whist[w * RADIX + d] += run;
-            run += tcount[r];
-        }
-    }
-    __syncthreads();
-
-    // gather by digit in LDS
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        uint32_t d = digit64(key[j], shift, mask);
-        if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
-        const uint32_t r = wh[d] + rnk[j];
-        s_stage_k[r] = key[j];
-        if constexpr (VALS) s_stage_v[r] = val[j];
-    }
-
-    // lookback
-    if (tid < DT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t d = tid * R + r;
-            const uint32_t excl = lookback_digit<S>(status, static_cast<int32_t>(tile), first, d, RADIX, error_flag);
-            if (static_cast<int32_t>(tile) != first)
-                status_store(status + static_cast<size_t>(tile) * RADIX + d, St::make(kFlagIncl, excl + tcount[r]));
-            s_gbase[d] = pass_base[d] + excl - dexcl[r];
-        }
-    }
-    __syncthreads();
-
-    // scatter; the clamp keeps a logic error from storing outside the array.
-    // A full tile needs no per-slot guard, so its LDS reads issue together.
-    if (full) {
-        uint64_t sk[IPT];
-        uint32_t sp[IPT];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) sk[j] = s_stage_k[j * BLOCK + tid];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) sp[j] = min(s_gbase[digit64(sk[j], shift, mask)] + j * BLOCK + tid, n - 1u);
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            dst_k[sp[j]] = sk[j];
-            if constexpr (VALS) dst_v[sp[j]] = s_stage_v[j * BLOCK + tid];
-        }
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t i = j * BLOCK + tid;
-        const uint64_t k = s_stage_k[i];
-        const uint32_t p = min(s_gbase[digit64(k, shift, mask)] + i, n - 1u);
-        if (i < valid) {
-            dst_k[p] = k;
-            if constexpr (VALS) dst_v[p] = s_stage_v[i];
-        }
-    }
+    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint64_t, V, (VW > 0)> lds;
+    onesweep_pass<BITS, BLOCK, IPT, uint64_t, V, (VW > 0), false, S, true>(lds, plan, pass, n, status,
+                                                                           chunk_counter, error_flag);
 }
 
 // Moves the result of a sort with exactly one executed pass from the

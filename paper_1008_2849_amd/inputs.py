@@ -40,6 +40,7 @@ SEED_BATCHED = 4          # 4096 segments
 SEED_SERVING = 5          # serving request stream
 SEED_PAIRS64_256M = 6     # 2^28 uniform 64-bit keys with 32-bit index values
 SEED_TABLE1 = 7           # 2^26 (64 Mi) uniform keys: the paper's own N, keys only and pairs
+SEED_KEYS_256M = 8        # 2^28 uniform keys, keys only
 
 # Distribution ids shared with the device generator.
 DIST_UNIFORM = 0
@@ -276,6 +277,7 @@ class Workload:
 WORKLOADS: Dict[str, Workload] = {
     "keys_1m_uniform": Workload("keys_1m_uniform", 2**20, False, "uniform", SEED_KEYS_1M),
     "pairs_256m_uniform": Workload("pairs_256m_uniform", 2**28, True, "uniform", SEED_PAIRS_256M),
+    "keys_256m_uniform": Workload("keys_256m_uniform", 2**28, False, "uniform", SEED_KEYS_256M),
     "pairs_64m_and2": Workload("pairs_64m_and2", 2**26, True, "and", SEED_AND[2], 2),
     "pairs_64m_and4": Workload("pairs_64m_and4", 2**26, True, "and", SEED_AND[4], 4),
     "pairs_64m_and8": Workload("pairs_64m_and8", 2**26, True, "and", SEED_AND[8], 8),
