@@ -137,6 +137,24 @@ size_t rt_workspace_bytes(size_t n, int with_values, const rt_config *cfg);
 rt_status rt_sort_pairs_ex(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
                            void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * rt_sort_pairs_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sort, with the library's static per-device scratch
+ * array (64 MiB, held until the process ends) as its workspace.  It calls
+ * no hipMalloc, hipFree or other allocating routine.  n items must fit that
+ * scratch (rt_workspace_bytes(n, vals != NULL, cfg) <= 64 MiB: about 3.9M
+ * pairs or 7.8M keys with the tuned configuration); larger n is
+ * RT_ERR_TOO_LARGE, before any device work.  Arguments, cfg, flags and
+ * errors as for rt_sort_pairs_ex.  Every call on one GPU uses that GPU's
+ * one scratch array: calls that overlap on a GPU (other streams, other
+ * threads) race and corrupt each other's results; calls ordered on one
+ * stream are fine.  Each call clears, with its own kernels, whatever part
+ * of the scratch must start at zero.
+ */
+rt_status rt_sort_pairs_noalloc(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+                                hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * 64-bit keys
  * --------------------------------------------------------------------- */

@@ -93,6 +93,7 @@ SIGNATURES = {
     "rt_sort_pairs": (ctypes.c_int, [vp, vp, sz, vp]),
     "rt_workspace_bytes": (sz, [sz, ctypes.c_int, ctypes.POINTER(RtConfig)]),
     "rt_sort_pairs_ex": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
+    "rt_sort_pairs_noalloc": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp]),
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
     "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
     "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),

@@ -128,6 +128,18 @@ def sort_ex(keys, vals=None, cfg: Optional[Config] = None, workspace=None, strea
           "rt_sort_pairs_ex")
 
 
+def sort_noalloc(keys, vals=None, cfg: Optional[Config] = None, stream=None) -> None:
+    """The sort of sort_ex with the library's static scratch as workspace:
+    no device allocation (at most rt_workspace_bytes() <= 64 MiB of work)."""
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals")
+    if vals is not None and vals.numel() != keys.numel():
+        raise ValueError("keys and vals differ in length")
+    c, p = _cfg_ptr(cfg)
+    check(lib().rt_sort_pairs_noalloc(_ptr(keys), _ptr(vals), keys.numel(), p, _stream(stream)),
+          "rt_sort_pairs_noalloc")
+
+
 def _check_tensor64(t, name: str, dtypes):
     torch = _torch()
     if t is None:

@@ -556,6 +556,73 @@ extern "C" rt_status rt_sort_pairs_ex(uint32_t *keys, uint32_t *vals, size_t n, 
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// the sort without allocation: a static device scratch array as workspace
+// ---------------------------------------------------------------------------
+
+// Workspace of rt_sort_pairs_noalloc: one array per device, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a host-side stand-in); it uses the device address
+// noalloc_scratch() looked up once per device.
+constexpr size_t kNoAllocScratchBytes = static_cast<size_t>(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> address of its scratch
+}  // namespace
+
+// The current device's scratch address, looked up with that device current
+// on the first call on it.
+static rt_status noalloc_scratch(void **out, const char *what) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: hipGetDevice: %s", what, hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return RT_OK;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return set_error(RT_ERR_HIP, "%s: hipGetSymbolAddress(scratch): %s", what, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_sort_pairs_noalloc(uint32_t *keys, uint32_t *vals, size_t n, const rt_config *cfg,
+                                           hipStream_t stream) {
+    rt_status s = check_ranges(keys, vals, n, "rt_sort_pairs_noalloc");
+    if (s != RT_OK || n < 2) return s;
+    Resolved r;
+    s = resolve_config(cfg, n, vals != nullptr, &r);
+    if (s != RT_OK) return s;
+    const Layout L = make_layout(n, r, false);
+    if (L.total > kNoAllocScratchBytes)
+        return set_error(RT_ERR_TOO_LARGE,
+                         "rt_sort_pairs_noalloc: %zu items need %zu bytes of workspace; the static scratch holds %zu "
+                         "(use rt_sort_pairs_ex)",
+                         n, L.total, kNoAllocScratchBytes);
+    void *ws = nullptr;
+    s = noalloc_scratch(&ws, "rt_sort_pairs_noalloc");
+    if (s != RT_OK) return s;
+    // every region that must start at zero (histograms, lookback words,
+    // tile counters, error word) is cleared by the sort's own kernels
+    launch_sort(keys, vals, static_cast<uint32_t>(n), r, L, static_cast<char *>(ws), false, nullptr, nullptr,
+                stream);
+    s = finish_call(stream, "rt_sort_pairs_noalloc");
+    if (s == RT_OK && ((r.flags & RT_FLAG_VALIDATE) || debug_sync_enabled())) {
+        uint32_t err = 0;
+        s = read_device_word(static_cast<char *>(ws) + L.ctr + sizeof(uint32_t) * kMaxPasses, stream, &err,
+                             "rt_sort_pairs_noalloc");
+        if (s == RT_OK && err) return set_error(RT_ERR_HIP, "rt_sort_pairs_noalloc: device error word 0x%x", err);
+    }
+    return s;
+}
+
 extern "C" rt_status rt_sort_keys(uint32_t *keys, size_t n, hipStream_t stream) {
     return rt_sort_pairs_ex(keys, nullptr, n, nullptr, nullptr, 0, stream);
 }
