@@ -218,11 +218,17 @@ def bench_batched(rts, inputs, dev, K, W, single_gkeys):
     for i in range(W):
         graphs[i].replay()
     torch.cuda.synchronize()
+    # each replay bracketed by events on the stream it runs on (back to
+    # back, as the wall-clock figure): its latency on the device
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     t0 = time.perf_counter()
-    for i in range(W, W + K):
+    for j, i in enumerate(range(W, W + K)):
+        ev[j][0].record()
         graphs[i].replay()
+        ev[j][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    replay_ms = [a.elapsed_time(b) for a, b in ev]
     del graphs
     # properties of the last output: within every segment keys ascend, each
     # key arrives with its own index, indices stay in their segment and in
@@ -245,10 +251,13 @@ def bench_batched(rts, inputs, dev, K, W, single_gkeys):
             "segments": len(sizes), "launch": "one hipGraph replay per call",
             "Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
             "eager_Gkeys/s": round(n / (eager_wall / K) / 1e9, 3),
+            "replay_p50_ms": round(float(np.percentile(replay_ms, 50)), 4),
+            "replay_p99_ms": round(float(np.percentile(replay_ms, 99)), 4),
             "eager_call_p50_ms": round(float(np.percentile(per_call, 50)), 4),
             "eager_call_p99_ms": round(float(np.percentile(per_call, 99)), 4),
             "tiled_pass_ms": round(float(np.mean(pass_ms)), 4) if pass_ms else None,
-            "size_classes": [list(c) for c in rts.segment_classes()],
+            "size_classes": [list(c) + [b] for c, b in zip(rts.segment_classes(), rts.segment_config()[0])],
+            "tiled_tile": list(rts.segment_config()[1]),
             "frac_of_single_array": round(gk / single_gkeys, 4), "parity_properties_ok": ok}
 
 

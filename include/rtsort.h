@@ -439,8 +439,10 @@ rt_status rt_server_destroy(rt_server *s);
  * "pairs" entries map single-array sorts of n in [min_n, max_n] to digit
  * widths, block size, items per thread and flags; its "segments" entries
  * (increasing max_n, at most 4, each at most 16384 and within its shape,
- * digits 8,8,8,8) are the whole-in-LDS size classes of the segmented sort
- * (see rt_segment_classes).  A malformed table is RT_ERR_INVALID_ARG and
+ * digits 8,8,8,8 or 11,11,10) are the whole-in-LDS size classes of the
+ * segmented sort (see rt_segment_classes), and a "segments_tiled" entry
+ * (block x ipt of 1024x16 or 512x16, digits 8,8,8,8) its tiled passes' tile
+ * (see rt_segment_config).  A malformed table is RT_ERR_INVALID_ARG and
  * leaves the loaded one in force.  NULL restores the built-in defaults.
  */
 rt_status rt_load_tuning(const char *json_path);
@@ -486,6 +488,16 @@ rt_status rt_profile_stop(uint32_t *kinds, float *ms, uint32_t capacity, uint32_
  * server those in force when it was created.
  */
 rt_status rt_segment_classes(uint32_t *count, uint32_t *max_n, uint32_t *block, uint32_t *ipt);
+
+/*
+ * The rest of the segmented sort's tuning in force: bits[c] (host array of
+ * at least 4 entries, may be NULL) the digit width of class c's passes (8:
+ * four 8-bit passes; 11: passes of 11, 11 and 10 bits), and the tile of the
+ * tiled segments' passes in batched calls and MSD-first sorts, tile_block x
+ * tile_ipt items (1024 x 16 or 512 x 16; the server keeps 1024 x 16).  Any
+ * pointer may be NULL.
+ */
+rt_status rt_segment_config(uint32_t *bits, uint32_t *tile_block, uint32_t *tile_ipt);
 
 const char *rt_status_string(rt_status s);
 const char *rt_last_error(void);

@@ -103,6 +103,7 @@ SIGNATURES = {
     "rt_workspace_bytes64": (sz, [sz, u32, ctypes.POINTER(RtConfig)]),
     "rt_msd_first_workspace_bytes": (sz, [sz, ctypes.c_int]),
     "rt_segment_classes": (ctypes.c_int, [ctypes.POINTER(u32)] * 4),
+    "rt_segment_config": (ctypes.c_int, [ctypes.POINTER(u32)] * 3),
     "rt_sort_msd_first": (ctypes.c_int, [vp, vp, sz, u32, vp, sz, vp]),
     "rt_digit_histograms": (ctypes.c_int, [vp, sz, ctypes.POINTER(RtConfig), vp, vp]),
     "rt_counting_pass": (ctypes.c_int, [vp, vp, vp, vp, sz, u32, u32, vp]),

@@ -329,6 +329,17 @@ def segment_classes():
     return [(int(arrs[0][c]), int(arrs[1][c]), int(arrs[2][c])) for c in range(count.value)]
 
 
+def segment_config():
+    """(digit bits of each whole-in-LDS class, (tile threads, tile items per
+    thread) of the tiled segments' passes) in force."""
+    count = ctypes.c_uint32(0)
+    check(lib().rt_segment_classes(ctypes.byref(count), None, None, None), "rt_segment_classes")
+    bits = (ctypes.c_uint32 * 4)()
+    tb, ti = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    check(lib().rt_segment_config(bits, ctypes.byref(tb), ctypes.byref(ti)), "rt_segment_config")
+    return [int(bits[c]) for c in range(count.value)], (int(tb.value), int(ti.value))
+
+
 def version() -> str:
     return lib().rt_version().decode()
 

@@ -13,14 +13,16 @@ counts, so a configuration can only win by sorting correctly.
 
 Segmented sort ("segments"): for each size range (2^(k-1), 2^k], k = 6..14,
 it sorts a batch of about 2^23 items in segments of sizes uniform in the
-range, once with each whole-in-LDS kernel shape that holds 2^k items and
-once with the range left to the tiled path, and keeps the fastest (each
-output must equal the built-in classes' output bit for bit).  Consecutive
-ranges with the same winner form one class; the classes stop at the first
-range where tiling wins, and at most four are kept (the split with the
-least per-segment time, found by dynamic programming).  The split is then
-timed on the batched workload's log-uniform mix against the built-in
-classes, and the faster of the two is written.
+range, once with each whole-in-LDS kernel shape that holds 2^k items under
+each digit width it is built for (four 8-bit passes, or 11/11/10), and once
+with the range left to the tiled path under each tile (1024x16, 512x16),
+and keeps the fastest (each output must equal the built-in classes' output
+bit for bit).  The classes are at most four contiguous runs of ranges, one
+shape and digit width each, ending where tiling wins (the split with the
+least per-segment time, found by dynamic programming).  The split and the
+built-in classes are then timed on the batched workload's log-uniform mix
+with either tile, and the fastest pair is written: the "segments" entries
+(with their digit widths) and a "segments_tiled" entry (the tile).
 """
 from __future__ import annotations
 
@@ -128,26 +130,41 @@ SEG_RANGES = list(range(6, 15))  # (2^(k-1), 2^k]
 SEG_BATCH_ITEMS = 1 << 23
 
 
-def _segment_table(classes):
-    return {"entries": [{"op": "segments", "min_n": 0, "max_n": m, "digit_bits": [8, 8, 8, 8],
-                         "block": b, "ipt": i} for m, b, i in classes]}
+SEG_BITS = {8: (8, 8, 8, 8), 11: (11, 11, 10)}
+SEG_TILES = [(1024, 16), (512, 16)]  # tiles of the tiled segments' passes; keep in step with rt_common.h
 
 
-def _time_batched(keys0, vals0, off, n, classes, reps, check, tmpdir):
+def seg_small_supported(b, i, bits):
+    """Whether the library compiles the whole-in-LDS kernel b x i with
+    bits-bit digits (11-bit counters need 8 KiB a wave: at most 512 threads)."""
+    return bits == 8 or b <= 512
+
+
+def _segment_table(classes, tile=(1024, 16)):
+    """classes: [(max_n, block, ipt, bits)]; tile: (block, ipt) of the tiled passes."""
+    entries = [{"op": "segments", "min_n": 0, "max_n": m, "digit_bits": list(SEG_BITS[bits]),
+                "block": b, "ipt": i} for m, b, i, bits in classes]
+    entries.append({"op": "segments_tiled", "min_n": 0, "max_n": 0, "digit_bits": [8, 8, 8, 8],
+                    "block": tile[0], "ipt": tile[1]})
+    return {"entries": entries}
+
+
+def _time_batched(keys0, vals0, off, n, classes, reps, check, tmpdir, tile=(1024, 16), latencies=False):
     """Median call time (ms, from the library's kernel marks) of a batched
-    sort under the given classes, after checking its output."""
+    sort under the given classes and tile, after checking its output (with
+    latencies: also the sorted per-call times)."""
     import os
     import torch
     path = os.path.join(tmpdir, "seg_candidate.json")
     with open(path, "w") as f:
-        json.dump(_segment_table(classes), f)
+        json.dump(_segment_table(classes, tile), f)
     api.load_tuning(path)
     ws = torch.empty(api.batched_workspace_bytes(off.numel() - 1, n, True), dtype=torch.uint8, device=keys0.device)
     slots = [(keys0.clone(), vals0.clone()) for _ in range(reps + 1)]
     api.sort_batched_ex(slots[0][0], slots[0][1], off, n, workspace=ws)
     torch.cuda.synchronize()
     if check is not None and not (torch.equal(slots[0][0], check[0]) and torch.equal(slots[0][1], check[1])):
-        raise RuntimeError(f"classes {classes} sorted incorrectly")
+        raise RuntimeError(f"classes {classes}, tile {tile} sorted incorrectly")
     api.profile_start(64 * reps + 64)
     for k, v in slots[1:]:
         api.sort_batched_ex(k, v, off, n, workspace=ws)
@@ -160,11 +177,18 @@ def _time_batched(keys0, vals0, off, n, classes, reps, check, tmpdir):
         elif cur is not None:
             cur[0] += ms
     times = sorted(c[0] for c in calls)
+    if latencies:
+        return times[len(times) // 2], times
     return times[len(times) // 2], (slots[0][0], slots[0][1])
 
 
+def _key(b, i, bits):
+    return f"{b}x{i}@{bits}"
+
+
 def tune_segments(reps, log=print):
-    """Whole-in-LDS size classes of the segmented sort; returns (entries, report)."""
+    """Whole-in-LDS size classes of the segmented sort (shape and digit width
+    per class) and the tile of its tiled passes; returns (entries, report)."""
     import tempfile
     import numpy as np
     import torch
@@ -190,24 +214,28 @@ def tune_segments(reps, log=print):
             for b, i in SEG_SHAPES:
                 if b * i < hi:
                     continue
-                t, _ = _time_batched(keys0, vals0, off, n, [(hi, b, i)], reps, ref, tmpdir)
-                times[(b, i)] = t
-                log(f"  segments ({lo}..{hi}] x{count}: {b}x{i} {t:.4f} ms")
+                for bits in SEG_BITS:
+                    if not seg_small_supported(b, i, bits):
+                        continue
+                    t, _ = _time_batched(keys0, vals0, off, n, [(hi, b, i, bits)], reps, ref, tmpdir)
+                    times[_key(b, i, bits)] = t
+                    log(f"  segments ({lo}..{hi}] x{count}: {b}x{i} {bits}-bit digits {t:.4f} ms")
             # one class that ends below the range: every segment of it is tiled
-            t, _ = _time_batched(keys0, vals0, off, n, [(lo - 1, 1024, 16)], reps, ref, tmpdir)
-            times["tiled"] = t
-            log(f"  segments ({lo}..{hi}] x{count}: tiled {t:.4f} ms")
-            best = min(times, key=times.get)
+            for tb, ti in SEG_TILES:
+                t, _ = _time_batched(keys0, vals0, off, n, [(lo - 1, 1024, 16, 8)], reps, ref, tmpdir, (tb, ti))
+                times[f"tiled@{tb}x{ti}"] = t
+                log(f"  segments ({lo}..{hi}] x{count}: tiled {tb}x{ti} {t:.4f} ms")
+            times["tiled"] = min(v for c, v in times.items() if c.startswith("tiled@"))
+            best = min((c for c in times if c != "tiled"), key=times.get)
             report.append({"op": "segments", "range": [lo, hi], "segments": count, "items": n,
-                           "best": list(best) if best != "tiled" else "tiled",
-                           "ms": {("x".join(map(str, c)) if c != "tiled" else c): round(v, 4)
-                                  for c, v in times.items()}})
+                           "best": best, "ms": {c: round(v, 4) for c, v in times.items()}})
             del keys0, vals0, off, ref
             torch.cuda.empty_cache()
     api.load_tuning(None)
     entries = segment_entries(report)
-    # the split must also pay off on a mix of sizes: the batched workload
-    # (log-uniform sizes) under the split and under the built-in classes
+    # the split and the tile must also pay off on a mix of sizes: the batched
+    # workload (log-uniform sizes) under the split and under the built-in
+    # classes, each with either tile
     sizes = inputs.batched_sizes()
     off_h = np.zeros(len(sizes) + 1, dtype=np.uint32)
     off_h[1:] = np.cumsum(sizes)
@@ -218,20 +246,27 @@ def tune_segments(reps, log=print):
     ref = keys0.clone(), vals0.clone()
     api.sort_pairs_batched(ref[0], ref[1], off, n)
     torch.cuda.synchronize()
-    split = [(e["max_n"], e["block"], e["ipt"]) for e in entries]
-    builtin = [(2048, 256, 8), (8192, 512, 16), (16384, 1024, 16)]
+    split = [(e["max_n"], e["block"], e["ipt"], 8 if e["digit_bits"][0] == 8 else 11) for e in entries]
+    builtin = [(2048, 256, 8, 8), (8192, 512, 16, 8), (16384, 1024, 16, 8)]
+    results = {}
     with tempfile.TemporaryDirectory() as tmpdir:
-        t_split, _ = _time_batched(keys0, vals0, off, n, split, max(reps, 9), ref, tmpdir)
-        t_builtin, _ = _time_batched(keys0, vals0, off, n, builtin, max(reps, 9), ref, tmpdir)
+        for name, cls in (("split", split), ("builtin", builtin)):
+            for tile in SEG_TILES:
+                t, _ = _time_batched(keys0, vals0, off, n, cls, max(reps, 9), ref, tmpdir, tile)
+                results[(name, tile)] = t
+                log(f"  batched workload: {name} classes, tile {tile[0]}x{tile[1]}: {t:.4f} ms")
     api.load_tuning(None)
-    chosen = "split" if t_split <= t_builtin else "builtin"
-    log(f"  batched workload: split {t_split:.4f} ms, built-in {t_builtin:.4f} ms -> {chosen}")
+    (chosen, tile), t_best = min(results.items(), key=lambda kv: kv[1])
+    log(f"  batched workload: {chosen} classes with tile {tile[0]}x{tile[1]} ({t_best:.4f} ms)")
     report.append({"op": "segments_workload", "segments": len(sizes), "items": n,
-                   "split": [list(c) for c in split], "split_ms": round(t_split, 4),
-                   "builtin_ms": round(t_builtin, 4), "chosen": chosen})
+                   "split": [list(c) for c in split],
+                   "ms": {f"{nm} tile {tl[0]}x{tl[1]}": round(v, 4) for (nm, tl), v in results.items()},
+                   "chosen": chosen, "tile": list(tile)})
     if chosen == "builtin":
-        entries = [{"op": "segments", "min_n": lo + 1, "max_n": m, "digit_bits": [8, 8, 8, 8], "block": b,
-                    "ipt": i, "flags": 0} for lo, (m, b, i) in zip([0, 2048, 8192], builtin)]
+        entries = [{"op": "segments", "min_n": lo + 1, "max_n": m, "digit_bits": list(SEG_BITS[bits]), "block": b,
+                    "ipt": i, "flags": 0} for lo, (m, b, i, bits) in zip([0, 2048, 8192], builtin)]
+    entries.append({"op": "segments_tiled", "min_n": 0, "max_n": 0, "digit_bits": [8, 8, 8, 8],
+                    "block": tile[0], "ipt": tile[1], "flags": 0})
     return entries, report
 
 
@@ -239,26 +274,26 @@ def segment_entries(report):
     """Size classes from the per-range measurements of tune_segments.
 
     The ranges are split, from the smallest up, into at most four
-    contiguous classes, each sorted by one whole-in-LDS shape that holds its
-    largest range, with every range above the last class left to the tiled
-    path.  Among all such splits (by dynamic programming over the ranges)
-    the one with the least total time per segment wins; per-segment times
-    (a range's time over its segment count) weigh the ranges as a
-    log-uniform size mix does.
+    contiguous classes, each sorted by one whole-in-LDS shape and digit
+    width (a "BxI@bits" candidate) that holds its largest range, with every
+    range above the last class left to the tiled path.  Among all such
+    splits (by dynamic programming over the ranges) the one with the least
+    total time per segment wins; per-segment times (a range's time over its
+    segment count) weigh the ranges as a log-uniform size mix does.
     """
     rows = sorted((r for r in report if r["op"] == "segments"), key=lambda r: r["range"][1])
     if not rows:
         return []
     per_seg = [{c: t / r["segments"] for c, t in r["ms"].items()} for r in rows]
-    shapes = sorted({c for r in rows for c in r["ms"] if c != "tiled"},
-                    key=lambda c: [int(x) for x in c.split("x")])
-    cap = {c: int(c.split("x")[0]) * int(c.split("x")[1]) for c in shapes}
+    shapes = sorted({c for r in rows for c in r["ms"] if not c.startswith("tiled")},
+                    key=lambda c: [int(x) for x in c.replace("@", "x").split("x")])
+    cap = {c: int(c.split("x")[0]) * int(c.split("x")[1].split("@")[0]) for c in shapes}
     R = len(rows)
     tiled_tail = [0.0] * (R + 1)  # ranges i.. left to the tiled path
     for i in range(R - 1, -1, -1):
         tiled_tail[i] = tiled_tail[i + 1] + per_seg[i]["tiled"]
 
-    def span(i, j):  # ranges i..j as one class: its best shape and cost
+    def span(i, j):  # ranges i..j as one class: its best candidate and cost
         best = None
         for c in shapes:
             if cap[c] < rows[j]["range"][1] or any(c not in per_seg[q] for q in range(i, j + 1)):
@@ -296,8 +331,9 @@ def segment_entries(report):
     classes.reverse()
     entries, prev = [], 0
     for max_n, c in classes:
-        b, i = (int(x) for x in c.split("x"))
-        entries.append({"op": "segments", "min_n": prev + 1, "max_n": max_n, "digit_bits": [8, 8, 8, 8],
+        shape, bits = c.split("@")
+        b, i = (int(x) for x in shape.split("x"))
+        entries.append({"op": "segments", "min_n": prev + 1, "max_n": max_n, "digit_bits": list(SEG_BITS[int(bits)]),
                         "block": b, "ipt": i, "flags": 0})
         prev = max_n
     return entries
@@ -338,7 +374,7 @@ def main(argv=None) -> int:
         report += seg_report
     tuned = {e["op"] for e in entries} | ops
     if "segments" in tuned:
-        tuned.add("segments_workload")
+        tuned |= {"segments_workload", "segments_tiled"}
     entries = [e for e in old.get("entries", []) if e["op"] not in tuned] + entries
     report = [r for r in old.get("measurements", []) if r.get("op") not in tuned] + report
     table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0),

@@ -20,28 +20,36 @@ SegClassLimits SegClassTable::limits() const {
     return l;
 }
 
-bool seg_small_shape_supported(int block, int ipt) {
-#define RT_SEG_SHAPE_CASE(BLK, I) \
-    if (block == BLK && ipt == I) return true;
+bool seg_small_shape_supported(int block, int ipt, int bits) {
+#define RT_SEG_SHAPE_CASE(BLK, I, B) \
+    if (block == BLK && ipt == I && bits == B) return true;
     RT_FOR_EACH_SEG_SMALL_SHAPE(RT_SEG_SHAPE_CASE)
 #undef RT_SEG_SHAPE_CASE
     return false;
 }
 
+bool seg_tile_shape_supported(int block, int ipt) {
+#define RT_SEG_TILE_CASE(BLK, I) \
+    if (block == BLK && ipt == I) return true;
+    RT_FOR_EACH_SEG_TILE_SHAPE(RT_SEG_TILE_CASE)
+#undef RT_SEG_TILE_CASE
+    return false;
+}
+
 void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStream_t stream, const SegDesc *descs,
-                      const uint32_t *list, const SegHeader *h, int which, int passes, int to_temp) {
+                      const uint32_t *list, const SegHeader *h, int which, int key_bits, int to_temp) {
     // enough blocks to fill the CUs: more per CU for smaller shapes (LDS)
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
     const uint32_t per_cu = std::max<uint32_t>(1u, kSegLdsMax / static_cast<uint32_t>(c.block * c.ipt));
     const uint32_t grid = std::max<uint32_t>(1u, std::min<uint32_t>(max_listed, cus * per_cu));
-#define RT_SEG_SHAPE_LAUNCH(BLK, I)                                                                              \
-    if (c.block == BLK && c.ipt == I) {                                                                          \
+#define RT_SEG_SHAPE_LAUNCH(BLK, I, B)                                                                           \
+    if (c.block == BLK && c.ipt == I && c.bits == B) {                                                           \
         if (vals)                                                                                                \
-            hipLaunchKernelGGL((k_seg_small<BLK, I, true>), dim3(grid), dim3(BLK), 0, stream, descs, list, h,    \
-                               which, passes, to_temp);                                                          \
+            hipLaunchKernelGGL((k_seg_small<BLK, I, true, B>), dim3(grid), dim3(BLK), 0, stream, descs, list, h, \
+                               which, key_bits, to_temp);                                                        \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_seg_small<BLK, I, false>), dim3(grid), dim3(BLK), 0, stream, descs, list, h,   \
-                               which, passes, to_temp);                                                          \
+            hipLaunchKernelGGL((k_seg_small<BLK, I, false, B>), dim3(grid), dim3(BLK), 0, stream, descs, list,   \
+                               h, which, key_bits, to_temp);                                                     \
         return;                                                                                                  \
     }
     RT_FOR_EACH_SEG_SMALL_SHAPE(RT_SEG_SHAPE_LAUNCH)
@@ -55,7 +63,8 @@ SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_valu
     L.classes = seg_class_table();
     const size_t large_cap = std::min<size_t>(num_segments, capacity / (L.classes.lds_max() + 1));
     L.large_capacity = static_cast<uint32_t>(large_cap);
-    L.max_tiles = static_cast<uint32_t>((capacity + kSegTile - 1) / kSegTile + large_cap);
+    L.tile = L.classes.tile();
+    L.max_tiles = static_cast<uint32_t>((capacity + L.tile - 1) / L.tile + large_cap);
     L.wide_status = capacity >= (static_cast<size_t>(1) << 30);
     const size_t sw = L.wide_status ? 8 : 4;
     size_t off = 0;
@@ -93,12 +102,12 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
     uint32_t *large_list = P.lists + static_cast<size_t>(kSegLarge) * list_stride;
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
-                       L.large_capacity, L.max_tiles);
+                       L.large_capacity, L.max_tiles, L.tile);
     hipLaunchKernelGGL(k_seg_tilemap, dim3(cap_grid((L.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, stream,
                        P.first_tile, P.header, P.tile_seg, nchunks);
     prof_mark(stream, RT_KIND_SEGMENTED);
     hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
-                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist);
+                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist, L.tile);
     prof_mark(stream, RT_KIND_HISTOGRAM);
     hipLaunchKernelGGL(k_seg_plan, dim3(cap_grid(L.large_capacity, cus * 4)), dim3(256), 0, stream, P.descs,
                        large_list, P.header, P.hist, P.base);
@@ -106,15 +115,19 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     // whole-in-LDS classes
     for (uint32_t c = 0; c < L.classes.count; ++c)
         launch_seg_small(L.classes.cls[c], VALS, list_stride, stream, P.descs,
-                         P.lists + static_cast<size_t>(c) * list_stride, P.header, static_cast<int>(c), passes,
-                         to_temp);
+                         P.lists + static_cast<size_t>(c) * list_stride, P.header, static_cast<int>(c),
+                         passes * kSegBits, to_temp);
     prof_mark(stream, RT_KIND_SEG_SMALL);
     for (int p = 0; p < passes; ++p) {
         S *status = reinterpret_cast<S *>(reinterpret_cast<char *>(P.status) + p * L.status_pass);
-        hipLaunchKernelGGL((k_seg_onesweep<1024, 16, VALS, S>), dim3(L.max_tiles), dim3(1024), 0, stream, P.descs,
-                           large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status,
-                           P.header_words + offsetof(SegHeader, chunk_ctr) / 4 + p * kChunks,
-                           P.header_words + offsetof(SegHeader, error) / 4, nchunks);
+        uint32_t *ctr = P.header_words + offsetof(SegHeader, chunk_ctr) / 4 + p * kChunks;
+        uint32_t *err = P.header_words + offsetof(SegHeader, error) / 4;
+#define RT_SEG_TILE_LAUNCH(BLK, I)                                                                               \
+    if (L.classes.tile_block == BLK && L.classes.tile_ipt == I)                                                  \
+        hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S>), dim3(L.max_tiles), dim3(BLK), 0, stream, P.descs,  \
+                           large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status, ctr, err, nchunks);
+        RT_FOR_EACH_SEG_TILE_SHAPE(RT_SEG_TILE_LAUNCH)
+#undef RT_SEG_TILE_LAUNCH
         prof_mark(stream, RT_KIND_PASS + p);
     }
 }
@@ -155,7 +168,7 @@ void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
     // XCD chunks of the tile list pay off for long segments only: with a few
     // tiles per segment (many partial tiles, short lookback chains) one
     // chunk measured faster.  The segments' mean size bounds their tiles.
-    const uint32_t nchunks = seg_chunk_count(L.capacity, num_segments);
+    const uint32_t nchunks = seg_chunk_count(L.capacity, num_segments, L.tile);
     if (L.wide_status) {
         if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
         else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);

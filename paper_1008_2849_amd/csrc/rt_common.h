@@ -74,21 +74,39 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
                  bool direct, uint32_t *direct_out_k, uint32_t *direct_out_v, hipStream_t stream,
                  uint32_t pass_kind = RT_KIND_PASS);
 
-// Whole-in-LDS kernel shapes (threads, items per thread) compiled for the
-// segmented sort; a shape holds segments of up to threads x items.
+// Whole-in-LDS kernel shapes (threads, items per thread, digit bits)
+// compiled for the segmented sort; a shape holds segments of up to threads
+// x items.  8-bit digits sort a 32-bit key in four passes, 11-bit digits in
+// three (11, 11, 10); the 11-bit per-wave counters (8 KiB a wave) limit
+// those to 512 threads.
 #define RT_FOR_EACH_SEG_SMALL_SHAPE(X) \
-    X(64, 4)                           \
-    X(64, 8)                           \
-    X(128, 4)                          \
-    X(128, 8)                          \
-    X(256, 4)                          \
-    X(256, 8)                          \
-    X(512, 4)                          \
-    X(512, 8)                          \
-    X(256, 16)                         \
-    X(512, 16)                         \
-    X(1024, 8)                         \
-    X(1024, 16)
+    X(64, 4, 8)                        \
+    X(64, 8, 8)                        \
+    X(128, 4, 8)                       \
+    X(128, 8, 8)                       \
+    X(256, 4, 8)                       \
+    X(256, 8, 8)                       \
+    X(512, 4, 8)                       \
+    X(512, 8, 8)                       \
+    X(256, 16, 8)                      \
+    X(512, 16, 8)                      \
+    X(1024, 8, 8)                      \
+    X(1024, 16, 8)                     \
+    X(64, 4, 11)                       \
+    X(64, 8, 11)                       \
+    X(128, 4, 11)                      \
+    X(128, 8, 11)                      \
+    X(256, 4, 11)                      \
+    X(256, 8, 11)                      \
+    X(256, 16, 11)                     \
+    X(512, 4, 11)                      \
+    X(512, 8, 11)                      \
+    X(512, 16, 11)
+
+// Tile shapes (threads, items per thread) of the tiled segments' passes.
+#define RT_FOR_EACH_SEG_TILE_SHAPE(X) \
+    X(1024, 16)                       \
+    X(512, 16)
 
 // The whole-in-LDS size classes of the segmented sort: class c holds the
 // segments of more than cls[c - 1].max_n and at most cls[c].max_n items and
@@ -98,18 +116,25 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
 struct SegClass {
     uint32_t max_n;
     int block, ipt;
+    int bits;  // digit width of the class's passes: 8 or 11
 };
+// The classes, and the tile shape (tile_block x tile_ipt items) of the
+// tiled segments' passes (the server keeps 1024 x 16).
 struct SegClassTable {
     uint32_t count;
     SegClass cls[kSegMaxClasses];
+    int tile_block, tile_ipt;
     SegClassLimits limits() const;
     uint32_t lds_max() const { return count ? cls[count - 1].max_n : 0u; }
+    uint32_t tile() const { return static_cast<uint32_t>(tile_block * tile_ipt); }
 };
 SegClassTable seg_class_table();
-bool seg_small_shape_supported(int block, int ipt);
-// Launches the whole-in-LDS kernel of class `which` over its list.
+bool seg_small_shape_supported(int block, int ipt, int bits);
+bool seg_tile_shape_supported(int block, int ipt);
+// Launches the whole-in-LDS kernel of class `which` over its list; the
+// segments are sorted on their low `key_bits` bits.
 void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStream_t stream,
-                      const SegDesc *descs, const uint32_t *list, const SegHeader *h, int which, int passes,
+                      const SegDesc *descs, const uint32_t *list, const SegHeader *h, int which, int key_bits,
                       int to_temp);
 
 // Workspace of a segmented sort (byte offsets) and its device pointers.
@@ -118,6 +143,7 @@ struct SegLayout {
     size_t capacity;          // temporaries hold this many items
     uint32_t large_capacity;  // most segments the tiled path can hold
     uint32_t max_tiles;
+    uint32_t tile;            // items per tile of the tiled segments' passes
     bool wide_status;
     SegClassTable classes;    // size classes the layout was made for
     size_t header, descs, lists, first_tile, tile_seg, hist, base, status, status_pass, tk, tv;
@@ -131,8 +157,8 @@ struct SegLayout {
 // (many partial tiles, short lookback chains) measured faster on one chain.
 constexpr uint32_t kSegChunkMinTiles = 16;
 constexpr uint32_t kSegChunkMinSegments = 16 * kChunks;
-inline uint32_t seg_chunk_count(size_t items, size_t segments) {
-    return segments >= kSegChunkMinSegments && items / segments >= static_cast<size_t>(kSegChunkMinTiles) * kSegTile
+inline uint32_t seg_chunk_count(size_t items, size_t segments, uint32_t tile) {
+    return segments >= kSegChunkMinSegments && items / segments >= static_cast<size_t>(kSegChunkMinTiles) * tile
                ? kChunks
                : 1u;
 }

@@ -77,7 +77,7 @@ struct PlanArgs {
 constexpr int kSegBits = 8;
 constexpr int kSegPasses = 4;
 constexpr int kSegRadix = 1 << kSegBits;
-constexpr int kSegTile = 1024 * 16;  // items per tile of the pass kernels
+constexpr int kSegTile = 1024 * 16;  // items per tile of the server's passes (batched calls: tuned)
 constexpr int kSegMaxClasses = 4;    // whole-in-LDS size classes at most
 constexpr uint32_t kSegLdsMax = 1024 * 16;  // largest segment one block sorts in LDS
 constexpr int kSegLarge = kSegMaxClasses;   // list index of the tiled segments

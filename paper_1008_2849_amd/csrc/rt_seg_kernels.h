@@ -111,19 +111,19 @@ static __global__ __launch_bounds__(64) void k_seg_set_count(SegHeader *__restri
 static __global__ __launch_bounds__(1024) void k_seg_tiles(const SegDesc *__restrict__ descs,
                                                            const uint32_t *__restrict__ list,
                                                            uint32_t *__restrict__ first_tile, SegHeader *__restrict__ h,
-                                                           uint32_t large_capacity, uint32_t max_tiles) {
+                                                           uint32_t large_capacity, uint32_t max_tiles, uint32_t tile) {
     __shared__ uint32_t s_wsum[16];
     const uint32_t listed = h->count[kSegLarge];
     const uint32_t count = min(listed, large_capacity);
     const uint32_t per = (count + 1023u) / 1024u;
     const uint32_t lo = min(count, threadIdx.x * per), hi = min(count, lo + per);
-    uint32_t sum = 0;  // at most 256 entries of at most 2^18 tiles: no overflow
-    for (uint32_t i = lo; i < hi; ++i) sum += (descs[list[i]].n + kSegTile - 1) / kSegTile;
+    uint32_t sum = 0;  // at most 256 entries of at most 2^19 tiles: no overflow
+    for (uint32_t i = lo; i < hi; ++i) sum += (descs[list[i]].n + tile - 1) / tile;
     // saturate, so the block total stays exact up to max_tiles and cannot wrap
     uint32_t run = block_exclusive_sum<1024>(min(sum, max_tiles + 1u), s_wsum);
     for (uint32_t i = lo; i < hi; ++i) {
         first_tile[i] = run;
-        run += (descs[list[i]].n + kSegTile - 1) / kSegTile;
+        run += (descs[list[i]].n + tile - 1) / tile;
     }
     if (threadIdx.x == 1023) {
         const bool fits = run <= max_tiles;
@@ -184,12 +184,12 @@ static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__re
 // leave an odd pass count's result).  Ranking inside a pass is the onesweep
 // ranking: wave-local ballot match plus per-wave digit counters, then digit
 // offsets across the block.
-template <int BLOCK, int IPT, bool VALS>
+template <int BLOCK, int IPT, bool VALS, int BITS>
 __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__ descs,
                                                      const uint32_t *__restrict__ list,
-                                                     const SegHeader *__restrict__ h, int which, int passes,
+                                                     const SegHeader *__restrict__ h, int which, int key_bits,
                                                      int to_temp) {
-    constexpr int RADIX = kSegRadix;
+    constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
     constexpr int TILE = BLOCK * IPT;
     constexpr int WAVE_ITEMS = 64 * IPT;
@@ -219,16 +219,16 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             key[j] = i < n ? d.k[i] : ~0u;
             if constexpr (VALS) val[j] = i < n ? d.v[i] : 0u;
         }
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t shift = p * kSegBits;
+        for (uint32_t shift = 0; shift < static_cast<uint32_t>(key_bits); shift += BITS) {
+            const uint32_t width = min(static_cast<uint32_t>(BITS), static_cast<uint32_t>(key_bits) - shift);
             for (uint32_t i = lane; i < RADIX; i += 64) wh[i] = 0u;
             // (the previous pass finished reading wh before its last barrier)
             uint32_t rnk[IPT];
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
-                const uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, kSegBits);
+                const uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, width);
                 uint32_t lo, hi;
-                match_digit<kSegBits>(dg, lo, hi);
+                match_digit<BITS>(dg, lo, hi);
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
                 const uint32_t cnt = wh[dg];
                 rnk[j] = cnt + below;
@@ -268,12 +268,12 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
-                const uint32_t r = wh[__builtin_amdgcn_ubfe(key[j], shift, kSegBits)] + rnk[j];
+                const uint32_t r = wh[__builtin_amdgcn_ubfe(key[j], shift, width)] + rnk[j];
                 s_k[r] = key[j];
                 if constexpr (VALS) s_v[r] = val[j];
             }
             __syncthreads();
-            if (p + 1 < passes) {
+            if (shift + BITS < static_cast<uint32_t>(key_bits)) {
 #pragma unroll
                 for (int j = 0; j < IPT; ++j) {
                     key[j] = s_k[wslot0 + j * 64];
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
                                                          const uint32_t *__restrict__ first_tile,
                                                          const uint32_t *__restrict__ tile_seg,
                                                          const SegHeader *__restrict__ h,
-                                                         uint32_t *__restrict__ hist) {
+                                                         uint32_t *__restrict__ hist, uint32_t tile) {
     constexpr int BINS = kSegPasses * kSegRadix;
     constexpr int ROW = BINS + 1;
     constexpr int WAVES = BLOCK / 64;
@@ -349,8 +349,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
             cur = e;
         }
         const SegDesc d = descs[list[e]];
-        const uint32_t start = (t - first_tile[e]) * kSegTile;
-        const uint32_t valid = min(static_cast<uint32_t>(kSegTile), d.n - start);
+        const uint32_t start = (t - first_tile[e]) * tile;
+        const uint32_t valid = min(tile, d.n - start);
         const uint32_t *src = d.k + start;
         for (uint32_t base = wave * SPAN; base < valid; base += WAVES * SPAN) {
             uint32_t k[U];
@@ -409,9 +409,10 @@ static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restri
 // tiled segments: one counting-sort pass over every listed segment
 // ---------------------------------------------------------------------------
 
-// One block per tile, claimed as in k_onesweep from nchunks chunks of whole
-// segments (chunk_counter: the launch's kChunks counters, zeroed before it;
-// chunk bounds from k_seg_tilemap with the same nchunks), then the pass body
+// One block per tile (of BLOCK * IPT items: the tile the tile map was built
+// for), claimed as in k_onesweep from nchunks chunks of whole segments
+// (chunk_counter: the launch's kChunks counters, zeroed before it; chunk
+// bounds from k_seg_tilemap with the same nchunks), then the pass body
 // of onesweep_tile on it.  The tile's segment runs pass `pass` (or its own
 // d.pass when pass < 0): even passes read k/v and write tk/tv, odd passes the
 // reverse, so four passes leave the result in k/v and three in tk/tv.  The
@@ -427,7 +428,6 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
                                                         uint32_t *__restrict__ chunk_counter,
                                                         uint32_t *__restrict__ error_flag, uint32_t nchunks) {
     constexpr int TILE = BLOCK * IPT;
-    static_assert(TILE == kSegTile, "tiles of the pass and of the tile map differ");
     constexpr bool SMALL = sizeof(S) == 4;  // every segment below 2^30 items
     __shared__ OnesweepLds<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS> lds;
 

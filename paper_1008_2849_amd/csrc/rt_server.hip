@@ -447,11 +447,11 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         hipLaunchKernelGGL(k_srv_clear_rows, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist,
                            d_hh, d_hist);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_hlist, d_first_h, d_hh, stride,
-                           m.max_tiles);
+                           m.max_tiles, static_cast<uint32_t>(kSegTile));
         hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
                            d_hh, d_seg_h, 1u);
         hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_descs,
-                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist);
+                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist, static_cast<uint32_t>(kSegTile));
         hipLaunchKernelGGL(k_seg_plan, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
                            d_hist, d_base);
     }
@@ -459,9 +459,9 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         hipLaunchKernelGGL(k_fill_zero, dim3(grid((P.tiles * kSegRadix + 4095) / 4096, 4096)), dim3(256), 0, st,
                            d_status, P.tiles * kSegRadix);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_hp, stride,
-                           m.max_tiles);
+                           m.max_tiles, static_cast<uint32_t>(kSegTile));
         // XCD chunks when the step's tiled requests are long (see seg_chunk_count)
-        const uint32_t nchunks = seg_chunk_count(P.tiles * kSegTile, P.tiled);
+        const uint32_t nchunks = seg_chunk_count(P.tiles * kSegTile, P.tiled, kSegTile);
         hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p,
                            d_hp, d_seg_p, nchunks);
         uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, chunk_ctr) / 4;
@@ -480,7 +480,7 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
     for (uint32_t c = 0; c < s->classes.count; ++c)  // small requests, whole in LDS
         if (P.small[c])
             launch_seg_small(s->classes.cls[c], P.vals, P.small[c], st, d_descs,
-                             d_lists + static_cast<size_t>(c) * stride, d_hp, static_cast<int>(c), kSegPasses, 0);
+                             d_lists + static_cast<size_t>(c) * stride, d_hp, static_cast<int>(c), 32, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "server: launch: %s", hipGetErrorString(e));
     // the error words of both headers come back with the step

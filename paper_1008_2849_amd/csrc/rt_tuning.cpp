@@ -3,15 +3,18 @@
 //
 // Table format:
 //   {"arch": "gfx950", "entries": [
-//      {"op": "keys"|"pairs"|"segments", "min_n": N0, "max_n": N1,
+//      {"op": "keys"|"pairs"|"segments"|"segments_tiled", "min_n": N0, "max_n": N1,
 //       "digit_bits": [w0, w1, ...], "block": B, "ipt": I, "flags": F}, ...]}
 // A "keys" or "pairs" entry applies to single-array sorts of n in
 // [min_n, max_n]; the first matching entry wins.  The "segments" entries, in
 // increasing max_n, are the whole-in-LDS size classes of the segmented sort
 // (batched calls, the MSD-first sort's buckets, small server requests): each
 // sorts the segments of up to max_n items (and more than the previous
-// entry's) in one block of B threads x I items, with 8-bit digits; larger
-// segments are tiled.  Without "segments" entries the built-in classes hold.
+// entry's) in one block of B threads x I items, with the entry's digits
+// (8,8,8,8 or 11,11,10); larger segments are tiled.  A "segments_tiled"
+// entry sets the tile (B x I items, 1024x16 or 512x16) of the tiled
+// segments' passes in batched calls and MSD-first sorts.  Without
+// "segments" entries the built-in classes hold.
 #include <cctype>
 #include <cstdio>
 #include <cstdlib>
@@ -126,7 +129,7 @@ struct JParser {
 };
 
 struct Entry {
-    int op;  // 0 keys, 1 pairs, 2 segments
+    int op;  // 0 keys, 1 pairs, 2 segments, 3 segments_tiled
     double min_n, max_n;
     rt_config cfg;
 };
@@ -139,9 +142,11 @@ SegClassTable g_seg;
 SegClassTable builtin_seg_classes() {
     SegClassTable t{};
     t.count = 3;
-    t.cls[0] = SegClass{256 * 8, 256, 8};
-    t.cls[1] = SegClass{512 * 16, 512, 16};
-    t.cls[2] = SegClass{1024 * 16, 1024, 16};
+    t.cls[0] = SegClass{256 * 8, 256, 8, 8};
+    t.cls[1] = SegClass{512 * 16, 512, 16, 8};
+    t.cls[2] = SegClass{1024 * 16, 1024, 16, 8};
+    t.tile_block = 1024;
+    t.tile_ipt = 16;
     return t;
 }
 
@@ -219,6 +224,7 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
         if (op->str == "keys") en.op = 0;
         else if (op->str == "pairs") en.op = 1;
         else if (op->str == "segments") en.op = 2;
+        else if (op->str == "segments_tiled") en.op = 3;
         else return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: unknown op %s", i, op->str.c_str());
         en.min_n = lo->num;
         en.max_n = hi->num;
@@ -230,21 +236,37 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
         en.cfg.items_per_thread = static_cast<uint32_t>(ipt->num);
         en.cfg.flags = flags ? static_cast<uint32_t>(flags->num) : 0u;
         Resolved r;
-        if (en.op != 2) {
+        if (en.op < 2) {  // a single-array sort
             if (resolve_config(&en.cfg, 1024, en.op, &r) != RT_OK)
                 return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: %s", i, last_error());
             table.push_back(en);
             continue;
         }
-        // a whole-in-LDS class of the segmented sort
         const int blk = static_cast<int>(en.cfg.block_threads), ip = static_cast<int>(en.cfg.items_per_thread);
+        // digits of the segmented sort: four of 8 bits, or (whole-in-LDS
+        // classes) 11, 11 and 10 bits
         bool eight = en.cfg.num_passes == static_cast<uint32_t>(kSegPasses);
         for (uint32_t p = 0; p < en.cfg.num_passes; ++p) eight = eight && en.cfg.digit_bits[p] == kSegBits;
-        if (!eight)
-            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: segments use four 8-bit digits", i);
-        if (!seg_small_shape_supported(blk, ip))
-            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: no whole-in-LDS kernel %dx%d", i, blk,
-                             ip);
+        const bool eleven = en.cfg.num_passes == 3 && en.cfg.digit_bits[0] == 11 && en.cfg.digit_bits[1] == 11 &&
+                            en.cfg.digit_bits[2] == 10;
+        if (en.op == 3) {  // the tile of the tiled segments' passes
+            if (!eight || !seg_tile_shape_supported(blk, ip))
+                return set_error(RT_ERR_INVALID_ARG,
+                                 "rt_load_tuning: entry %zu: tiled segments take four 8-bit digits and a built "
+                                 "tile shape (1024x16 or 512x16), not %dx%d",
+                                 i, blk, ip);
+            seg.tile_block = blk;
+            seg.tile_ipt = ip;
+            continue;
+        }
+        // a whole-in-LDS class of the segmented sort
+        if (!eight && !eleven)
+            return set_error(RT_ERR_INVALID_ARG,
+                             "rt_load_tuning: entry %zu: segments use digits 8,8,8,8 or 11,11,10", i);
+        const int cbits = eight ? 8 : 11;
+        if (!seg_small_shape_supported(blk, ip, cbits))
+            return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: entry %zu: no whole-in-LDS kernel %dx%d with "
+                             "%d-bit digits", i, blk, ip, cbits);
         if (seg.count == static_cast<uint32_t>(kSegMaxClasses))
             return set_error(RT_ERR_INVALID_ARG, "rt_load_tuning: more than %d segment classes", kSegMaxClasses);
         const double prev = seg.count ? seg.cls[seg.count - 1].max_n : 0.0;
@@ -253,12 +275,31 @@ extern "C" rt_status rt_load_tuning(const char *json_path) {
                              "rt_load_tuning: entry %zu: segment class limit %.0f must rise, fit %dx%d and be at "
                              "most %u",
                              i, en.max_n, blk, ip, kSegLdsMax);
-        seg.cls[seg.count++] = SegClass{static_cast<uint32_t>(en.max_n), blk, ip};
+        seg.cls[seg.count++] = SegClass{static_cast<uint32_t>(en.max_n), blk, ip, cbits};
+    }
+    if (seg.count > 0 && seg.tile_block == 0) {  // classes without a tile entry: the built-in tile
+        seg.tile_block = 1024;
+        seg.tile_ipt = 16;
+    }
+    if (seg.count == 0 && seg.tile_block != 0) {  // a tile entry alone keeps the built-in classes
+        SegClassTable b = builtin_seg_classes();
+        b.tile_block = seg.tile_block;
+        b.tile_ipt = seg.tile_ipt;
+        seg = b;
     }
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.swap(table);
     g_seg_tuned = seg.count > 0;
     g_seg = seg;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_segment_config(uint32_t *bits, uint32_t *tile_block, uint32_t *tile_ipt) {
+    const SegClassTable t = seg_class_table();
+    for (uint32_t c = 0; c < t.count; ++c)
+        if (bits) bits[c] = static_cast<uint32_t>(t.cls[c].bits);
+    if (tile_block) *tile_block = static_cast<uint32_t>(t.tile_block);
+    if (tile_ipt) *tile_ipt = static_cast<uint32_t>(t.tile_ipt);
     return RT_OK;
 }
 

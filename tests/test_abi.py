@@ -224,17 +224,33 @@ def test_segment_classes_from_tuning_table(so, tmp_path):
                 [seg(2048, 256, 8), seg(2048, 512, 8)],           # not increasing
                 [seg(16385, 1024, 16)],                           # beyond the LDS limit
                 [seg(2048, 128, 16)],                             # no such kernel
-                [seg(2048, 256, 8, (11, 11, 10))],                # digits other than 8 x 4
+                [seg(2048, 256, 8, (16, 16))],                    # digits other than 8 x 4 or 11/11/10
+                [seg(16384, 1024, 16, (11, 11, 10))],             # 11-bit counters do not fit 1024 threads
+                [{"op": "segments_tiled", "min_n": 0, "max_n": 0, "digit_bits": [8, 8, 8, 8],
+                  "block": 256, "ipt": 16}],                      # no such tile shape
                 [seg(512 * (i + 1), 512, 8) for i in range(5)]):  # more than four classes
         p.write_text(json.dumps({"entries": bad}))
         assert so.rt_load_tuning(str(p).encode()) == _lib.RT_ERR_INVALID_ARG, bad
         assert api.segment_classes() == [(1024, 256, 4), (4096, 512, 8), (8192, 1024, 8), (16384, 1024, 16)]
+    # 11-bit classes and the tile of the tiled segments
+    mixed = [seg(1024, 256, 4, (11, 11, 10)), seg(4096, 256, 16), seg(8192, 512, 16, (11, 11, 10)),
+             {"op": "segments_tiled", "min_n": 0, "max_n": 0, "digit_bits": [8, 8, 8, 8], "block": 512, "ipt": 16}]
+    p.write_text(json.dumps({"entries": mixed}))
+    assert so.rt_load_tuning(str(p).encode()) == _lib.RT_OK
+    assert api.segment_classes() == [(1024, 256, 4), (4096, 256, 16), (8192, 512, 16)]
+    assert api.segment_config() == ([11, 8, 11], (512, 16))
+    # 8K-item tiles: twice the tiles, so more lookback words
+    assert so.rt_batched_workspace_bytes(4096, n, 1) > so.rt_batched_workspace_bytes(4096, 0, 1)
+    # a tile entry alone keeps the built-in classes
+    p.write_text(json.dumps({"entries": [mixed[-1]]}))
+    assert so.rt_load_tuning(str(p).encode()) == _lib.RT_OK
+    assert api.segment_classes() == builtin and api.segment_config() == ([8, 8, 8], (512, 16))
     # a lower LDS limit leaves more segments tiled: the workspace grows
     p.write_text(json.dumps({"entries": [seg(2048, 256, 8)]}))
     assert so.rt_load_tuning(str(p).encode()) == _lib.RT_OK
     assert so.rt_batched_workspace_bytes(4096, n, 1) > tuned_ws
     assert so.rt_load_tuning(None) == _lib.RT_OK
-    assert api.segment_classes() == builtin
+    assert api.segment_classes() == builtin and api.segment_config() == ([8, 8, 8], (1024, 16))
     api.load_default_tuning()
 
 
@@ -365,7 +381,7 @@ def test_committed_tuning_table_loads(so):
     assert so.rt_load_tuning(path.encode()) == _lib.RT_OK
     c = _lib.RtConfig()
     for e in table["entries"]:
-        if e["op"] == "segments":
+        if e["op"] in ("segments", "segments_tiled"):
             continue
         n = max(2, e["min_n"])
         assert so.rt_tuned_config(n, 1 if e["op"] == "pairs" else 0, ctypes.byref(c)) == _lib.RT_OK
@@ -374,4 +390,7 @@ def test_committed_tuning_table_loads(so):
     from paper_1008_2849_amd import api
     seg = [(e["max_n"], e["block"], e["ipt"]) for e in table["entries"] if e["op"] == "segments"]
     assert seg and api.segment_classes() == seg
+    bits = [8 if e["digit_bits"][0] == 8 else 11 for e in table["entries"] if e["op"] == "segments"]
+    tile = [(e["block"], e["ipt"]) for e in table["entries"] if e["op"] == "segments_tiled"]
+    assert api.segment_config() == (bits, tile[0] if tile else (1024, 16))
     assert so.rt_load_tuning(None) == _lib.RT_OK

@@ -1,6 +1,7 @@
 """The segmented sort under tuned size classes: tables other than the
 built-in one (four classes of different kernel shapes; a single small class
-that leaves mid-size segments to the tiled path) give the oracle's result,
+that leaves mid-size segments to the tiled path; classes with 11-bit
+digits; the 8K-item tile for the tiled passes) give the oracle's result,
 bit-exact, in batched calls, the MSD-first sort and the server."""
 import json
 
@@ -17,12 +18,17 @@ from test_gpu_batched import check, offsets_of, run_batched
 
 pytestmark = pytest.mark.gpu
 
+# (max_n, block, ipt) per class, digit bits per class, tile of the tiled passes
 TABLES = {
-    "four": [(1024, 256, 4), (4096, 512, 8), (8192, 1024, 8), (16384, 1024, 16)],
-    "one_small": [(2048, 256, 8)],
-    "wide_first": [(4096, 256, 16), (16384, 1024, 16)],
-    "one_wave": [(256, 64, 4), (512, 64, 8), (1024, 128, 8), (16384, 1024, 16)],
+    "four": ([(1024, 256, 4), (4096, 512, 8), (8192, 1024, 8), (16384, 1024, 16)], [8] * 4, (1024, 16)),
+    "one_small": ([(2048, 256, 8)], [8], (1024, 16)),
+    "wide_first": ([(4096, 256, 16), (16384, 1024, 16)], [8, 8], (1024, 16)),
+    "one_wave": ([(256, 64, 4), (512, 64, 8), (1024, 128, 8), (16384, 1024, 16)], [8] * 4, (1024, 16)),
+    "eleven_bits": ([(256, 64, 4), (1024, 256, 4), (4096, 256, 16), (8192, 512, 16)], [11, 11, 11, 11],
+                    (1024, 16)),
+    "mixed_tile8k": ([(512, 64, 8), (2048, 256, 8), (8192, 512, 16)], [11, 8, 11], (512, 16)),
 }
+BITS = {8: [8, 8, 8, 8], 11: [11, 11, 10]}
 
 
 @pytest.fixture(params=sorted(TABLES) + ["builtin", "committed"])
@@ -32,12 +38,15 @@ def classes(request, tmp_path):
     elif request.param == "committed":  # the autotuner's table for gfx950
         rts.load_tuning(_lib.TUNING_PATH)
     else:
+        cls, bits, tile = TABLES[request.param]
         path = tmp_path / "classes.json"
         path.write_text(json.dumps({"entries": [
-            {"op": "segments", "min_n": 0, "max_n": m, "digit_bits": [8, 8, 8, 8], "block": b, "ipt": i}
-            for m, b, i in TABLES[request.param]]}))
+            {"op": "segments", "min_n": 0, "max_n": m, "digit_bits": BITS[w], "block": b, "ipt": i}
+            for (m, b, i), w in zip(cls, bits)] + [
+            {"op": "segments_tiled", "min_n": 0, "max_n": 0, "digit_bits": BITS[8], "block": tile[0],
+             "ipt": tile[1]}]}))
         rts.load_tuning(str(path))
-        assert rts.segment_classes() == TABLES[request.param]
+        assert rts.segment_classes() == cls and rts.segment_config() == (bits, tile)
     yield request.param, rts.segment_classes()
     rts.load_default_tuning()
 
@@ -63,10 +72,11 @@ def test_batched(classes):
     check(run_batched(k, None, off), oracle.lsd_sort_segmented(k, None, off), name + " keys")
 
 
-def test_msd_first(classes):
+@pytest.mark.parametrize("n", [(1 << 19) + 77, (1 << 23) + 5])
+def test_msd_first(classes, n):
+    """2^19 items: MSD buckets of about 2048 items, on both sides of the
+    limits; 2^23: buckets of about 32K items, sorted by the tiled passes."""
     name, table = classes
-    # 2^19 items: MSD buckets of about 2048 items, on both sides of the limits
-    n = (1 << 19) + 77
     announce(f"MSD-first under classes {name} n={n}")
     k = inputs.uniform_keys(n, 95)
     v = inputs.index_values(n)
