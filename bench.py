@@ -47,18 +47,25 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(digest: str):
-    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
-    or None when that summary predates the current kernel source."""
+def counters_from_profiles(digest: str):
+    """From the committed rocprofv3 counter summary of the pass: HBM bytes
+    per launch (traffic), VALU instructions per item, the share of 32-byte
+    write requests and of LDS bank-conflict cycles; all None when that
+    summary predates the current kernel source."""
+    out = {"traffic": None, "valu_per_item": None, "write_32B_share": None, "lds_bank_conflict_share": None}
     path = os.path.join(PROFILES, "onesweep_pass_pairs_256m_counters.md")
     if not os.path.exists(path):
-        return None
+        return out
     text = open(path).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != digest:
-        return None
-    return float(t.group(1))
+    if not m or m.group(1) != digest:
+        return out
+    for key, name in (("traffic", "traffic_bytes_per_launch"), ("valu_per_item", "valu_per_item"),
+                      ("write_32B_share", "write_32B_share"), ("lds_bank_conflict_share", "lds_bank_conflict_share")):
+        t = re.search(name + r":\s*([0-9.eE+-]+)", text)
+        if t:
+            out[key] = float(t.group(1))
+    return out
 
 
 def cpu_model() -> str:
@@ -602,6 +609,8 @@ def main() -> int:
                     help="further single-array workloads timed and checked against the oracle (empty to skip)")
     ap.add_argument("--no-xcd-compare", action="store_true",
                     help="skip re-timing the headline sort on one lookback chain per pass")
+    ap.add_argument("--no-fused-compare", action="store_true",
+                    help="skip timing the fused next-digit histogram against the upfront read")
     ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
                     "of single-array throughput), replayed open loop; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -709,18 +718,28 @@ def main() -> int:
         del src64
     del k64
 
-    # achievable copy bandwidth: 2 GiB read + 2 GiB written
+    # the achievable bandwidth on this device: copies of 2 GiB (2 GiB read +
+    # 2 GiB written, the pass's mix), and 2 GiB read only and written only
+    from paper_1008_2849_amd._lib import RT_PROBE_COPY, RT_PROBE_COPY_NT, RT_PROBE_READ, RT_PROBE_WRITE
     big_src = torch.empty(1 << 29, dtype=torch.int32, device=dev).fill_(7)
     big_dst = torch.empty_like(big_src)
-    rts.copy(big_src, big_dst)
-    torch.cuda.synchronize()
-    rts.profile_start(64)
-    for _ in range(5):
-        rts.copy(big_src, big_dst)
-    torch.cuda.synchronize()
-    cm = [ms for kind, ms in rts.profile_stop(64) if kind == RT_KIND_COPY]
-    copy_gbps = 2 * big_src.numel() * 4 / float(np.median(cm)) / 1e6 if cm else None
-    del big_src, big_dst
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    probes = {}
+    for name, kind, moved in (("copy", RT_PROBE_COPY, 2), ("copy_nt_x4", RT_PROBE_COPY_NT, 2),
+                              ("read_only", RT_PROBE_READ, 1), ("write_only", RT_PROBE_WRITE, 1)):
+        src_t = None if kind == RT_PROBE_WRITE else big_src
+        dst_t = None if kind == RT_PROBE_READ else big_dst
+        rts.bandwidth_probe(kind, src=src_t, dst=dst_t, sink=sink)
+        torch.cuda.synchronize()
+        rts.profile_start(64)
+        for _ in range(7):
+            rts.bandwidth_probe(kind, src=src_t, dst=dst_t, sink=sink)
+        torch.cuda.synchronize()
+        cm = [ms for kind_, ms in rts.profile_stop(64) if kind_ == RT_KIND_COPY]
+        probes[name] = round(moved * big_src.numel() * 4 / float(np.median(cm)) / 1e6, 1) if cm else None
+    copy_gbps = max(v for k_, v in probes.items() if k_.startswith("copy") and v)
+    log(f"bandwidth probes (GB/s): {probes}")
+    del big_src, big_dst, sink
 
     # the same sort on one lookback chain per pass (RT_FLAG_ONE_CHAIN), for
     # what the XCD chunks buy: the same W warm-up and K timed sorts of fresh
@@ -770,8 +789,52 @@ def main() -> int:
         log(f"one chain per pass: {oc_ms:.3f} ms/sort; XCD chunks {oc_ms / ms_per_step:.3f}x faster")
         del oc_ws
 
+    # the fused next-digit histogram (RT_FLAG_FUSED_HISTOGRAM) against the
+    # upfront read of every digit, both on one chain (the fused form's
+    # condition), same input, same W and K, same per-kernel marks
+    from paper_1008_2849_amd._lib import RT_FLAG_FUSED_HISTOGRAM, RT_KIND_PLAN
+    fused = None
+    if not args.no_fused_compare:
+        ref = (ko.clone(), None if vo is None else vo.clone())
+        legs = {}
+        for label, extra in (("upfront", RT_FLAG_ONE_CHAIN), ("fused", RT_FLAG_ONE_CHAIN | RT_FLAG_FUSED_HISTOGRAM)):
+            fcfg = rts.Config(cfg.digit_bits, cfg.block_threads, cfg.items_per_thread, cfg.flags | extra)
+            for k, v in slots:
+                k.copy_(k0)
+                if v is not None:
+                    v.copy_(v0)
+            fws = torch.empty(rts.workspace_bytes(n, vals_on, fcfg), dtype=torch.uint8, device=dev)
+            for i in range(W):
+                rts.sort_ex(slots[i][0], slots[i][1], fcfg, fws)
+            torch.cuda.synchronize()
+            rts.profile_start(max_marks=32 * K + 32)
+            t0 = time.perf_counter()
+            for i in range(W, W + K):
+                rts.sort_ex(slots[i][0], slots[i][1], fcfg, fws)
+            torch.cuda.synchronize()
+            f_ms = 1e3 * (time.perf_counter() - t0) / K
+            fm = rts.profile_stop(capacity=32 * K + 32)
+            last = slots[W + K - 1]
+            same = bool(torch.equal(last[0], ref[0])) and (ref[1] is None or bool(torch.equal(last[1], ref[1])))
+            per = lambda lo, hi: [ms for kind, ms in fm if lo <= kind < hi]
+            legs[label] = {"ms_per_sort": round(f_ms, 4),
+                           "pass_ms": round(float(np.mean(per(RT_KIND_PASS, RT_KIND_PASS + 8))), 4),
+                           "histogram_ms": round(float(np.mean(per(RT_KIND_HISTOGRAM, RT_KIND_HISTOGRAM + 1))), 4),
+                           "plan_ms_per_sort": round(float(np.sum(per(RT_KIND_PLAN, RT_KIND_PLAN + 1))) / K, 4),
+                           "output_equal": same}
+            del fws
+        slots[W + K - 1][0].copy_(ref[0])
+        if ref[1] is not None:
+            slots[W + K - 1][1].copy_(ref[1])
+        del ref
+        fused = dict(legs, speedup=round(legs["upfront"]["ms_per_sort"] / legs["fused"]["ms_per_sort"], 4),
+                     note="both on one lookback chain; fused: the upfront read counts digit 0 only and passes "
+                          "0-2 count the next digit while they write")
+        log(f"fused histogram: {fused}")
+
     digest = kernel_source_digest()
-    traffic = traffic_from_profiles(digest)
+    counters = counters_from_profiles(digest)
+    traffic = counters["traffic"]
 
     out_k = to_np = None
     cpu = None
@@ -858,6 +921,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
+                     "valu_per_item": counters["valu_per_item"],
+                     "write_32B_share": counters["write_32B_share"],
+                     "lds_bank_conflict_share": counters["lds_bank_conflict_share"],
                      "kernel": "k_onesweep (one counting-sort pass: rank, lookback, scatter)",
                      "algorithmic_bytes_per_launch": pass_bytes,
                      "avg_launch_ms": round(dom_ms, 4)},
@@ -866,8 +932,10 @@ def main() -> int:
         "histogram": hist,
         "copy_peak_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "pass_frac_of_copy_peak": None if copy_gbps is None else round(achieved / copy_gbps, 4),
+        "bandwidth_probes_GBps": probes,
         "parity_properties_ok": props,
         "xcd_chunks": xcd,
+        "fused_histogram": fused,
         "transfer_inclusive": pcie,
         "msd_first": msd_first,
         "sort64": sort64,
@@ -883,6 +951,7 @@ def main() -> int:
     ok = ok and all(w_["matches_oracle_bit_exact"] for w_ in workloads)
     ok = ok and all(not s.get("failures") for s in serving)
     ok = ok and (pcie is None or pcie["matches_device_sort"])
+    ok = ok and (fused is None or all(fused[x]["output_equal"] for x in ("upfront", "fused")))
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
     ok = ok and (sort64 is None or sort64["parity_properties_ok"])
     ok = ok and (table1 is None or all(r["outputs_equal"] for k, r in table1.items() if "outputs_equal" in r))

@@ -85,6 +85,17 @@ typedef enum rt_status {
  * the flags are for measuring and testing.  They exclude each other. */
 #define RT_FLAG_ONE_CHAIN 0x10u
 #define RT_FLAG_CHUNKS 0x20u
+/* Fused next-digit histogram (Section 4, Algorithm 2's histogram2, counted
+ * while the data passes anyway): the upfront read counts only the first
+ * pass's digit, and each pass counts the next pass's digit of the items it
+ * writes; a small planning launch between passes turns those counts into
+ * the next pass's digit starts.  For measuring that trade against the
+ * upfront read of every digit.  Same result.  Implies RT_FLAG_ONE_CHAIN and
+ * RT_FLAG_NO_SKIP (the later histograms do not exist when the buffers are
+ * planned); digits of at most 8 bits; not combinable with RT_FLAG_CHUNKS,
+ * RT_FLAG_DIRECT_SCATTER or RT_FLAG_NT_STORES (RT_ERR_UNSUPPORTED).
+ * Single-array 32-bit sorts only. */
+#define RT_FLAG_FUSED_HISTOGRAM 0x40u
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".
@@ -301,6 +312,24 @@ rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *k
  * against.
  */
 rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
+
+/*
+ * Bandwidth probes: the ceilings a pass's HBM rate is set against, for
+ * measurement.  kind RT_PROBE_COPY: the copy of rt_copy (one 16-byte word
+ * per thread); RT_PROBE_COPY_NT: copy with four 16-byte words in flight per
+ * thread and non-temporal loads and stores, 16 blocks per CU in a
+ * grid-stride loop; RT_PROBE_READ: reads src only (an XOR of every word,
+ * written to the device word *sink only if it hits a fixed value, so the
+ * loads stay); RT_PROBE_WRITE: writes dst only (a fixed pattern).  src and
+ * dst: device memory of `bytes` bytes, 16-byte aligned, bytes a multiple of
+ * 16 (src unused by RT_PROBE_WRITE, dst by RT_PROBE_READ).
+ */
+#define RT_PROBE_COPY 0u
+#define RT_PROBE_COPY_NT 1u
+#define RT_PROBE_READ 2u
+#define RT_PROBE_WRITE 3u
+rt_status rt_bandwidth_probe(const void *src, void *dst, size_t bytes, uint32_t kind, uint32_t *sink,
+                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Device input generator (counter-based SplitMix64)

@@ -29,7 +29,12 @@ RT_FLAG_NT_STORES = 0x2
 RT_FLAG_DIRECT_SCATTER = 0x8
 RT_FLAG_ONE_CHAIN = 0x10
 RT_FLAG_CHUNKS = 0x20
+RT_FLAG_FUSED_HISTOGRAM = 0x40
 RT_FLAG_VALIDATE = 0x4
+RT_PROBE_COPY = 0
+RT_PROBE_COPY_NT = 1
+RT_PROBE_READ = 2
+RT_PROBE_WRITE = 3
 
 RT_KIND_FILL = 1
 RT_KIND_HISTOGRAM = 2
@@ -94,6 +99,7 @@ SIGNATURES = {
     "rt_workspace_bytes": (sz, [sz, ctypes.c_int, ctypes.POINTER(RtConfig)]),
     "rt_sort_pairs_ex": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp, sz, vp]),
     "rt_sort_pairs_noalloc": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtConfig), vp]),
+    "rt_bandwidth_probe": (ctypes.c_int, [vp, vp, sz, u32, vp, vp]),
     "rt_sort_pairs_batched": (ctypes.c_int, [vp, vp, vp, u32, sz, vp]),
     "rt_batched_workspace_bytes": (sz, [u32, sz, ctypes.c_int]),
     "rt_sort_batched_ex": (ctypes.c_int, [vp, vp, vp, u32, sz, u32, vp, sz, vp]),

@@ -20,6 +20,7 @@ FLAG_DIRECT_SCATTER = _lib.RT_FLAG_DIRECT_SCATTER
 FLAG_ONE_CHAIN = _lib.RT_FLAG_ONE_CHAIN
 FLAG_CHUNKS = _lib.RT_FLAG_CHUNKS
 FLAG_VALIDATE = _lib.RT_FLAG_VALIDATE
+FLAG_FUSED_HISTOGRAM = _lib.RT_FLAG_FUSED_HISTOGRAM
 MAX_DIGIT_BITS = _lib.RT_MAX_DIGIT_BITS
 MAX_PASSES = _lib.RT_MAX_PASSES
 
@@ -279,6 +280,16 @@ def copy(src, dst, stream=None) -> None:
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst is smaller than src")
     check(lib().rt_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream(stream)), "rt_copy")
+
+
+def bandwidth_probe(kind: int, src=None, dst=None, sink=None, stream=None) -> None:
+    """One bandwidth probe (_lib.RT_PROBE_*) over the bytes of src (copy,
+    read) or dst (write); sink: a device word the read probe may write."""
+    t = src if src is not None else dst
+    nbytes = t.numel() * t.element_size()
+    check(lib().rt_bandwidth_probe(None if src is None else src.data_ptr(), None if dst is None else dst.data_ptr(),
+                                   nbytes, int(kind), None if sink is None else sink.data_ptr(), _stream(stream)),
+          "rt_bandwidth_probe")
 
 
 def gen_params_to_c(p) -> RtGenParams:

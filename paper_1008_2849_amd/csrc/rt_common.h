@@ -32,6 +32,7 @@ struct Resolved {
     bool with_values;
     bool chunked;  // passes may run in XCD chunks (every digit of at most 8 bits)
     bool probe;    // chunked: the probe kernel decides per sort (else chunks always)
+    bool fused;    // RT_FLAG_FUSED_HISTOGRAM: passes count the next pass's digit
 };
 
 // Byte offsets of the workspace regions.

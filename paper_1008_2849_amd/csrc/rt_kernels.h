@@ -584,6 +584,34 @@ static __global__ __launch_bounds__(256) void k_plan(PlanArgs a, const uint32_t 
     plan->copy_back = (!direct && executed == 1) ? 1u : 0u;
 }
 
+// Fused next-digit histogram (RT_FLAG_FUSED_HISTOGRAM): a pass counts the
+// next pass's digit (at most 8 bits) of the items it writes into
+// kFusedCopies copies of that pass's histogram row, spread by block so that
+// fewer blocks add into one word; copy c holds bins [c * 256, c * 256 + 256)
+// of the row (the row has kMaxRadix words).
+constexpr int kFusedBins = 256;
+constexpr int kFusedCopies = kMaxRadix / kFusedBins;
+
+// Pass `pass`'s digit starts from its fused histogram (RT_FLAG_FUSED_HISTOGRAM):
+// the sum of the kFusedCopies copies of its row, then the exclusive prefix
+// sum, written to its base row (digits past its range start at n).  One
+// block of 256 threads, launched after pass - 1 (which counted the row).
+// The sort runs on one chain, so the row is the pass's whole plan.
+static __global__ __launch_bounds__(256) void k_plan_fused(const uint32_t *__restrict__ hist,
+                                                    uint32_t *__restrict__ base, uint32_t pass, uint32_t width,
+                                                    uint32_t n) {
+    __shared__ uint32_t s_wsum[4];
+    const uint32_t d = threadIdx.x;
+    const uint32_t *row = hist + static_cast<size_t>(pass) * kMaxRadix;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kFusedCopies; ++k) c += row[k * kFusedBins + d];
+    const uint32_t run = block_exclusive_sum<256>(c, s_wsum);
+    uint32_t *out = base + static_cast<size_t>(pass) * kMaxRadix;
+    out[d] = d < (1u << width) ? run : n;
+    for (uint32_t i = d + 256; i < static_cast<uint32_t>(kMaxRadix); i += 256) out[i] = n;
+}
+
 // ---------------------------------------------------------------------------
 // onesweep counting-sort pass
 // ---------------------------------------------------------------------------
@@ -780,13 +808,17 @@ struct TileJob {
     uint32_t tile, first;
     uint32_t valid;
     uint32_t bound;
+    // FUSED: where the next pass's digit counts go (its histogram row) and
+    // that digit's bits
+    uint32_t *next_hist;
+    uint32_t next_shift, next_width;
 };
 
 // LDS of one onesweep block: the tile staged by digit, per-wave digit
 // counters (then offsets) with a 64-word scratch row per wave that absorbs
 // the counter writes of non-leader lanes, each digit's output slot, the
 // block scan's wave sums, and the claimed tile (broadcast by thread 0).
-template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS>
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool FUSED = false>
 struct OnesweepLds {
     static constexpr int RADIX = 1 << BITS;
     static constexpr int WAVES = BLOCK / 64;
@@ -797,6 +829,7 @@ struct OnesweepLds {
     uint32_t gbase[RADIX];
     uint32_t wsum[WAVES];
     uint32_t claim[6];
+    uint32_t fused[FUSED ? kFusedBins : 1];  // the tile's counts of the next pass's digit
 };
 
 // Stable rank of a wave's items, slot by slot and lane by lane (input
@@ -853,9 +886,9 @@ __device__ __forceinline__ void rank_items(const K (&key)[IPT], V (&val)[VALS ? 
 // runs.  This is the pass without write-combining (the paper's "VM only"
 // counterpart), kept to measure what the staging buys.
 template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE,
-          bool SMALL>
+          bool SMALL, bool FUSED = false>
 __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
-                                              OnesweepLds<BITS, BLOCK, IPT, K, V, VALS> &lds,
+                                              OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED> &lds,
                                               S *__restrict__ status, uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
@@ -990,6 +1023,10 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
             store_t<NT, K>(gptr<K, SMALL>(job.dst_k, sp[j]), sk[j]);
             if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, sp[j]), lds.stage_v[j * BLOCK + tid]);
         }
+        if constexpr (FUSED) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) atomicAdd(&lds.fused[key_digit(sk[j], job.next_shift, job.next_width)], 1u);
+        }
     } else if constexpr (STAGE) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
@@ -999,6 +1036,7 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
             if (i < valid) {
                 store_t<NT, K>(gptr<K, SMALL>(job.dst_k, p), k);
                 if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, p), lds.stage_v[i]);
+                if constexpr (FUSED) atomicAdd(&lds.fused[key_digit(k, job.next_shift, job.next_width)], 1u);
             }
         }
     } else {  // each item from its registers: output slot = digit start + tile rank
@@ -1009,6 +1047,14 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
             const uint32_t p = min(lds.gbase[d] + wh[d] + rnk[j], last);
             store_t<NT, K>(gptr<K, SMALL>(job.dst_k, p), key[j]);
             if constexpr (VALS) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, p), val[j]);
+        }
+    }
+    if constexpr (FUSED) {  // the tile's next-digit counts into one copy of the next pass's row
+        __syncthreads();
+        uint32_t *row = job.next_hist + (blockIdx.x % kFusedCopies) * kFusedBins;
+        for (uint32_t d = tid; d < static_cast<uint32_t>(kFusedBins); d += BLOCK) {
+            const uint32_t c = lds.fused[d];
+            if (c) atomicAdd(&row[d], c);
         }
     }
 }
@@ -1024,19 +1070,22 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
 // first and last tile can be partial.  The grid needs ctile[nchunks]
 // blocks; surplus blocks find every chunk exhausted and exit.  The plan's
 // pointers are reinterpreted as K keys and V values.
-template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE>
-__device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V, VALS> &lds,
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE,
+          bool FUSED = false>
+__device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED> &lds,
                                               const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                               S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
-                                              uint32_t *__restrict__ error_flag) {
+                                              uint32_t *__restrict__ error_flag, uint32_t *__restrict__ hist = nullptr) {
     constexpr int TILE = BLOCK * IPT;
     constexpr uint32_t RADIX = 1u << BITS;
     // byte offsets fit in 32 bits (the 32-bit status words serve n < 2^30)
     constexpr bool SMALL = sizeof(S) == 4 && sizeof(K) == 4 && sizeof(V) == 4;
     const PassPlan *pp = plan->pass + pass;
     if (!pp->active) return;
-    // this wave's digit counters start at zero
+    // this wave's digit counters start at zero (and the fused counts)
     for (uint32_t i = threadIdx.x & 63u; i < RADIX; i += 64) lds.whist[(threadIdx.x >> 6) * RADIX + i] = 0u;
+    if constexpr (FUSED)
+        for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(kFusedBins); i += BLOCK) lds.fused[i] = 0u;
     if (threadIdx.x == 0)
         claim_tile<TILE>(pp, chunk_counter, lds.claim[0], lds.claim[1], lds.claim[2], lds.claim[3], lds.claim[4]);
     __syncthreads();
@@ -1054,17 +1103,22 @@ __device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V
     job.first = lds.claim[1];
     job.valid = lds.claim[4];
     job.bound = n;
-    onesweep_tile<BITS, BLOCK, IPT, K, V, VALS, NT, S, STAGE, SMALL>(job, lds, status, error_flag);
+    job.next_hist = FUSED ? hist + (pass + 1) * kMaxRadix : nullptr;
+    job.next_shift = FUSED ? plan->pass[pass + 1].shift : 0u;
+    job.next_width = FUSED ? plan->pass[pass + 1].width : 0u;
+    onesweep_tile<BITS, BLOCK, IPT, K, V, VALS, NT, S, STAGE, SMALL, FUSED>(job, lds, status, error_flag);
 }
 
-// The pass over 32-bit keys (with 32-bit values when VALS).
-template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true>
+// The pass over 32-bit keys (with 32-bit values when VALS).  FUSED: the
+// pass also counts the next pass's digit of the items it writes into hist's
+// row pass + 1 (kFusedCopies copies; see k_plan_fused).
+template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STAGE = true, bool FUSED = false>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                                     S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
-                                                    uint32_t *__restrict__ error_flag) {
-    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS> lds;
-    onesweep_pass<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, NT, S, STAGE>(lds, plan, pass, n, status,
-                                                                           chunk_counter, error_flag);
+                                                    uint32_t *__restrict__ error_flag, uint32_t *__restrict__ hist) {
+    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, FUSED> lds;
+    onesweep_pass<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, NT, S, STAGE, FUSED>(lds, plan, pass, n, status,
+                                                                                  chunk_counter, error_flag, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -1093,6 +1147,62 @@ static __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__
                                                 size_t words) {
     const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i < words) dst[i] = src[i];
+}
+
+// Bandwidth probes, the ceilings the passes are set against (measurement
+// only).  Each moves whole 16-byte words: copy with 4 words in flight per
+// thread and non-temporal loads and stores over a grid-stride loop; read
+// only (an XOR of every word, stored only if it hits a fixed value, so the
+// loads cannot be dropped); write only.
+constexpr int kProbeWords = 4;  // 16-byte words in flight per thread
+
+static __global__ __launch_bounds__(256) void k_copy16_nt(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                          size_t words) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const v4u *s = reinterpret_cast<const v4u *>(src);
+    v4u *d = reinterpret_cast<v4u *>(dst);
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256 * kProbeWords;
+    for (size_t b = static_cast<size_t>(blockIdx.x) * 256 * kProbeWords; b < words; b += stride) {
+        v4u v[kProbeWords];
+#pragma unroll
+        for (int u = 0; u < kProbeWords; ++u) {
+            const size_t i = b + u * 256 + threadIdx.x;
+            if (i < words) v[u] = __builtin_nontemporal_load(s + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeWords; ++u) {
+            const size_t i = b + u * 256 + threadIdx.x;
+            if (i < words) __builtin_nontemporal_store(v[u], d + i);
+        }
+    }
+}
+
+static __global__ __launch_bounds__(256) void k_read16(const uint4 *__restrict__ src, uint32_t *__restrict__ sink,
+                                                       size_t words) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256 * kProbeWords;
+    uint32_t acc = 0;
+    for (size_t b = static_cast<size_t>(blockIdx.x) * 256 * kProbeWords; b < words; b += stride) {
+        uint4 v[kProbeWords];
+#pragma unroll
+        for (int u = 0; u < kProbeWords; ++u) {
+            const size_t i = b + u * 256 + threadIdx.x;
+            v[u] = i < words ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeWords; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;
+}
+
+static __global__ __launch_bounds__(256) void k_write16(uint4 *__restrict__ dst, size_t words) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256 * kProbeWords;
+    for (size_t b = static_cast<size_t>(blockIdx.x) * 256 * kProbeWords; b < words; b += stride) {
+#pragma unroll
+        for (int u = 0; u < kProbeWords; ++u) {
+            const size_t i = b + u * 256 + threadIdx.x;
+            if (i < words) dst[i] = make_uint4(static_cast<uint32_t>(i), 1u, 2u, 3u);
+        }
+    }
 }
 
 static __global__ __launch_bounds__(256) void k_copy4(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,

@@ -133,8 +133,22 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
     r.flags = c.flags;
     r.with_values = with_values != 0;
     if (r.flags & ~static_cast<uint32_t>(RT_FLAG_NO_SKIP | RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER |
-                                         RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS | RT_FLAG_VALIDATE))
+                                         RT_FLAG_ONE_CHAIN | RT_FLAG_CHUNKS | RT_FLAG_VALIDATE |
+                                         RT_FLAG_FUSED_HISTOGRAM))
         return set_error(RT_ERR_INVALID_ARG, "unknown flags 0x%x", r.flags);
+    r.fused = (r.flags & RT_FLAG_FUSED_HISTOGRAM) != 0;
+    if (r.fused) {
+        if (r.flags & RT_FLAG_CHUNKS)
+            return set_error(RT_ERR_UNSUPPORTED, "RT_FLAG_FUSED_HISTOGRAM runs on one chain: not with RT_FLAG_CHUNKS");
+        if (r.flags & (RT_FLAG_DIRECT_SCATTER | RT_FLAG_NT_STORES))
+            return set_error(RT_ERR_UNSUPPORTED,
+                             "RT_FLAG_FUSED_HISTOGRAM is built for the staged pass with plain stores only");
+        for (uint32_t p = 0; p < r.num_passes; ++p)
+            if (r.width[p] > 8)
+                return set_error(RT_ERR_UNSUPPORTED, "RT_FLAG_FUSED_HISTOGRAM needs digits of at most 8 bits");
+        // the later histograms do not exist when the buffers are planned
+        r.flags |= RT_FLAG_NO_SKIP | RT_FLAG_ONE_CHAIN;
+    }
     if ((r.flags & RT_FLAG_ONE_CHAIN) && (r.flags & RT_FLAG_CHUNKS))
         return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
     // per-chunk counts need digits of at most 8 bits (kChunkRadix); below
@@ -282,26 +296,34 @@ void prof_mark(hipStream_t stream, uint32_t kind) { prof_record(stream, kind); }
 // launches
 // ---------------------------------------------------------------------------
 
+// fused_hist (RT_FLAG_FUSED_HISTOGRAM, not for a sort's last pass): the
+// pass also counts the next pass's digit into that pass's row of it.
 template <int BITS, int BLOCK, int IPT>
 static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStream_t stream, const SortPlan *plan,
-                              int pass, uint32_t n, void *status, uint32_t *ctr, uint32_t kind) {
+                              int pass, uint32_t n, void *status, uint32_t *ctr, uint32_t kind,
+                              uint32_t *fused_hist) {
     const dim3 grid(L.grid_tiles), block(BLOCK);
     uint32_t *err = ctr + kMaxPasses;
     uint32_t *chunk_ctr = ctr + kMaxPasses + 1 + pass * kChunks;
     const bool nt = (flags & RT_FLAG_NT_STORES) != 0;
     const bool stage = (flags & RT_FLAG_DIRECT_SCATTER) == 0;
-#define RT_OS(V, NTV, S, STG)                                                                                      \
-    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG>), grid, block, 0, stream, plan, pass, n, \
-                       static_cast<S *>(status), chunk_ctr, err)
-    if (!stage) {  // resolve_config rules out the non-temporal form here
-        if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, false); else RT_OS(false, false, uint64_t, false); }
-        else               { if (vals) RT_OS(true, false, uint32_t, false); else RT_OS(false, false, uint32_t, false); }
+#define RT_OS(V, NTV, S, STG, FU)                                                                                \
+    hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG, FU>), grid, block, 0, stream, plan, pass, n, \
+                       static_cast<S *>(status), chunk_ctr, err, fused_hist)
+    if (fused_hist != nullptr) {  // resolve_config: staged, plain stores, digits of at most 8 bits
+        if constexpr (BITS == 8) {
+            if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, true, true); else RT_OS(false, false, uint64_t, true, true); }
+            else               { if (vals) RT_OS(true, false, uint32_t, true, true); else RT_OS(false, false, uint32_t, true, true); }
+        }
+    } else if (!stage) {  // resolve_config rules out the non-temporal form here
+        if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, false, false); else RT_OS(false, false, uint64_t, false, false); }
+        else               { if (vals) RT_OS(true, false, uint32_t, false, false); else RT_OS(false, false, uint32_t, false, false); }
     } else if (L.wide_status) {
-        if (vals) { if (nt) RT_OS(true, true, uint64_t, true); else RT_OS(true, false, uint64_t, true); }
-        else      { if (nt) RT_OS(false, true, uint64_t, true); else RT_OS(false, false, uint64_t, true); }
+        if (vals) { if (nt) RT_OS(true, true, uint64_t, true, false); else RT_OS(true, false, uint64_t, true, false); }
+        else      { if (nt) RT_OS(false, true, uint64_t, true, false); else RT_OS(false, false, uint64_t, true, false); }
     } else {
-        if (vals) { if (nt) RT_OS(true, true, uint32_t, true); else RT_OS(true, false, uint32_t, true); }
-        else      { if (nt) RT_OS(false, true, uint32_t, true); else RT_OS(false, false, uint32_t, true); }
+        if (vals) { if (nt) RT_OS(true, true, uint32_t, true, false); else RT_OS(true, false, uint32_t, true, false); }
+        else      { if (nt) RT_OS(false, true, uint32_t, true, false); else RT_OS(false, false, uint32_t, true, false); }
     }
 #undef RT_OS
     prof_mark(stream, kind);
@@ -309,11 +331,11 @@ static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStr
 
 static void launch_pass(int bits_class, int block, int ipt, const Layout &L, bool vals, uint32_t flags,
                         hipStream_t stream, const SortPlan *plan, int pass, uint32_t n, void *status,
-                        uint32_t *ctr, uint32_t kind) {
-#define RT_SHAPE_LAUNCH(B, BLK, I)                                                               \
-    if (bits_class == B && block == BLK && ipt == I) {                                           \
-        launch_pass_shape<B, BLK, I>(L, vals, flags, stream, plan, pass, n, status, ctr, kind); \
-        return;                                                                                  \
+                        uint32_t *ctr, uint32_t kind, uint32_t *fused_hist) {
+#define RT_SHAPE_LAUNCH(B, BLK, I)                                                                           \
+    if (bits_class == B && block == BLK && ipt == I) {                                                       \
+        launch_pass_shape<B, BLK, I>(L, vals, flags, stream, plan, pass, n, status, ctr, kind, fused_hist); \
+        return;                                                                                              \
     }
     RT_FOR_EACH_SHAPE(RT_SHAPE_LAUNCH)
 #undef RT_SHAPE_LAUNCH
@@ -458,7 +480,11 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
                        fill_words);
     prof_mark(stream, RT_KIND_FILL);
     uint32_t *mode = ctr + kMaxPasses + 1 + kMaxPasses * kChunks;
-    const bool probed = launch_histograms(keys, n, r, hist, stream, true, r.chunked, r.probe ? mode : nullptr);
+    // fused: the upfront read counts only the first pass's digit; each pass
+    // counts the next one's
+    Resolved rh = r;
+    if (r.fused) rh.num_passes = 1;
+    const bool probed = launch_histograms(keys, n, rh, hist, stream, true, r.chunked, r.probe ? mode : nullptr);
 
     PlanArgs a{};
     a.num_passes = r.num_passes;
@@ -488,9 +514,16 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, stream, a, hist, base, plan, ctr, direct ? 1u : 0u);
     prof_mark(stream, RT_KIND_PLAN);
 
-    for (uint32_t p = 0; p < r.num_passes; ++p)
+    for (uint32_t p = 0; p < r.num_passes; ++p) {
+        const bool count_next = r.fused && p + 1 < r.num_passes;
         launch_pass(bits_class_of(r.width[p]), r.block, r.ipt, L, r.with_values, r.flags, stream, plan,
-                    static_cast<int>(p), n, status + L.status_pass[p], ctr, pass_kind + p);
+                    static_cast<int>(p), n, status + L.status_pass[p], ctr, pass_kind + p,
+                    count_next ? hist : nullptr);
+        if (count_next) {  // the next pass's digit starts from what this pass counted
+            hipLaunchKernelGGL(k_plan_fused, dim3(1), dim3(256), 0, stream, hist, base, p + 1, r.width[p + 1], n);
+            prof_mark(stream, RT_KIND_PLAN);
+        }
+    }
 
     if (!direct && (r.num_passes == 1 || !(r.flags & RT_FLAG_NO_SKIP))) {
         const uint32_t grid_c = grid_for(n, 256 * 8, static_cast<uint32_t>(device_cu_count()) * 8);
@@ -734,6 +767,42 @@ extern "C" rt_status rt_copy(const void *src, void *dst, size_t bytes, hipStream
     }
     prof_mark(stream, RT_KIND_COPY);
     return finish_call(stream, "rt_copy");
+}
+
+extern "C" rt_status rt_bandwidth_probe(const void *src, void *dst, size_t bytes, uint32_t kind, uint32_t *sink,
+                                        hipStream_t stream) {
+    if (kind > RT_PROBE_WRITE) return set_error(RT_ERR_INVALID_ARG, "rt_bandwidth_probe: unknown kind %u", kind);
+    if (bytes == 0) return RT_OK;
+    const bool reads = kind != RT_PROBE_WRITE, writes = kind != RT_PROBE_READ;
+    if ((reads && src == nullptr) || (writes && dst == nullptr) || (kind == RT_PROBE_READ && sink == nullptr))
+        return set_error(RT_ERR_INVALID_ARG, "rt_bandwidth_probe: NULL pointer");
+    if ((bytes | (reads ? reinterpret_cast<uintptr_t>(src) : 0u) | (writes ? reinterpret_cast<uintptr_t>(dst) : 0u)) &
+        15u)
+        return set_error(RT_ERR_INVALID_ARG, "rt_bandwidth_probe: pointers and bytes must be multiples of 16");
+    const size_t words = bytes / 16;
+    const uint32_t cus = static_cast<uint32_t>(device_cu_count());
+    // the grid-stride probes: 16 blocks of 256 threads per CU
+    const uint32_t grid = grid_for(words, 256 * kProbeWords, cus * 16);
+    prof_begin(stream);
+    switch (kind) {
+        case RT_PROBE_COPY:
+            hipLaunchKernelGGL(k_copy16, dim3(static_cast<uint32_t>((words + 255) / 256)), dim3(256), 0, stream,
+                               static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), words);
+            break;
+        case RT_PROBE_COPY_NT:
+            hipLaunchKernelGGL(k_copy16_nt, dim3(grid), dim3(256), 0, stream, static_cast<const uint4 *>(src),
+                               static_cast<uint4 *>(dst), words);
+            break;
+        case RT_PROBE_READ:
+            hipLaunchKernelGGL(k_read16, dim3(grid), dim3(256), 0, stream, static_cast<const uint4 *>(src), sink,
+                               words);
+            break;
+        default:
+            hipLaunchKernelGGL(k_write16, dim3(grid), dim3(256), 0, stream, static_cast<uint4 *>(dst), words);
+            break;
+    }
+    prof_mark(stream, RT_KIND_COPY);
+    return finish_call(stream, "rt_bandwidth_probe");
 }
 
 extern "C" rt_status rt_generate(uint32_t *keys, uint32_t *vals, size_t n, const rt_gen_params *params,

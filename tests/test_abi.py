@@ -131,6 +131,47 @@ def test_validate_flag_is_accepted_everywhere(so):
     assert so.rt_workspace_bytes(1 << 20, 1, ctypes.byref(c)) == 0
 
 
+def test_bandwidth_probe_argument_errors(so):
+    fake = ctypes.c_void_p(0x10000)
+    sink = ctypes.c_void_p(0x20000)
+    assert so.rt_bandwidth_probe(fake, fake, 0, _lib.RT_PROBE_COPY, None, None) == _lib.RT_OK  # nothing to do
+    assert so.rt_bandwidth_probe(fake, fake, 4096, 4, None, None) == _lib.RT_ERR_INVALID_ARG  # no such kind
+    assert so.rt_bandwidth_probe(None, fake, 4096, _lib.RT_PROBE_COPY, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_bandwidth_probe(fake, None, 4096, _lib.RT_PROBE_READ, None, None) == _lib.RT_ERR_INVALID_ARG  # no sink
+    assert so.rt_bandwidth_probe(None, fake, 4100, _lib.RT_PROBE_WRITE, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_bandwidth_probe(ctypes.c_void_p(0x10004), sink, 4096, _lib.RT_PROBE_READ, sink, None) \
+        == _lib.RT_ERR_INVALID_ARG  # misaligned
+
+
+def test_fused_histogram_flag(so):
+    """RT_FLAG_FUSED_HISTOGRAM resolves for 8-bit digits (and then never
+    needs the second temporary: every pass runs), and is refused with wider
+    digits, XCD chunks forced, the direct scatter, non-temporal stores, or
+    64-bit keys."""
+    fake_k, fake_v = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
+
+    def cfg(bits, flags):
+        c = _lib.RtConfig()
+        c.num_passes = len(bits)
+        for i, b in enumerate(bits):
+            c.digit_bits[i] = b
+        c.flags = flags
+        return c
+
+    F = _lib.RT_FLAG_FUSED_HISTOGRAM
+    n = 1 << 20
+    plain = so.rt_workspace_bytes(n, 1, ctypes.byref(cfg((8, 8, 8, 8), 0)))
+    fused = so.rt_workspace_bytes(n, 1, ctypes.byref(cfg((8, 8, 8, 8), F)))
+    assert fused > 0 and plain - fused >= 2 * 4 * n  # no second temporary (two arrays of n words)
+    assert so.rt_workspace_bytes(n, 1, ctypes.byref(cfg((8, 8, 8, 8), F | _lib.RT_FLAG_ONE_CHAIN))) == fused
+    for bits, flags in (((11, 11, 10), F), ((8, 8, 8, 8), F | _lib.RT_FLAG_CHUNKS),
+                        ((8, 8, 8, 8), F | _lib.RT_FLAG_DIRECT_SCATTER), ((8, 8, 8, 8), F | _lib.RT_FLAG_NT_STORES)):
+        c = cfg(bits, flags)
+        assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED, \
+            (bits, flags)
+    assert so.rt_workspace_bytes64(n, 4, ctypes.byref(cfg((8,) * 8, F))) == 0
+
+
 def test_config_validation(so):
     fake_k, fake_v = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
     for bits, want in [((8, 8, 8), _lib.RT_ERR_INVALID_ARG),        # sums to 24

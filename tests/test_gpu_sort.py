@@ -159,6 +159,23 @@ def test_validated_sort(n):
         assert_same((to_host(kd), to_host(vd)), want, f"validate {extra} caller workspace")
 
 
+@pytest.mark.parametrize("n,dist", [(1000, "uniform"), (3 * TILE + 77, "uniform"), (3 * TILE + 77, "and4"),
+                                    ((1 << 22) + 123, "uniform"), ((1 << 22) + 123, "zipf16")])
+def test_fused_histogram(n, dist):
+    """RT_FLAG_FUSED_HISTOGRAM: passes 0-2 count the next pass's digit while
+    they write, and the sort still equals the oracle's, pairs and keys only,
+    with ragged last tiles, under 8x4 digits, two 4-bit digits in other
+    shapes, and 4-bit digits throughout."""
+    from paper_1008_2849_amd.api import FLAG_FUSED_HISTOGRAM
+    announce(f"fused histogram n={n} dist={dist}")
+    k = inputs.uniform_keys(n, 94) if dist == "uniform" else _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    for widths, shape in (((8, 8, 8, 8), (1024, 16)), ((4, 4, 8, 8, 8), (512, 16)), ((4,) * 8, (1024, 8))):
+        cfg = Config(widths, shape[0], shape[1], FLAG_FUSED_HISTOGRAM)
+        assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"fused {widths}")
+        assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k, None, widths), f"fused keys {widths}")
+
+
 @pytest.mark.parametrize("widths,shape", [((11, 11, 10), (512, 16)), ((8, 8, 8, 8), (256, 16)),
                                           ((4,) * 8, (1024, 8))])
 def test_direct_scatter_configs(widths, shape):
@@ -387,6 +404,32 @@ def test_copy_probe():
     rts.copy(a[1:], c[1:n])  # not 16-byte aligned
     sync()
     assert torch.equal(c[1:n], a[1:])
+
+
+def test_bandwidth_probes():
+    """The probes move what they say: both copies reproduce the source, the
+    write probe writes its pattern (word i: i, 1, 2, 3), the read probe
+    leaves its source alone."""
+    import torch
+    from paper_1008_2849_amd import _lib
+    n = (1 << 22) + 64  # 16-byte words: a multiple of 4 items, past one grid stride
+    a = to_dev(inputs.uniform_keys(n, 93))
+    for kind in (_lib.RT_PROBE_COPY, _lib.RT_PROBE_COPY_NT):
+        b = torch.zeros_like(a)
+        rts.bandwidth_probe(kind, src=a, dst=b)
+        sync()
+        assert torch.equal(a, b), kind
+    w = torch.zeros_like(a)
+    rts.bandwidth_probe(_lib.RT_PROBE_WRITE, dst=w)
+    sync()
+    words = w.view(-1, 4).cpu().numpy().view(np.uint32)
+    assert np.array_equal(words[:, 0], np.arange(n // 4, dtype=np.uint32))
+    assert (words[:, 1:] == np.array([1, 2, 3], dtype=np.uint32)).all()
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    before = a.clone()
+    rts.bandwidth_probe(_lib.RT_PROBE_READ, src=a, sink=sink)
+    sync()
+    assert torch.equal(a, before)
 
 
 @pytest.mark.parametrize("n,dist", [(3 * TILE + 1234, "uniform"), ((1 << 25) + 1234, "uniform"),
