@@ -296,6 +296,25 @@ rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const rt_config *c
                               uint32_t *hist, hipStream_t stream);
 
 /*
+ * The XCD-chunk decision that rt_sort_pairs_ex (with_values != 0) or
+ * rt_sort_keys-style calls (with_values == 0) make for these n keys under
+ * cfg (NULL = tuned default), written to *mode (device u32): 1 = the passes
+ * run in XCD chunks, 0 = one lookback chain per pass.  Where the sort
+ * samples its keys (see RT_FLAG_CHUNKS) this runs the same sample kernel on
+ * the same keys; otherwise it writes what the size, the digit widths and the
+ * flags fix.  n < 2 writes 0.  A measurement and test hook: the sort's
+ * result does not depend on the decision.  Errors as for rt_digit_histograms
+ * (mode NULL: RT_ERR_INVALID_ARG).
+ */
+rt_status rt_chunk_decision(const uint32_t *keys, size_t n, int with_values, const rt_config *cfg,
+                            uint32_t *mode, hipStream_t stream);
+
+/* The same for a sort of 64-bit keys with value_bytes of 0, 4 or 8
+ * (rt_sort64_ex's decision). */
+rt_status rt_chunk_decision64(const uint64_t *keys, size_t n, uint32_t value_bytes, const rt_config *cfg,
+                              uint32_t *mode, hipStream_t stream);
+
+/*
  * One stable counting-sort pass, out of place (Section 3, naive algorithm:
  * histogram, exclusive prefix sum, scatter with increment) on digit
  * [shift, shift + width).  kin/vin are read, kout/vout written (vin and vout

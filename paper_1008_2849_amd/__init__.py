@@ -13,7 +13,7 @@ __all__ = [
     "Config", "sort_keys", "sort_pairs", "sort_ex", "sort_noalloc", "bandwidth_probe", "sort_pairs_batched",
     "sort_batched_ex", "batched_workspace_bytes", "workspace_bytes", "sort_msd_first",
     "msd_first_workspace_bytes", "sort_keys64", "sort_pairs64", "sort64_ex", "workspace_bytes64",
-    "segment_classes", "segment_config", "digit_histograms", "counting_pass", "copy",
+    "segment_classes", "segment_config", "digit_histograms", "chunk_decision", "counting_pass", "copy",
     "generate", "load_tuning", "load_default_tuning", "tuned_config", "version", "Server", "RtError",
     "profile_start", "profile_stop",
 ]

@@ -112,6 +112,8 @@ SIGNATURES = {
     "rt_segment_config": (ctypes.c_int, [ctypes.POINTER(u32)] * 3),
     "rt_sort_msd_first": (ctypes.c_int, [vp, vp, sz, u32, vp, sz, vp]),
     "rt_digit_histograms": (ctypes.c_int, [vp, sz, ctypes.POINTER(RtConfig), vp, vp]),
+    "rt_chunk_decision": (ctypes.c_int, [vp, sz, ctypes.c_int, ctypes.POINTER(RtConfig), vp, vp]),
+    "rt_chunk_decision64": (ctypes.c_int, [vp, sz, u32, ctypes.POINTER(RtConfig), vp, vp]),
     "rt_counting_pass": (ctypes.c_int, [vp, vp, vp, vp, sz, u32, u32, vp]),
     "rt_copy": (ctypes.c_int, [vp, vp, sz, vp]),
     "rt_generate": (ctypes.c_int, [vp, vp, sz, ctypes.POINTER(RtGenParams), u32, vp]),

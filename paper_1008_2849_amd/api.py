@@ -266,6 +266,24 @@ def digit_histograms(keys, cfg: Optional[Config] = None, stream=None):
     return hist[:passes]
 
 
+def chunk_decision(keys, with_values: bool = True, cfg: Optional[Config] = None, value_bytes: int = 4,
+                   stream=None) -> int:
+    """The XCD-chunk decision a sort of these keys makes: 1 = chunks, 0 = one
+    chain.  u32 keys ask for the 32-bit sort's decision (with or without
+    values), u64 keys for the 64-bit sort's with value_bytes of 0, 4 or 8."""
+    torch = _torch()
+    _check_tensor64(keys, "keys", (torch.int32, torch.uint32, torch.int64, torch.uint64))
+    mode = torch.full((1,), -1, dtype=torch.int32, device=keys.device)
+    c, p = _cfg_ptr(cfg)
+    if keys.element_size() == 8:
+        check(lib().rt_chunk_decision64(_ptr(keys), keys.numel(), value_bytes, p, mode.data_ptr(), _stream(stream)),
+              "rt_chunk_decision64")
+    else:
+        check(lib().rt_chunk_decision(_ptr(keys), keys.numel(), 1 if with_values else 0, p, mode.data_ptr(),
+                                      _stream(stream)), "rt_chunk_decision")
+    return int(mode.item())
+
+
 def counting_pass(kin, vin, kout, vout, shift: int, width: int, stream=None) -> None:
     """One stable counting-sort pass on bits [shift, shift+width), out of place."""
     for t, nm in ((kin, "kin"), (vin, "vin"), (kout, "kout"), (vout, "vout")):

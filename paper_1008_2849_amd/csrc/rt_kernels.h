@@ -162,6 +162,10 @@ static __global__ __launch_bounds__(256) void k_fill_zero(uint32_t *__restrict__
         p[i] = 0u;
 }
 
+static __global__ __launch_bounds__(64) void k_set_word(uint32_t *__restrict__ p, uint32_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // upfront histograms of all passes (one read of the keys)
 // ---------------------------------------------------------------------------

@@ -427,6 +427,13 @@ static void launch_histogram_auto_copies(const uint32_t *keys, uint32_t n, const
                        mode, hist);
 }
 
+// Whether the sample kernel chooses between XCD chunks and one chain (it
+// runs only where the plain counts have all 16 lane-class copies, which the
+// histogram kernel that reads its choice needs); otherwise r.chunked stands.
+static bool sample_decides(const Resolved &r, uint32_t n) {
+    return r.probe && hist_copies(hist_args(r, n, false).total_bins) == 16;
+}
+
 // hist_zeroed: the caller has cleared the counters already.  chunked: the
 // per-chunk counts of a sort with r.chunked, in place of the plain ones;
 // with mode set (r.probe) the probe kernel chooses between the two and
@@ -441,7 +448,7 @@ bool launch_histograms(const uint32_t *keys, uint32_t n, const Resolved &r, uint
         prof_mark(stream, RT_KIND_FILL);
     }
     const HistArgs hp = hist_args(r, n, false);
-    const bool probe = chunked && mode != nullptr && hist_copies(hp.total_bins) == 16;
+    const bool probe = chunked && mode != nullptr && sample_decides(r, n);
     if (probe) {
         hipLaunchKernelGGL(k_chunk_probe<1024>, dim3(1), dim3(1024), 0, stream, keys, n, ha, mode);
         prof_mark(stream, RT_KIND_PROBE);
@@ -685,6 +692,26 @@ extern "C" rt_status rt_digit_histograms(const uint32_t *keys, size_t n, const r
     prof_begin(stream);
     launch_histograms(keys, static_cast<uint32_t>(n), r, hist, stream, false, false, nullptr);
     return finish_call(stream, "rt_digit_histograms");
+}
+
+extern "C" rt_status rt_chunk_decision(const uint32_t *keys, size_t n, int with_values, const rt_config *cfg,
+                                       uint32_t *mode, hipStream_t stream) {
+    if (n >= (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_TOO_LARGE, "rt_chunk_decision: n = %zu", n);
+    if (mode == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision: mode is NULL");
+    if (keys == nullptr && n > 0) return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision: keys is NULL");
+    Resolved r;
+    rt_status s = resolve_config(cfg, n < 2 ? 2 : n, with_values, &r);
+    if (s != RT_OK) return s;
+    prof_begin(stream);
+    if (n >= 2 && sample_decides(r, static_cast<uint32_t>(n))) {
+        hipLaunchKernelGGL(k_chunk_probe<1024>, dim3(1), dim3(1024), 0, stream, keys, static_cast<uint32_t>(n),
+                           hist_args(r, n, true), mode);
+        prof_mark(stream, RT_KIND_PROBE);
+    } else {
+        hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, stream, mode, (n >= 2 && r.chunked) ? 1u : 0u);
+    }
+    return finish_call(stream, "rt_chunk_decision");
 }
 
 extern "C" rt_status rt_counting_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,

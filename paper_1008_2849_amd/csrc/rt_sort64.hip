@@ -110,6 +110,15 @@ void chunk_mode64(size_t n, Resolved *r) {
     r->probe = r->chunked && !forced;
 }
 
+int copies64(uint32_t bins);
+
+// Whether the sample kernel chooses between XCD chunks and one chain: only
+// where the plain eight-digit counts have all 8 copies, as the histogram
+// kernel that reads its choice needs; otherwise r.chunked stands.
+static bool sample_decides64(const Resolved &r, uint32_t n) {
+    return r.probe && copies64(hist_args(r, n, false).total_bins) == 8;
+}
+
 struct Layout64 {
     size_t hist, ctr, base, plan, status, status_bytes;
     size_t status_pass[kMaxPasses];
@@ -270,7 +279,7 @@ void launch_sort64(uint64_t *keys, uint32_t *vals, uint32_t vw, uint32_t n, cons
     bool probed = false;
     if (r.chunked) {
         const HistArgs hc = hist_args(r, n, true);
-        if (r.probe && copies64(ha.total_bins) == 8) {
+        if (sample_decides64(r, n)) {
             hipLaunchKernelGGL((k_chunk_probe<1024, uint64_t>), dim3(1), dim3(1024), 0, stream, keys, n, hc, mode);
             prof_mark(stream, RT_KIND_PROBE);
             switch (copies64(hc.total_bins)) {
@@ -400,6 +409,29 @@ extern "C" rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_byt
         if (s == RT_OK && err) return set_error(RT_ERR_HIP, "rt_sort64_ex: device error word 0x%x", err);
     }
     return s;
+}
+
+extern "C" rt_status rt_chunk_decision64(const uint64_t *keys, size_t n, uint32_t value_bytes, const rt_config *cfg,
+                                         uint32_t *mode, hipStream_t stream) {
+    if (n >= (static_cast<size_t>(1) << 32))
+        return set_error(RT_ERR_TOO_LARGE, "rt_chunk_decision64: n = %zu", n);
+    if (mode == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision64: mode is NULL");
+    if (keys == nullptr && n > 0) return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision64: keys is NULL");
+    if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8)
+        return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision64: value_bytes %u is not 0, 4 or 8", value_bytes);
+    Resolved r;
+    rt_status s = resolve64(cfg, value_bytes / 4, &r);
+    if (s != RT_OK) return s;
+    chunk_mode64(n, &r);
+    prof_begin(stream);
+    if (n >= 2 && sample_decides64(r, static_cast<uint32_t>(n))) {
+        hipLaunchKernelGGL((k_chunk_probe<1024, uint64_t>), dim3(1), dim3(1024), 0, stream, keys,
+                           static_cast<uint32_t>(n), hist_args(r, n, true), mode);
+        prof_mark(stream, RT_KIND_PROBE);
+    } else {
+        hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, stream, mode, (n >= 2 && r.chunked) ? 1u : 0u);
+    }
+    return finish_call(stream, "rt_chunk_decision64");
 }
 
 extern "C" rt_status rt_sort_keys64(uint64_t *keys, size_t n, hipStream_t stream) {

@@ -143,6 +143,23 @@ def test_bandwidth_probe_argument_errors(so):
         == _lib.RT_ERR_INVALID_ARG  # misaligned
 
 
+def test_chunk_decision_argument_errors(so):
+    """The chunk-decision hooks refuse what the sorts refuse, before any
+    launch."""
+    fake = ctypes.c_void_p(0x10000)
+    mode = ctypes.c_void_p(0x20000)
+    assert so.rt_chunk_decision(fake, 1 << 25, 1, None, None, None) == _lib.RT_ERR_INVALID_ARG  # mode NULL
+    assert so.rt_chunk_decision(None, 1 << 25, 1, None, mode, None) == _lib.RT_ERR_INVALID_ARG  # keys NULL
+    assert so.rt_chunk_decision(fake, 1 << 32, 1, None, mode, None) == _lib.RT_ERR_TOO_LARGE
+    both = _lib.RtConfig()
+    both.flags = _lib.RT_FLAG_ONE_CHAIN | _lib.RT_FLAG_CHUNKS
+    assert so.rt_chunk_decision(fake, 1 << 25, 1, ctypes.byref(both), mode, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_chunk_decision64(fake, 1 << 25, 2, None, mode, None) == _lib.RT_ERR_INVALID_ARG  # value bytes
+    assert so.rt_chunk_decision64(fake, 1 << 25, 4, None, None, None) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_chunk_decision64(fake, 1 << 32, 4, None, mode, None) == _lib.RT_ERR_TOO_LARGE
+    assert so.rt_chunk_decision64(fake, 1 << 25, 4, ctypes.byref(both), mode, None) == _lib.RT_ERR_INVALID_ARG
+
+
 def test_fused_histogram_flag(so):
     """RT_FLAG_FUSED_HISTOGRAM resolves for 8-bit digits (and then never
     needs the second temporary: every pass runs), and is refused with wider

@@ -206,16 +206,45 @@ def test_chunk_flags(dist):
     assert_same(gpu_sort(k, None, cfg), oracle.lsd_sort(k), f"keys chunks {dist}")
 
 
-@pytest.mark.parametrize("dist", ["uniform", "and4", "zipf16", "top_a5", "low_byte_only", "sorted"])
+# The sample's decision where it is clear from the distribution: uniform and
+# constant-top-byte keys balance the chunks; AND-4 keys (digit 0 in 60 % of
+# them) and Zipf-16 keys (the first key in about 36 %) put far more than
+# 1/64 of the sample in one bin.  None: not asserted.
+PROBE_EXPECTED = {"uniform": 1, "top_a5": 1, "and4": 0, "zipf16": 0, "low_byte_only": None, "sorted": None}
+
+
+@pytest.mark.parametrize("dist", list(PROBE_EXPECTED))
 def test_probed_sizes(dist):
     """At 2^25 items and above the default samples the keys and picks XCD
     chunks (uniform, constant top byte) or one chain (skewed keys): the
-    result is the oracle's either way."""
+    decision is the expected one, and the result is the oracle's either
+    way."""
+    import torch
     n = (1 << 25) + 77
     announce(f"probed dist={dist} n={n}")
     k = inputs.uniform_keys(n, 700) if dist == "uniform" else _dist_cases(n)[dist]
     v = inputs.index_values(n)
+    mode = rts.chunk_decision(torch.from_numpy(k.view(np.int32)).cuda())
+    assert mode in (0, 1)
+    if PROBE_EXPECTED[dist] is not None:
+        assert mode == PROBE_EXPECTED[dist], f"{dist}: chunk decision {mode}"
     assert_same(gpu_sort(k, v), oracle.lsd_sort(k, v), dist)
+
+
+def test_chunk_decision_fixed_cases():
+    """Where no sample is taken the decision follows the size, the digit
+    widths and the flags: below 2^25 items one chain, RT_FLAG_CHUNKS chunks at
+    any size, RT_FLAG_ONE_CHAIN and 11-bit digits one chain."""
+    import torch
+    announce("chunk decision fixed cases")
+    small = torch.from_numpy(inputs.uniform_keys(1 << 20, 701).view(np.int32)).cuda()
+    assert rts.chunk_decision(small) == 0
+    assert rts.chunk_decision(small[:1]) == 0
+    assert rts.chunk_decision(small, cfg=Config((8, 8, 8, 8), 1024, 16, FLAG_CHUNKS)) == 1
+    big = torch.from_numpy(_dist_cases((1 << 25) + 1)["and4"].view(np.int32)).cuda()
+    assert rts.chunk_decision(big, cfg=Config((8, 8, 8, 8), 1024, 16, FLAG_CHUNKS)) == 1
+    assert rts.chunk_decision(big, cfg=Config((8, 8, 8, 8), 1024, 16, FLAG_ONE_CHAIN)) == 0
+    assert rts.chunk_decision(big, cfg=Config((11, 11, 10), 512, 16, 0)) == 0
 
 
 def test_probed_keys_only_tuned_shape():

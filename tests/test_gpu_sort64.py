@@ -126,14 +126,17 @@ def test_chunk_flags(dist):
     check(gpu_sort64(k, v8, cfg), oracle.lsd_sort64(k, v8), f"{dist} 8-byte values")
 
 
-@pytest.mark.parametrize("dist", ["uniform", "and2", "dict16"])
-def test_probed_size(dist):
+@pytest.mark.parametrize("dist,expected", [("uniform", 1), ("and2", 0), ("dict16", 0)])
+def test_probed_size(dist, expected):
     """At 2^25 items the default samples the keys and picks chunks (uniform)
-    or one chain (skewed); the result is the oracle's either way."""
+    or one chain (skewed: digit 0 in 10 % of AND-2 keys, a 16-key
+    dictionary): the decision is the expected one, and the result is the
+    oracle's either way."""
     n = (1 << 25) + 33
     announce(f"64-bit keys probed dist={dist} n={n}")
     k = inputs.keys64("uniform", n, 740) if dist == "uniform" else _dists(n)[dist]
     v = values(n, 4)
+    assert rts.chunk_decision(dev64(k), value_bytes=4) == expected, dist
     check(gpu_sort64(k, v), oracle.lsd_sort64(k, v), dist)
 
 
