@@ -47,7 +47,7 @@ typedef enum rt_status {
     RT_ERR_HIP = 4,           /* a HIP call or kernel launch failed */
     RT_ERR_BUDGET = 5,        /* serving: request larger than the HBM budget */
     RT_ERR_UNSUPPORTED = 6,   /* configuration this build does not provide */
-    RT_ERR_CANCELLED = 7,     /* serving: request dropped at shutdown */
+    RT_ERR_CANCELLED = 7,     /* serving: request cancelled, or dropped at shutdown */
     RT_ERR_TIMEOUT = 8,       /* serving: wait timed out, request still live */
     RT_ERR_NOT_FOUND = 9      /* serving: unknown or already collected ticket */
 } rt_status;
@@ -436,6 +436,22 @@ rt_status rt_server_fetch(rt_server *s, uint64_t ticket, uint32_t *out_keys, uin
 
 /* Release a finished request's server memory without copying it. */
 rt_status rt_server_release(rt_server *s, uint64_t ticket);
+
+/*
+ * Cancel a request.  A queued request ends at once; an admitted one takes no
+ * further pass, gives its memory back to the budget and ends when the step
+ * now being planned has run.  Either way rt_server_wait (or
+ * rt_server_wait_any) then reports it as RT_ERR_CANCELLED.  What a cancelled
+ * request leaves behind: an in-place request's arrays hold its input or the
+ * state after an even number of passes (a permutation of the input, not
+ * sorted); an out-of-place request's outputs are unspecified and its input
+ * untouched; a generated request keeps its memory until rt_server_release.
+ * Returns RT_OK if the request will end cancelled, RT_ERR_INVALID_ARG if it
+ * has finished or its last pass is already under way (its result stands),
+ * RT_ERR_NOT_FOUND for an unknown or collected ticket.  A wait already in
+ * progress on the request returns RT_ERR_CANCELLED when it ends.
+ */
+rt_status rt_server_cancel(rt_server *s, uint64_t ticket);
 
 /*
  * Latency percentiles (us) over completed requests and throughput

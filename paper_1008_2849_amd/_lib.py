@@ -124,6 +124,7 @@ SIGNATURES = {
     "rt_server_wait_any": (ctypes.c_int, [vp, i64, ctypes.POINTER(u64), dblp]),
     "rt_server_fetch": (ctypes.c_int, [vp, u64, vp, vp]),
     "rt_server_release": (ctypes.c_int, [vp, u64]),
+    "rt_server_cancel": (ctypes.c_int, [vp, u64]),
     "rt_server_stats": (ctypes.c_int, [vp, dblp, dblp, dblp]),
     "rt_server_stats_ex": (ctypes.c_int, [vp, dblp, dblp, dblp, ctypes.POINTER(u64), ctypes.POINTER(sz)]),
     "rt_server_replay": (ctypes.c_int, [vp, vp, sz, dblp, dblp]),

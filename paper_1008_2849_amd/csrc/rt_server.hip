@@ -39,6 +39,7 @@
 #include <vector>
 
 #include "rt_common.h"
+#include "rt_sched.h"
 #include "rt_seg_kernels.h"
 
 namespace rt {
@@ -50,80 +51,10 @@ double now_us() {
     return std::chrono::duration<double, std::micro>(Clock::now().time_since_epoch()).count();
 }
 
-constexpr size_t kGranule = 256;
 constexpr size_t kMaxRequestItems = (static_cast<size_t>(1) << 30) - 1;  // 32-bit lookback words
 
-size_t round_up(size_t x) { return (x + kGranule - 1) & ~(kGranule - 1); }
-
-// First-fit allocator over [0, size) with coalescing of free ranges.
-class Arena {
-   public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = round_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = round_up(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-   private:
-    std::map<size_t, size_t> free_;
-};
-
-enum State { kQueued, kActive, kDone };
-
-struct Request {
-    uint64_t id = 0;
-    size_t n = 0;
-    bool generated = false;
-    bool with_values = false;
-    rt_gen_params gen{};
-    uint32_t *k = nullptr, *v = nullptr;    // input, then the sorted result
-    // out-of-place caller requests: the input, copied into k/v when the
-    // request is admitted (NULL: sorted in place)
-    const uint32_t *in_k = nullptr, *in_v = nullptr;
-    uint32_t *tk = nullptr, *tv = nullptr;  // temporaries
-    size_t data_off = 0, data_bytes = 0;    // arena: generated input/result
-    size_t tmp_off = 0, tmp_bytes = 0;      // arena: temporaries
-    State state = kQueued;
-    rt_status status = RT_OK;
-    std::string error;  // detail of a failed request
-    uint32_t pass = 0;  // next pass (tiled requests)
-    uint32_t row = 0;   // histogram / prefix-sum row
-    bool fresh = true;  // histograms not built yet
-    bool collected = false;  // reported by a wait
-    double t_submit = 0, t_done = 0;
-};
-
-// Sorted whole in LDS (in its first step) rather than tiled.
-bool is_small(const Request &r, uint32_t lds_max) { return r.n <= lds_max; }
+using sched::Request;
+using sched::round_up;
 
 // One generated request of a step: its arrays and stream parameters.
 struct GenDesc {
@@ -214,12 +145,14 @@ constexpr int kRing = 8;  // most steps in flight (ring slots)
 
 // Host side of one step in flight: its pinned staging (step block, then the
 // generated-request descriptors, then the header words read back), the
-// event that marks its end, and the requests it touched / finishes.
+// event that marks its end, the scheduler's plan of it, and a failure to
+// enqueue it.
 struct StepSlot {
     char *host = nullptr;
     hipEvent_t done = nullptr;
-    std::vector<Request *> members;
-    std::vector<Request *> finishing;
+    sched::Step step;
+    rt_status enqueue_status = RT_OK;
+    std::string enqueue_error;
 };
 
 struct rt_server {
@@ -228,8 +161,6 @@ struct rt_server {
     hipStream_t io = nullptr;      // fetch copies
     char *arena = nullptr;
     size_t arena_bytes = 0;
-    Arena alloc;
-    size_t used = 0, peak = 0;
     uint32_t max_active = 0;
     rt::SegClassTable classes{};  // whole-in-LDS size classes, fixed at creation
     Meta meta{};
@@ -239,84 +170,37 @@ struct rt_server {
     int ring_head = 0;   // oldest step in flight
     int ring_count = 0;  // steps in flight
 
-    std::mutex mu;
+    std::mutex mu;  // guards sched, stop and the ring bookkeeping
     std::condition_variable cv_work, cv_done;
-    std::deque<Request *> queue;
-    std::deque<uint64_t> finished;  // tickets in completion order, for rt_server_wait_any
-    uint64_t uncollected = 0;       // requests submitted and not yet reported by a wait
-    std::vector<Request *> active;
-    std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
-    std::vector<uint32_t> free_rows;
-    uint64_t next_id = 1;
+    std::unique_ptr<sched::Scheduler> sched;
     bool stop = false;
     std::thread thr;
-
-    std::vector<double> latencies;
-    double first_submit = -1, last_done = 0;
-    uint64_t items_done = 0;
-    uint64_t steps = 0;
 };
 
 namespace {
-
-size_t footprint(const rt_server *s, const Request &r) {
-    const size_t arr = round_up(r.n * sizeof(uint32_t));
-    const size_t per = r.with_values ? 2 : 1;
-    return (r.generated ? per * arr : 0) + (is_small(r, s->classes.lds_max()) ? 0 : per * arr);
-}
 
 size_t slot_bytes(const Meta &m, uint32_t max_active) {
     return m.block_bytes + sizeof(GenDesc) * max_active + 2 * 256;
 }
 
-// Admit queued requests in arrival order while memory and slots last.
-// Returns the requests admitted (mu held by the caller).
-std::vector<Request *> admit(rt_server *s) {
-    std::vector<Request *> fresh;
-    while (!s->queue.empty() && s->active.size() < s->max_active) {
-        Request *r = s->queue.front();
+// Points newly admitted requests at their arena ranges (mu held).
+void place(rt_server *s, const std::vector<Request *> &admitted) {
+    for (Request *r : admitted) {
         const size_t arr = round_up(r->n * sizeof(uint32_t));
-        const size_t per = r->with_values ? 2 : 1;
-        size_t data_off = 0, tmp_off = 0;
-        const size_t data_bytes = r->generated ? per * arr : 0;
-        const size_t tmp_bytes = is_small(*r, s->classes.lds_max()) ? 0 : per * arr;
-        if (data_bytes && !s->alloc.alloc(data_bytes, &data_off)) break;
-        if (tmp_bytes && !s->alloc.alloc(tmp_bytes, &tmp_off)) {
-            if (data_bytes) s->alloc.release(data_off, data_bytes);
-            break;
-        }
-        s->queue.pop_front();
-        r->data_off = data_off;
-        r->data_bytes = data_bytes;
-        r->tmp_off = tmp_off;
-        r->tmp_bytes = tmp_bytes;
         if (r->generated) {
-            r->k = reinterpret_cast<uint32_t *>(s->arena + data_off);
-            r->v = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + data_off + arr) : nullptr;
+            r->k = reinterpret_cast<uint32_t *>(s->arena + r->data_off);
+            r->v = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + r->data_off + arr) : nullptr;
         }
-        if (tmp_bytes) {
-            r->tk = reinterpret_cast<uint32_t *>(s->arena + tmp_off);
-            r->tv = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + tmp_off + arr) : nullptr;
+        if (r->tmp_bytes) {
+            r->tk = reinterpret_cast<uint32_t *>(s->arena + r->tmp_off);
+            r->tv = r->with_values ? reinterpret_cast<uint32_t *>(s->arena + r->tmp_off + arr) : nullptr;
         }
-        s->used += data_bytes + tmp_bytes;
-        s->peak = std::max(s->peak, s->used);
-        r->row = s->free_rows.back();
-        s->free_rows.pop_back();
-        r->state = kActive;
-        r->pass = 0;
-        r->fresh = true;
-        s->active.push_back(r);
-        fresh.push_back(r);
     }
-    return fresh;
 }
 
-// Builds the next step in ring slot `slot` from the active requests (mu
-// held): descriptors and work lists on the host, then the bookkeeping that
-// does not depend on the device finishing -- every request advances one
-// pass, and the temporaries and rows of the requests this step finishes go
-// back to the pools at once (later steps run after this one on the same
-// stream, so reusing them is ordered behind its kernels).
+// Builds the next step in ring slot `slot` (mu held): the scheduler plans
+// it (one pass, or the whole sort in LDS, for every admitted request), then
+// its descriptors and work lists are written to the slot's pinned block.
 struct StepPlan {
     size_t tiles = 0;
     uint32_t fresh_tiled = 0, tiled = 0, small[kSegMaxClasses] = {0, 0, 0, 0}, gen = 0, gen_chunks = 0;
@@ -328,6 +212,9 @@ struct StepPlan {
 StepPlan build_step(rt_server *s, StepSlot &slot) {
     const Meta &m = s->meta;
     StepPlan P;
+    s->sched->plan(slot.step);
+    slot.enqueue_status = RT_OK;
+    slot.enqueue_error.clear();
     char *hb = slot.host;
     memset(hb, 0, m.block_bytes);
     SegHeader *hp = reinterpret_cast<SegHeader *>(hb + m.hdr_pass);
@@ -337,11 +224,10 @@ StepPlan build_step(rt_server *s, StepSlot &slot) {
     uint32_t *hlist = reinterpret_cast<uint32_t *>(hb + m.list_hist) + static_cast<size_t>(kSegLarge) * s->max_active;
     GenDesc *gen = reinterpret_cast<GenDesc *>(hb + m.block_bytes);
     const uint32_t stride = s->max_active;
-    slot.members.assign(s->active.begin(), s->active.end());
-    slot.finishing.clear();
-    std::vector<Request *> still;
-    for (size_t i = 0; i < s->active.size(); ++i) {
-        Request *r = s->active[i];
+    const auto &items = slot.step.items;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const sched::StepItem &it = items[i];
+        const Request *r = it.r;
         P.vals = P.vals || r->with_values;
         SegDesc &d = descs[i];
         d.k = r->k;
@@ -349,13 +235,13 @@ StepPlan build_step(rt_server *s, StepSlot &slot) {
         d.tk = r->tk;
         d.tv = r->with_values ? r->tv : nullptr;
         d.n = static_cast<uint32_t>(r->n);
-        d.pass = r->pass;
+        d.pass = it.pass;
         d.row = r->row;
-        if (r->fresh && r->in_k != nullptr && r->n > 0) {
+        if (it.fresh && r->in_k != nullptr && r->n > 0) {
             P.copies.emplace_back(r->k, r->in_k, r->n * sizeof(uint32_t));
             if (r->with_values) P.copies.emplace_back(r->v, r->in_v, r->n * sizeof(uint32_t));
         }
-        if (r->fresh && r->generated && r->n > 0) {
+        if (it.fresh && r->generated && r->n > 0) {
             GenDesc &g = gen[P.gen++];
             g.k = r->k;
             g.v = r->with_values ? r->v : nullptr;
@@ -368,40 +254,23 @@ StepPlan build_step(rt_server *s, StepSlot &slot) {
             memcpy(g.g.dictionary, r->gen.dictionary, sizeof g.g.dictionary);
             memcpy(g.g.thresholds, r->gen.thresholds, sizeof g.g.thresholds);
         }
-        bool finished;
-        if (r->n < 2) {
-            finished = true;
-        } else if (is_small(*r, s->classes.lds_max())) {
+        if (r->n < 2) continue;  // nothing to sort
+        if (it.small) {
             int c = static_cast<int>(s->classes.count) - 1;
             for (int q = c; q >= 0; --q)
                 if (r->n <= s->classes.cls[q].max_n) c = q;
             lists[static_cast<size_t>(c) * stride + hp->count[c]++] = static_cast<uint32_t>(i);
             ++P.small[c];
-            finished = true;  // small requests are sorted whole in their first step
         } else {
             lists[static_cast<size_t>(kSegLarge) * stride + hp->count[kSegLarge]++] = static_cast<uint32_t>(i);
             ++P.tiled;
             P.tiles += (r->n + kSegTile - 1) / kSegTile;
-            if (r->fresh) {
+            if (it.fresh) {
                 hlist[hh->count[kSegLarge]++] = static_cast<uint32_t>(i);
                 ++P.fresh_tiled;
             }
-            finished = r->pass + 1 == kSegPasses;
         }
-        r->fresh = false;
-        if (!finished) {
-            ++r->pass;
-            still.push_back(r);
-            continue;
-        }
-        slot.finishing.push_back(r);
-        if (r->tmp_bytes) s->alloc.release(r->tmp_off, r->tmp_bytes);
-        s->used -= r->tmp_bytes;
-        r->tmp_bytes = 0;
-        s->free_rows.push_back(r->row);
     }
-    s->active.swap(still);
-    ++s->steps;
     return P;
 }
 
@@ -492,22 +361,23 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
 }
 
 // Retires the oldest step in flight once its event has fired (waiting for
-// it when `block`): the requests it finished become done.  Returns whether
-// a step was retired.
+// it when `block`): the scheduler completes it, with the failure of the
+// step if its enqueue, the device or a lookback word reported one.  Returns
+// whether a step was retired.
 bool retire_oldest(rt_server *s, bool block) {
     if (s->ring_count == 0) return false;
     StepSlot &slot = s->ring[s->ring_head];
     hipError_t e = block ? hipEventSynchronize(slot.done) : hipEventQuery(slot.done);
     if (e == hipErrorNotReady) return false;
     const char *rb = slot.host + s->meta.block_bytes + sizeof(GenDesc) * s->max_active;
-    uint32_t err = 0;
-    rt_status status = RT_OK;
-    std::string why;
-    if (e != hipSuccess) {
+    rt_status status = slot.enqueue_status;
+    std::string why = slot.enqueue_error;
+    if (status == RT_OK && e != hipSuccess) {
         status = RT_ERR_HIP;
         why = std::string("server: step failed: ") + hipGetErrorString(e);
-    } else {
-        err = reinterpret_cast<const SegHeader *>(rb)->error | reinterpret_cast<const SegHeader *>(rb + 256)->error;
+    } else if (status == RT_OK) {
+        const uint32_t err =
+            reinterpret_cast<const SegHeader *>(rb)->error | reinterpret_cast<const SegHeader *>(rb + 256)->error;
         if (err) {
             status = RT_ERR_HIP;
             char buf[96];
@@ -516,24 +386,7 @@ bool retire_oldest(rt_server *s, bool block) {
         }
     }
     std::lock_guard<std::mutex> lk(s->mu);
-    if (status != RT_OK)  // every request the step touched carries the failure
-        for (Request *r : slot.members) {
-            r->status = status;
-            r->error = why;
-        }
-    const double t = now_us();
-    for (Request *r : slot.finishing) {
-        r->state = kDone;
-        r->t_done = t;
-        s->finished.push_back(r->id);
-        if (r->status == RT_OK) {
-            s->latencies.push_back(t - r->t_submit);
-            s->items_done += r->n;
-            s->last_done = t;
-        }
-    }
-    slot.members.clear();
-    slot.finishing.clear();
+    s->sched->complete(slot.step, status, why, now_us());
     s->ring_head = (s->ring_head + 1) % kRing;
     --s->ring_count;
     s->cv_done.notify_all();
@@ -542,6 +395,7 @@ bool retire_oldest(rt_server *s, bool block) {
 
 void scheduler(rt_server *s) {
     (void)hipSetDevice(s->device);
+    std::vector<Request *> admitted;
     for (;;) {
         while (retire_oldest(s, false)) {
         }
@@ -552,16 +406,18 @@ void scheduler(rt_server *s) {
             retire_oldest(s, true);
             continue;
         }
-        admit(s);
-        if (s->active.empty()) {
+        admitted.clear();
+        s->sched->admit(&admitted);
+        place(s, admitted);
+        if (!s->sched->has_active()) {
             if (s->ring_count) {
                 lk.unlock();
                 retire_oldest(s, true);
                 continue;
             }
             // idle, or the head of the queue waits for memory to be released
-            if (s->queue.empty())
-                s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            if (!s->sched->has_queued())
+                s->cv_work.wait(lk, [&] { return s->stop || s->sched->has_queued() || s->sched->has_active(); });
             else
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
             continue;
@@ -572,14 +428,12 @@ void scheduler(rt_server *s) {
         lk.unlock();
         const rt_status st = enqueue_step(s, slot, P);
         if (st != RT_OK) {
-            // nothing of this step may have run: fail what it touched once
-            // the stream has drained, and retire it
+            // part of this step may have been enqueued: let the stream drain,
+            // then retire it as failed (its requests end or leave; the
+            // others are untouched)
             (void)hipStreamSynchronize(s->stream);
-            std::lock_guard<std::mutex> g(s->mu);
-            for (Request *r : slot.members) {
-                r->status = st;
-                r->error = last_error();
-            }
+            slot.enqueue_status = st;
+            slot.enqueue_error = last_error();
             (void)hipEventRecord(slot.done, s->stream);
         }
     }
@@ -591,18 +445,10 @@ rt_status enqueue(rt_server *s, std::unique_ptr<Request> r, uint64_t *ticket) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return set_error(RT_ERR_CANCELLED, "server: stopping");
     // one value layout per server (the step kernels are instantiated for it)
-    for (auto &kv : s->all) {
-        if (kv.second->with_values != r->with_values)
-            return set_error(RT_ERR_INVALID_ARG, "server: mixing keys-only and key/value requests is not supported");
-        break;
-    }
-    r->id = s->next_id++;
-    r->t_submit = now_us();
-    if (s->first_submit < 0) s->first_submit = r->t_submit;
-    *ticket = r->id;
-    ++s->uncollected;
-    s->queue.push_back(r.get());
-    s->all[r->id] = std::move(r);
+    const int held = s->sched->held_layout();
+    if (held >= 0 && held != (r->with_values ? 1 : 0))
+        return set_error(RT_ERR_INVALID_ARG, "server: mixing keys-only and key/value requests is not supported");
+    *ticket = s->sched->submit(std::move(r), now_us());
     s->cv_work.notify_one();
     return RT_OK;
 }
@@ -652,9 +498,7 @@ extern "C" rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_acti
         const int v = atoi(d);
         if (v >= 1 && v <= kRing) s->depth = v;
     }
-    s->alloc.reset(s->arena_bytes);
-    s->free_rows.reserve(max_active);
-    for (uint32_t i = max_active; i-- > 0;) s->free_rows.push_back(i);
+    s->sched.reset(new sched::Scheduler(s->arena_bytes, max_active, s->classes.lds_max(), kSegPasses));
     rt_server *raw = s.release();
     raw->thr = std::thread(scheduler, raw);
     *out = raw;
@@ -663,13 +507,9 @@ extern "C" rt_status rt_server_create(size_t hbm_budget_bytes, uint32_t max_acti
 
 static rt_status check_request_size(rt_server *s, size_t n, bool generated, bool with_values, const char *what) {
     if (n > kMaxRequestItems) return set_error(RT_ERR_TOO_LARGE, "%s: n = %zu, the server limit is 2^30 - 1", what, n);
-    Request probe;
-    probe.n = n;
-    probe.generated = generated;
-    probe.with_values = with_values;
-    if (footprint(s, probe) > s->arena_bytes)
-        return set_error(RT_ERR_BUDGET, "%s: %zu bytes needed, the budget is %zu", what, footprint(s, probe),
-                         s->arena_bytes);
+    const size_t need = s->sched->footprint(n, generated, with_values);
+    if (need > s->arena_bytes)
+        return set_error(RT_ERR_BUDGET, "%s: %zu bytes needed, the budget is %zu", what, need, s->arena_bytes);
     return RT_OK;
 }
 
@@ -731,88 +571,73 @@ extern "C" rt_status rt_server_submit_generated(rt_server *s, const rt_gen_param
 
 // Reports a finished request (mu held): its latency and status; a request
 // with nothing left to fetch is dropped.
-static rt_status collect(rt_server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it,
-                         double *latency_us, const char *what) {
-    Request *r = it->second.get();
-    const uint64_t id = r->id;
-    if (!r->collected) --s->uncollected;
-    r->collected = true;
-    if (latency_us) *latency_us = r->t_done - r->t_submit;
-    const rt_status st = r->status;
-    const std::string why = r->error;
-    if (!r->generated) s->all.erase(it);
-    if (st != RT_OK) return set_error(st, "%s: request %llu failed: %s", what, (unsigned long long)id, why.c_str());
+static rt_status collect(rt_server *s, uint64_t ticket, double *latency_us, const char *what) {
+    std::string why;
+    const rt_status st = s->sched->collect(ticket, latency_us, &why);
+    if (st == RT_ERR_NOT_FOUND)
+        return set_error(st, "%s: request %llu was collected by another wait", what, (unsigned long long)ticket);
+    if (st != RT_OK)
+        return set_error(st, "%s: request %llu failed: %s", what, (unsigned long long)ticket, why.c_str());
     return RT_OK;
 }
 
 extern "C" rt_status rt_server_wait(rt_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us) {
     if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_wait: server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    if (s->all.find(ticket) == s->all.end())
+    const Request *r = s->sched->find(ticket);
+    if (r == nullptr || r->collected)
         return set_error(RT_ERR_NOT_FOUND, "rt_server_wait: no request %llu", (unsigned long long)ticket);
-    // look the request up afresh: the table may rehash, and another waiter
-    // on the same ticket may have taken it, while this one sleeps
-    auto done = [&] {
-        auto f = s->all.find(ticket);
-        return f == s->all.end() || f->second->state == kDone;
-    };
+    // looked up afresh on every wake-up: another waiter on the same ticket
+    // may have taken it meanwhile
+    auto done = [&] { return s->sched->done(ticket); };
     if (timeout_us < 0) {
         s->cv_done.wait(lk, done);
     } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
         return set_error(RT_ERR_TIMEOUT, "rt_server_wait: request %llu still running", (unsigned long long)ticket);
     }
-    auto it = s->all.find(ticket);
-    if (it == s->all.end())
-        return set_error(RT_ERR_NOT_FOUND, "rt_server_wait: request %llu was collected by another wait",
-                         (unsigned long long)ticket);
-    return collect(s, it, latency_us, "rt_server_wait");
+    return collect(s, ticket, latency_us, "rt_server_wait");
 }
 
 extern "C" rt_status rt_server_wait_any(rt_server *s, int64_t timeout_us, uint64_t *ticket, double *latency_us) {
     if (s == nullptr || ticket == nullptr)
         return set_error(RT_ERR_INVALID_ARG, "rt_server_wait_any: NULL argument");
     std::unique_lock<std::mutex> lk(s->mu);
-    // drops finished tickets that a wait by ticket has already collected
-    auto ready = [&] {
-        while (!s->finished.empty()) {
-            auto f = s->all.find(s->finished.front());
-            if (f != s->all.end() && !f->second->collected) return true;
-            s->finished.pop_front();
-        }
-        return false;
-    };
+    auto ready = [&] { return s->sched->next_finished() != 0; };
     if (!ready()) {
-        if (s->uncollected == 0) return set_error(RT_ERR_NOT_FOUND, "rt_server_wait_any: no request outstanding");
+        if (s->sched->uncollected() == 0)
+            return set_error(RT_ERR_NOT_FOUND, "rt_server_wait_any: no request outstanding");
         if (timeout_us < 0) {
             s->cv_done.wait(lk, ready);
         } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
             return set_error(RT_ERR_TIMEOUT, "rt_server_wait_any: nothing finished");
         }
     }
-    *ticket = s->finished.front();
-    s->finished.pop_front();
-    return collect(s, s->all.find(*ticket), latency_us, "rt_server_wait_any");
+    *ticket = s->sched->next_finished();
+    return collect(s, *ticket, latency_us, "rt_server_wait_any");
 }
 
-static rt_status drop_generated(rt_server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it) {
-    Request *r = it->second.get();
-    if (r->data_bytes) {
-        s->alloc.release(r->data_off, r->data_bytes);
-        s->used -= r->data_bytes;
-    }
-    s->all.erase(it);
-    s->cv_work.notify_one();  // memory came free
+extern "C" rt_status rt_server_cancel(rt_server *s, uint64_t ticket) {
+    if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_cancel: server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const rt_status st = s->sched->cancel(ticket, now_us());
+    if (st == RT_ERR_NOT_FOUND)
+        return set_error(st, "rt_server_cancel: no request %llu", (unsigned long long)ticket);
+    if (st == RT_ERR_INVALID_ARG)
+        return set_error(st, "rt_server_cancel: request %llu has finished or its last pass is under way",
+                         (unsigned long long)ticket);
+    s->cv_done.notify_all();  // a queued request has ended
+    s->cv_work.notify_one();  // an admitted one leaves at the next step
     return RT_OK;
 }
 
 extern "C" rt_status rt_server_fetch(rt_server *s, uint64_t ticket, uint32_t *out_keys, uint32_t *out_vals) {
     if (s == nullptr || out_keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_fetch: NULL argument");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(ticket);
-    if (it == s->all.end() || !it->second->generated)
+    const Request *r = s->sched->find(ticket);
+    if (r == nullptr || !r->generated)
         return set_error(RT_ERR_NOT_FOUND, "rt_server_fetch: no generated request %llu", (unsigned long long)ticket);
-    Request *r = it->second.get();
-    if (r->state != kDone) return set_error(RT_ERR_INVALID_ARG, "rt_server_fetch: request %llu not finished", (unsigned long long)ticket);
+    if (r->state != sched::kDone)
+        return set_error(RT_ERR_INVALID_ARG, "rt_server_fetch: request %llu not finished", (unsigned long long)ticket);
     if (r->status != RT_OK) return set_error(r->status, "rt_server_fetch: request %llu failed", (unsigned long long)ticket);
     const size_t bytes = r->n * sizeof(uint32_t);
     hipError_t e = hipSuccess;
@@ -822,38 +647,31 @@ extern "C" rt_status rt_server_fetch(rt_server *s, uint64_t ticket, uint32_t *ou
         if (e == hipSuccess) e = hipStreamSynchronize(s->io);
     }
     if (e != hipSuccess) return set_error(RT_ERR_HIP, "rt_server_fetch: %s", hipGetErrorString(e));
-    return drop_generated(s, it);
+    (void)s->sched->release(ticket);
+    s->cv_work.notify_one();  // memory came free
+    return RT_OK;
 }
 
 extern "C" rt_status rt_server_release(rt_server *s, uint64_t ticket) {
     if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_release: server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(ticket);
-    if (it == s->all.end()) return set_error(RT_ERR_NOT_FOUND, "rt_server_release: no request %llu", (unsigned long long)ticket);
-    if (it->second->state != kDone)
-        return set_error(RT_ERR_INVALID_ARG, "rt_server_release: request %llu not finished", (unsigned long long)ticket);
-    return drop_generated(s, it);
+    const rt_status st = s->sched->release(ticket);
+    if (st == RT_ERR_NOT_FOUND)
+        return set_error(st, "rt_server_release: no request %llu", (unsigned long long)ticket);
+    if (st != RT_OK)
+        return set_error(st, "rt_server_release: request %llu not finished", (unsigned long long)ticket);
+    s->cv_work.notify_one();  // memory came free
+    return RT_OK;
 }
 
 extern "C" rt_status rt_server_stats_ex(rt_server *s, double *p50_us, double *p99_us, double *gkeys_per_s,
                                         uint64_t *completed, size_t *peak_bytes) {
     if (s == nullptr) return set_error(RT_ERR_INVALID_ARG, "rt_server_stats: server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    std::vector<double> l = s->latencies;
-    std::sort(l.begin(), l.end());
-    auto pct = [&](double q) {
-        if (l.empty()) return 0.0;
-        size_t i = static_cast<size_t>(q * static_cast<double>(l.size() - 1) + 0.5);
-        return l[std::min(i, l.size() - 1)];
-    };
-    if (p50_us) *p50_us = pct(0.50);
-    if (p99_us) *p99_us = pct(0.99);
-    if (gkeys_per_s) {
-        const double span = s->last_done - s->first_submit;
-        *gkeys_per_s = (span > 0 && s->items_done) ? static_cast<double>(s->items_done) / span / 1e3 : 0.0;
-    }
-    if (completed) *completed = l.size();
-    if (peak_bytes) *peak_bytes = s->peak;
+    double per_us = 0;
+    s->sched->stats(p50_us, p99_us, &per_us, completed);
+    if (gkeys_per_s) *gkeys_per_s = per_us / 1e3;
+    if (peak_bytes) *peak_bytes = s->sched->peak();
     return RT_OK;
 }
 
@@ -872,7 +690,8 @@ extern "C" rt_status rt_server_replay(rt_server *s, const rt_replay_request *req
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->uncollected) return set_error(RT_ERR_INVALID_ARG, "rt_server_replay: requests are outstanding");
+        if (s->sched->uncollected())
+            return set_error(RT_ERR_INVALID_ARG, "rt_server_replay: requests are outstanding");
     }
     if (span_us) *span_us = 0.0;
     if (count == 0) return RT_OK;
@@ -939,8 +758,7 @@ extern "C" rt_status rt_server_replay(rt_server *s, const rt_replay_request *req
             double done = 0;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                auto it = s->all.find(ticket);
-                if (it != s->all.end()) done = it->second->t_done;
+                if (const Request *r = s->sched->find(ticket)) done = r->t_done;
             }
             latency_us[i] = done - (t0 + reqs[i].arrival_us);
             last_done = std::max(last_done, done);
@@ -971,15 +789,7 @@ extern "C" rt_status rt_server_destroy(rt_server *s) {
     (void)hipStreamSynchronize(s->stream);
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        const double t = now_us();
-        for (auto &kv : s->all) {
-            Request *r = kv.second.get();
-            if (r->state != kDone) {
-                r->state = kDone;
-                r->status = RT_ERR_CANCELLED;
-                r->t_done = t;
-            }
-        }
+        s->sched->cancel_all(now_us());
         s->cv_done.notify_all();
     }
     for (int i = 0; i < kRing; ++i) {

@@ -99,6 +99,12 @@ class Server:
     def release(self, ticket: int) -> None:
         check(lib().rt_server_release(self.handle, int(ticket)), "rt_server_release")
 
+    def cancel(self, ticket: int) -> None:
+        """Cancel a request: it takes no further pass and its wait reports
+        RT_ERR_CANCELLED.  Raises RtError (RT_ERR_INVALID_ARG) if it has
+        finished or its last pass is under way."""
+        check(lib().rt_server_cancel(self.handle, int(ticket)), "rt_server_cancel")
+
     def stats(self) -> Tuple[float, float, float, int, int]:
         """(p50 us, p99 us, Gkeys/s, completed requests, peak budgeted bytes)."""
         p50, p99, gk = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -425,6 +425,7 @@ def test_server_argument_errors(so):
     assert so.rt_server_wait_any(None, 0, ctypes.byref(t), None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_fetch(None, 1, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_release(None, 1) == _lib.RT_ERR_INVALID_ARG
+    assert so.rt_server_cancel(None, 1) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_stats(None, None, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_stats_ex(None, None, None, None, None, None) == _lib.RT_ERR_INVALID_ARG
     assert so.rt_server_destroy(None) == _lib.RT_OK

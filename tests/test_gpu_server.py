@@ -11,7 +11,7 @@ import oracle
 from paper_1008_2849_amd import inputs
 from paper_1008_2849_amd.api import gen_params_to_c
 from paper_1008_2849_amd.server import Server
-from paper_1008_2849_amd._lib import RtError, RT_ERR_BUDGET, RT_ERR_NOT_FOUND
+from paper_1008_2849_amd._lib import RtError, RT_ERR_BUDGET, RT_ERR_CANCELLED, RT_ERR_INVALID_ARG, RT_ERR_NOT_FOUND
 from gpu_util import announce, sync, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -135,6 +135,60 @@ def test_budget_admission_waits_and_rejects():
             sync()
             assert np.array_equal(to_host(k), np.sort(inputs.counter_keys(p, n)))
         assert srv.stats()[4] <= 6 << 20
+
+
+def test_cancel_queued_and_admitted_requests():
+    """Cancelled requests end as RT_ERR_CANCELLED and leave their arrays
+    holding a permutation of the input with every key still beside its own
+    value (untouched, or the state after an even number of passes); a
+    cancel that comes too late is refused and that result is the oracle's;
+    every other request is the oracle's, and the server goes on serving.
+    One request is admitted at a time (max_active 1) and the first is 2^26
+    pairs, so the requests behind it are still queued when they are
+    cancelled right after submission."""
+    announce("server cancel")
+    sizes = [1 << 26, 2 << 20, 70_000, 2 << 20, 1000, 2 << 20, 300_001]
+    data = []
+    for i, n in enumerate(sizes):
+        keys = inputs.uniform_keys(n, 60 + i)
+        vals = inputs.index_values(n)
+        data.append((keys, vals, to_dev(keys), to_dev(vals)))
+    sync()
+    with Server(hbm_budget_bytes=600 << 20, max_active=1) as srv:
+        cases = [[srv.submit(kd, vd), keys, vals, kd, vd, None] for keys, vals, kd, vd in data]
+        for c in cases[1::2] + [cases[0]]:   # queued ones, then the admitted first one
+            try:
+                srv.cancel(c[0])
+                c[5] = "cancelled"
+            except RtError as e:
+                assert e.status == RT_ERR_INVALID_ARG   # finished, or its last pass under way
+                c[5] = "too late"
+        assert sum(c[5] == "cancelled" for c in cases[1::2]) >= 1
+        late_keys, late_vals = inputs.uniform_keys(123_457, 69), inputs.index_values(123_457)
+        late_kd, late_vd = to_dev(late_keys), to_dev(late_vals)   # kept alive until its wait
+        late = srv.submit(late_kd, late_vd)
+        for t, keys, vals, kd, vd, what in cases:
+            try:
+                srv.wait(t)
+                status = 0
+            except RtError as e:
+                status = e.status
+            hk, hv = to_host(kd), to_host(vd)
+            if what == "cancelled":
+                assert status == RT_ERR_CANCELLED, (len(keys), status)
+                counts = np.bincount(hv, minlength=len(vals))    # values are the indices
+                assert len(counts) == len(vals) and (counts == 1).all(), "a permutation of the input"
+                assert np.array_equal(hk, keys[hv]), "every key beside its own value"
+            else:
+                assert status == 0, (len(keys), status)
+                wk, wv = oracle.lsd_sort(keys, vals)
+                assert np.array_equal(hk, wk) and np.array_equal(hv, wv)
+        srv.wait(late)
+        wk, wv = oracle.lsd_sort(late_keys, late_vals)
+        assert np.array_equal(to_host(late_kd), wk) and np.array_equal(to_host(late_vd), wv)
+        with pytest.raises(RtError) as e:
+            srv.cancel(late)                     # collected
+        assert e.value.status == RT_ERR_NOT_FOUND
 
 
 def test_keys_only_server():
