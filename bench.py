@@ -532,10 +532,12 @@ def bench_serving_closed(rts, inputs, inflight, seconds, warm_s, single_gkeys, b
         t, _ = srv.wait_any()
         submit_time.pop(t, None)
         srv.release(t)
+    peak = srv.stats()[4]
     srv.close()
     gk = items / span / 1e9
     return {"mode": "closed_loop", "inflight": inflight, "achieved_Gkeys/s": round(gk, 3),
             "frac_of_single_array": round(gk / single_gkeys, 4),
+            "budget_GiB": budget_gib, "peak_budgeted_GiB": round(peak / 2**30, 3),
             "p50_ms": round(float(np.percentile(lats, 50)), 3), "p99_ms": round(float(np.percentile(lats, 99)), 3),
             "requests_measured": len(lats), "seconds": seconds,
             "sampled_parity": {"checked": checked, "wrong": wrong}, "failures": ["parity"] if wrong else []}
@@ -624,6 +626,9 @@ def main() -> int:
     ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
                     "of single-array throughput), replayed open loop; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-tight-gib", type=int, default=2,
+                    help="budget (GiB) of a closed-loop leg with 256 requests in flight that presses admission "
+                         "against memory (0 to skip)")
     ap.add_argument("--serve-inflight", default="64,256",
                     help="comma list of closed-loop request counts kept in flight (empty to skip)")
     args = ap.parse_args()
@@ -921,7 +926,7 @@ def main() -> int:
         table1 = bench_write_combining(rts, inputs, dev, K, W)
         log(f"table1: {table1}")
     serving = []
-    if (args.serve_loads or args.serve_inflight) and args.workload == "pairs_256m_uniform":
+    if (args.serve_loads or args.serve_inflight or args.serve_tight_gib) and args.workload == "pairs_256m_uniform":
         for load in (float(x) for x in args.serve_loads.split(",") if x):
             log(f"serving at load {load}")
             serving.append(bench_serving(rts, inputs, load, args.serve_seconds, 1.0, gkeys))
@@ -929,6 +934,11 @@ def main() -> int:
         for inflight in (int(x) for x in args.serve_inflight.split(",") if x):
             log(f"serving closed loop, {inflight} in flight")
             serving.append(bench_serving_closed(rts, inputs, inflight, args.serve_seconds, 1.0, gkeys))
+            log(f"serving: {serving[-1]}")
+        if args.serve_tight_gib > 0:
+            log(f"serving closed loop, 256 in flight, {args.serve_tight_gib} GiB budget")
+            serving.append(bench_serving_closed(rts, inputs, 256, args.serve_seconds, 1.0, gkeys,
+                                                budget_gib=args.serve_tight_gib))
             log(f"serving: {serving[-1]}")
 
     line = {
