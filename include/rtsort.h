@@ -189,12 +189,14 @@ rt_status rt_sort_pairs64(uint64_t *keys, uint32_t *vals, size_t n, hipStream_t 
 /*
  * Explicit form.  value_bytes: 0 (keys only, vals ignored), 4 or 8 bytes per
  * item; vals is then a device array of n such values, aligned to
- * value_bytes.  cfg (NULL = built-in default, eight 8-bit digits in 8K-item
- * tiles): digit_bits must sum to 64, each 1..RT_MAX_DIGIT_BITS; tile shapes
- * built are 1024x8 and 512x16 for digits of up to 8 bits and 512x8 for
- * wider ones (correct, but several times slower than 8-bit digits); flags:
- * RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN, RT_FLAG_CHUNKS (XCD chunks as for 32-bit
- * keys), RT_FLAG_VALIDATE (anything else is RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
+ * value_bytes.  cfg (NULL = built-in default: eight 8-bit digits, in
+ * 16K-item tiles from 2^24 items (12K with 8-byte values) and 8K-item tiles
+ * below): digit_bits must sum to 64, each 1..RT_MAX_DIGIT_BITS; tile shapes
+ * built are 1024x16, 1024x12, 1024x8 and 512x16 for digits of up to 8 bits
+ * and 512x8 for wider ones (correct, but several times slower than 8-bit
+ * digits); flags: RT_FLAG_NO_SKIP, RT_FLAG_ONE_CHAIN, RT_FLAG_CHUNKS (XCD
+ * chunks as for 32-bit keys), RT_FLAG_VALIDATE (anything else is
+ * RT_ERR_UNSUPPORTED).  workspace: at least rt_workspace_bytes64() bytes,
  * 256-byte aligned, or NULL for the library's per-stream cache; with a
  * caller workspace the call only enqueues kernels.  Errors and stream
  * behaviour as for rt_sort_pairs_ex.

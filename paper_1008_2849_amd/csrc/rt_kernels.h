@@ -822,13 +822,14 @@ struct TileJob {
 // counters (then offsets) with a 64-word scratch row per wave that absorbs
 // the counter writes of non-leader lanes, each digit's output slot, the
 // block scan's wave sums, and the claimed tile (broadcast by thread 0).
-template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool FUSED = false>
+template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool FUSED = false, bool SEQ = false>
 struct OnesweepLds {
     static constexpr int RADIX = 1 << BITS;
     static constexpr int WAVES = BLOCK / 64;
     static constexpr int TILE = BLOCK * IPT;
+    static_assert(!SEQ || (VALS && sizeof(V) <= sizeof(K)), "sequential staging puts the values in the key stage");
     K stage_k[TILE];
-    V stage_v[VALS ? TILE : 1];
+    V stage_v[(VALS && !SEQ) ? TILE : 1];
     uint32_t whist[WAVES * RADIX + WAVES * 64];
     uint32_t gbase[RADIX];
     uint32_t wsum[WAVES];
@@ -889,10 +890,15 @@ __device__ __forceinline__ void rank_items(const K (&key)[IPT], V (&val)[VALS ? 
 // registers to its output slot, so a wave's stores scatter over the digit
 // runs.  This is the pass without write-combining (the paper's "VM only"
 // counterpart), kept to measure what the staging buys.
+//
+// SEQ stages the keys, scatters them, then stages and scatters the values
+// through the same LDS: a tile whose keys and values would not fit the LDS
+// together (16K items of 64-bit keys with 4- or 8-byte values) keeps its
+// size at the cost of two more barriers.
 template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE,
-          bool SMALL, bool FUSED = false>
+          bool SMALL, bool FUSED = false, bool SEQ = false>
 __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
-                                              OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED> &lds,
+                                              OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED, SEQ> &lds,
                                               S *__restrict__ status, uint32_t *__restrict__ error_flag) {
     constexpr int RADIX = 1 << BITS;
     constexpr int WAVES = BLOCK / 64;
@@ -990,7 +996,8 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
             if (!full && wslot0 + j * 64 >= valid) d = RADIX - 1;
             const uint32_t r = wh[d] + rnk[j];
             lds.stage_k[r] = key[j];
-            if constexpr (VALS) lds.stage_v[r] = val[j];
+            if constexpr (VALS && !SEQ) lds.stage_v[r] = val[j];
+            if constexpr (SEQ) rnk[j] = r;  // the value's stage slot, after the keys have left
         }
     }
 
@@ -1014,7 +1021,29 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
     // ever turning into a store outside the array.  A full tile needs no
     // per-slot guard, so the LDS reads of all slots are issued together.
     const uint32_t last = job.bound - 1u;
-    if (STAGE && full) {
+    if constexpr (STAGE && SEQ) {
+        static_assert(!FUSED && !NT, "sequential staging: plain stores, no fused counts");
+        // keys first, keeping each slot's output position; then the values
+        // through the same stage, to the same positions
+        uint32_t sp[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = j * BLOCK + tid;
+            const K k = lds.stage_k[i];
+            sp[j] = min(lds.gbase[key_digit(k, shift, width)] + i, last);
+            if (full || i < valid) store_t<NT, K>(gptr<K, SMALL>(job.dst_k, sp[j]), k);
+        }
+        __syncthreads();  // every key out of the stage
+        V *stage_v = reinterpret_cast<V *>(lds.stage_k);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) stage_v[rnk[j]] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t i = j * BLOCK + tid;
+            if (full || i < valid) store_t<NT, V>(gptr<V, SMALL>(job.dst_v, sp[j]), stage_v[i]);
+        }
+    } else if (STAGE && full) {
         K sk[IPT];
         uint32_t sp[IPT];
 #pragma unroll
@@ -1075,8 +1104,8 @@ __device__ __forceinline__ void onesweep_tile(const TileJob<K, V> &job,
 // blocks; surplus blocks find every chunk exhausted and exit.  The plan's
 // pointers are reinterpreted as K keys and V values.
 template <int BITS, int BLOCK, int IPT, typename K, typename V, bool VALS, bool NT, typename S, bool STAGE,
-          bool FUSED = false>
-__device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED> &lds,
+          bool FUSED = false, bool SEQ = false>
+__device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V, VALS, FUSED, SEQ> &lds,
                                               const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                               S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                               uint32_t *__restrict__ error_flag, uint32_t *__restrict__ hist = nullptr) {
@@ -1110,7 +1139,7 @@ __device__ __forceinline__ void onesweep_pass(OnesweepLds<BITS, BLOCK, IPT, K, V
     job.next_hist = FUSED ? hist + (pass + 1) * kMaxRadix : nullptr;
     job.next_shift = FUSED ? plan->pass[pass + 1].shift : 0u;
     job.next_width = FUSED ? plan->pass[pass + 1].width : 0u;
-    onesweep_tile<BITS, BLOCK, IPT, K, V, VALS, NT, S, STAGE, SMALL, FUSED>(job, lds, status, error_flag);
+    onesweep_tile<BITS, BLOCK, IPT, K, V, VALS, NT, S, STAGE, SMALL, FUSED, SEQ>(job, lds, status, error_flag);
 }
 
 // The pass over 32-bit keys (with 32-bit values when VALS).  FUSED: the

@@ -16,6 +16,8 @@
 // slower than both 8K shapes for every value width.)
 #define RT64_FOR_EACH_SHAPE(X) \
     X(8, 1024, 8)              \
+    X(8, 1024, 12)             \
+    X(8, 1024, 16)             \
     X(8, 512, 16)              \
     X(11, 512, 8)
 
@@ -35,23 +37,34 @@ bool shape64_supported(int bits_class, int block, int ipt) {
 
 int bits_class_of(uint32_t width) { return width <= 8 ? 8 : 11; }
 
-// Built-in default: eight 8-bit digits in 8K-item tiles; 1024x8 for 4-byte
-// values, else 512x16, whose LDS footprint without values (74 KiB) lets two
-// blocks share a CU.  Measured at 2^28 items: keys only 27.5 vs 22.0
-// Gkeys/s, 4-byte values 17.3 vs 17.0, 8-byte values 14.4 vs 13.7 (the
-// chosen shape first).  11-bit digits are 4-5x slower: a 4K-item tile
-// publishes 2048 lookback words, more status traffic than data.
-void default_config64(uint32_t value_words, rt_config *c) {
+// Built-in default: eight 8-bit digits.  From 2^24 items, 16K-item tiles
+// (1024x16; with 8-byte values 1024x12), whose keys and values are staged
+// one after the other when they do not fit the LDS together.  Measured at
+// 2^28 items, pass times against the 8K-item shapes below: keys only 0.94
+// vs 1.05-1.09 ms, 4-byte values 1.29-1.32 vs 1.55 ms, 8-byte values
+// 1.67 vs 1.80-1.83 ms.  Below 2^24 items, 8K-item tiles (a grid of at
+// least a few tiles per CU): 1024x8 for 4-byte values, else 512x16, whose
+// LDS footprint without values (74 KiB) lets two blocks share a CU.
+// 11-bit digits are 4-5x slower: a 4K-item tile publishes 2048 lookback
+// words, more status traffic than data.
+constexpr size_t kWideTileMinItems = static_cast<size_t>(1) << 24;
+
+void default_config64(uint32_t value_words, size_t n, rt_config *c) {
     memset(c, 0, sizeof *c);
     c->num_passes = 8;
     for (int p = 0; p < 8; ++p) c->digit_bits[p] = 8;
-    c->block_threads = value_words == 1 ? 1024 : 512;
-    c->items_per_thread = value_words == 1 ? 8 : 16;
+    if (n >= kWideTileMinItems) {
+        c->block_threads = 1024;
+        c->items_per_thread = value_words == 2 ? 12 : 16;
+    } else {
+        c->block_threads = value_words == 1 ? 1024 : 512;
+        c->items_per_thread = value_words == 1 ? 8 : 16;
+    }
 }
 
-rt_status resolve64(const rt_config *cfg, uint32_t value_words, Resolved *out) {
+rt_status resolve64(const rt_config *cfg, uint32_t value_words, size_t n, Resolved *out) {
     rt_config c;
-    default_config64(value_words, &c);
+    default_config64(value_words, n, &c);
     if (cfg != nullptr && cfg->num_passes != 0) {
         c.num_passes = cfg->num_passes;
         memcpy(c.digit_bits, cfg->digit_bits, sizeof c.digit_bits);
@@ -373,7 +386,7 @@ extern "C" size_t rt_workspace_bytes64(size_t n, uint32_t value_bytes, const rt_
     if (n < 2 || n >= (static_cast<size_t>(1) << 32)) return 0;
     if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8) return 0;
     Resolved r;
-    if (resolve64(cfg, value_bytes / 4, &r) != RT_OK) return 0;
+    if (resolve64(cfg, value_bytes / 4, n, &r) != RT_OK) return 0;
     chunk_mode64(n, &r);
     return make_layout64(n, r, value_bytes / 4).total;
 }
@@ -384,7 +397,7 @@ extern "C" rt_status rt_sort64_ex(uint64_t *keys, void *vals, uint32_t value_byt
     if (s != RT_OK || n < 2) return s;
     const uint32_t vw = value_bytes / 4;
     Resolved r;
-    s = resolve64(cfg, vw, &r);
+    s = resolve64(cfg, vw, n, &r);
     if (s == RT_OK) chunk_mode64(n, &r);
     if (s != RT_OK) return s;
     const Layout64 L = make_layout64(n, r, vw);
@@ -420,7 +433,7 @@ extern "C" rt_status rt_chunk_decision64(const uint64_t *keys, size_t n, uint32_
     if (value_bytes != 0 && value_bytes != 4 && value_bytes != 8)
         return set_error(RT_ERR_INVALID_ARG, "rt_chunk_decision64: value_bytes %u is not 0, 4 or 8", value_bytes);
     Resolved r;
-    rt_status s = resolve64(cfg, value_bytes / 4, &r);
+    rt_status s = resolve64(cfg, value_bytes / 4, n, &r);
     if (s != RT_OK) return s;
     chunk_mode64(n, &r);
     prof_begin(stream);

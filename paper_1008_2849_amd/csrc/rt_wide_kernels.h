@@ -168,9 +168,12 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep64(const SortPlan *__restrict
                                                       S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                                       uint32_t *__restrict__ error_flag) {
     typedef typename ValWord<VW>::type V;
-    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint64_t, V, (VW > 0)> lds;
-    onesweep_pass<BITS, BLOCK, IPT, uint64_t, V, (VW > 0), false, S, true>(lds, plan, pass, n, status,
-                                                                           chunk_counter, error_flag);
+    // a tile whose keys and values do not fit the LDS together stages the
+    // keys, then the values through the same space
+    constexpr bool SEQ = VW > 0 && static_cast<size_t>(BLOCK) * IPT * (sizeof(uint64_t) + sizeof(V)) > 128 * 1024;
+    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint64_t, V, (VW > 0), false, SEQ> lds;
+    onesweep_pass<BITS, BLOCK, IPT, uint64_t, V, (VW > 0), false, S, true, false, SEQ>(lds, plan, pass, n, status,
+                                                                                       chunk_counter, error_flag);
 }
 
 // Moves the result of a sort with exactly one executed pass from the

@@ -1,6 +1,7 @@
 """Sorts past 2^30 items, where the lookback words become 64-bit and element
-offsets no longer fit 32-bit byte offsets: the single-array sort, the
-MSD-first sort (whose segmented passes switch too) and 64-bit keys.
+offsets no longer fit 32-bit byte offsets: the single-array sort (8-bit and
+11/11/10-bit digits), the MSD-first sort (whose segmented passes switch
+too) and 64-bit keys.
 
 At this size the oracle is checked on the output's defining properties, on
 the device: keys ascend (unsigned), the values are a permutation of the
@@ -44,6 +45,24 @@ def test_pairs_past_2_30(path):
         rts.sort_pairs(k, v)
     else:
         rts.sort_msd_first(k, v, validate=True)
+    sync()
+    _check_pairs(k0, k, v)
+    del k, v, k0
+    torch.cuda.empty_cache()
+
+
+def test_eleven_bit_digits_past_2_30():
+    """11/11/10-bit digits (three passes, 2048-word lookback rows) past 2^30
+    items, where those rows' words are 64-bit: the properties of the stable
+    sort, and no lookback gave up (RT_FLAG_VALIDATE)."""
+    import torch
+    from paper_1008_2849_amd.api import Config, FLAG_VALIDATE
+    announce(f"11/11/10 pairs n={N}")
+    k = torch.empty(N, dtype=torch.int32, device="cuda")
+    v = torch.empty(N, dtype=torch.int32, device="cuda")
+    rts.generate(k, v, inputs.counter_params(inputs.DIST_UNIFORM, 63, 0))
+    k0 = k.clone()
+    rts.sort_ex(k, v, Config((11, 11, 10), 512, 16, FLAG_VALIDATE))
     sync()
     _check_pairs(k0, k, v)
     del k, v, k0

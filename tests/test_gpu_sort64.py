@@ -141,7 +141,8 @@ def test_probed_size(dist, expected):
 
 
 CONFIGS = [((8,) * 8, 1024, 8), ((8,) * 8, 512, 16), ((11, 11, 11, 11, 10, 10), 512, 8),
-           ((10, 9, 9, 9, 9, 9, 9), 512, 8), ((8, 8, 8, 8, 8, 8, 8, 8), 1024, 8)]
+           ((10, 9, 9, 9, 9, 9, 9), 512, 8), ((8, 8, 8, 8, 8, 8, 8, 8), 1024, 8),
+           ((8,) * 8, 1024, 16), ((8,) * 8, 1024, 12)]
 
 
 @pytest.mark.parametrize("flags", [0, FLAG_NO_SKIP])
@@ -152,7 +153,7 @@ def test_configs(ci, flags):
     announce(f"64-bit keys config {widths} {block}x{ipt} flags={flags} n={n}")
     cfg = Config(widths, block, ipt, flags)
     for dist, k in [("uniform", inputs.keys64("uniform", n, 720 + ci)), ("small", inputs.keys64("small", n, 730))]:
-        for vb in (4, 8):
+        for vb in (0, 4, 8):
             v = values(n, vb)
             check(gpu_sort64(k, v, cfg), oracle.lsd_sort64(k, v, widths), f"{dist} {widths} vb={vb}")
 
