@@ -448,9 +448,11 @@ rt_status rt_server_release(rt_server *s, uint64_t ticket);
  * state after an even number of passes (a permutation of the input, not
  * sorted); an out-of-place request's outputs are unspecified and its input
  * untouched; a generated request keeps its memory until rt_server_release.
- * Returns RT_OK if the request will end cancelled, RT_ERR_INVALID_ARG if it
- * has finished or its last pass is already under way (its result stands),
- * RT_ERR_NOT_FOUND for an unknown or collected ticket.  A wait already in
+ * Returns RT_OK if the request will take no further pass (it then ends as
+ * RT_ERR_CANCELLED, or with the error of a step that had already failed
+ * it), RT_ERR_INVALID_ARG if it has finished or its last pass is already
+ * under way (its result stands), RT_ERR_NOT_FOUND for an unknown or
+ * collected ticket.  A wait already in
  * progress on the request returns RT_ERR_CANCELLED when it ends.
  */
 rt_status rt_server_cancel(rt_server *s, uint64_t ticket);

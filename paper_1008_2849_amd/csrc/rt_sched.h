@@ -277,7 +277,8 @@ class Scheduler {
     }
 
     // Cancels a request: a queued one ends at once (RT_ERR_CANCELLED), an
-    // admitted one leaves at the next plan and ends when that step has run.
+    // admitted one leaves at the next plan and ends when that step has run
+    // (as RT_ERR_CANCELLED, unless a failed step already marked it).
     // RT_ERR_INVALID_ARG when its last step is already planned or it has
     // finished (its result stands); RT_ERR_NOT_FOUND for an unknown or
     // collected ticket.

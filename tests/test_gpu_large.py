@@ -1,7 +1,7 @@
 """Sorts past 2^30 items, where the lookback words become 64-bit and element
 offsets no longer fit 32-bit byte offsets: the single-array sort (8-bit and
 11/11/10-bit digits), the MSD-first sort (whose segmented passes switch
-too) and 64-bit keys.
+too) and 64-bit keys, with and without values.
 
 At this size the oracle is checked on the output's defining properties, on
 the device: keys ascend (unsigned), the values are a permutation of the
@@ -66,6 +66,30 @@ def test_eleven_bit_digits_past_2_30():
     sync()
     _check_pairs(k0, k, v)
     del k, v, k0
+    torch.cuda.empty_cache()
+
+
+def test_pairs64_past_2_30():
+    """64-bit keys with 4-byte values past 2^30 items: 16K-item tiles whose
+    keys and values are staged one after the other, 64-bit lookback words,
+    64-bit element offsets.  Checked by the stable sort's properties."""
+    import torch
+    announce(f"64-bit keys with values n={N}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(64)
+    # few distinct high bits: long runs of equal keys exercise stability
+    k = torch.randint(0, 1 << 40, (N,), dtype=torch.int64, device="cuda", generator=g) << 20
+    v = torch.arange(N, dtype=torch.int32, device="cuda")
+    k0 = k.clone()
+    rts.sort64_ex(k, v)
+    sync()
+    assert bool((k[1:] >= k[:-1]).all()), "keys ascend"  # all keys below 2^60: signed order is unsigned order
+    vl = v.to(torch.int64)
+    assert bool((torch.bincount(vl, minlength=N) == 1).all()), "values are a permutation"
+    assert bool(torch.equal(k0[vl], k)), "each key arrives with its own index"
+    eq = k[1:] == k[:-1]
+    assert bool((vl[1:][eq] > vl[:-1][eq]).all()), "equal keys keep index order"
+    del k, v, k0, vl, eq
     torch.cuda.empty_cache()
 
 

@@ -321,6 +321,20 @@ def test_failed_step_isolation(mk):
     assert s.stats()["completed"] == 1 and s.stats()["used"] == 0
 
 
+def test_cancel_after_a_failed_step(mk):
+    """A request a failed step has marked can still be cancelled (it takes no
+    further pass either way) and ends with the step's failure."""
+    s = mk(256 * MiB)
+    t = s.submit(1 << 20, now=0)
+    s.step(now=1)
+    s.step(now=2, status=RT_ERR_HIP)
+    assert s.query(t)["state"] == ACTIVE and s.query(t)["status"] == RT_ERR_HIP
+    assert s.cancel(t, now=3) == RT_OK
+    items, fin = s.step(now=4)
+    assert items == {} and fin == [t]
+    assert s.collect(t)[0] == RT_ERR_HIP
+
+
 def test_failed_final_step(mk):
     """A request whose last step fails ends failed, not OK."""
     s = mk(64 * MiB)
