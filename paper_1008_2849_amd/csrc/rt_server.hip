@@ -10,8 +10,11 @@
 // that step, and its first pass runs in it.  A request of more than 16K
 // items is done after four steps, a smaller one after one.
 //
-// The scheduler thread builds a step on the host (descriptors, work lists),
-// uploads it from pinned memory, enqueues its kernels on the server's
+// The policy (admission, which request runs which pass, completion,
+// cancellation, failures) is the host-only scheduler of rt_sched.h, called
+// under the server's lock.  This file is its device side: the scheduler
+// thread turns each planned step into descriptors and work lists, uploads
+// them from pinned memory, enqueues the step's kernels on the server's
 // stream and records an event; a request is reported done when the event
 // of its last step has fired.  Up to `depth` steps may be in flight
 // (RT_SERVER_DEPTH, default 1: requests that arrive during a step then join
@@ -27,15 +30,12 @@
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
-#include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <tuple>
-#include <string>
 #include <unordered_map>
-#include <tuple>
 #include <vector>
 
 #include "rt_common.h"
