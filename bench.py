@@ -621,6 +621,8 @@ def main() -> int:
                     help="further single-array workloads timed and checked against the oracle (empty to skip)")
     ap.add_argument("--no-xcd-compare", action="store_true",
                     help="skip re-timing the headline sort on one lookback chain per pass")
+    ap.add_argument("--no-widths-compare", action="store_true",
+                    help="skip re-timing the headline sort with 11/11/10-bit digits")
     ap.add_argument("--no-fused-compare", action="store_true",
                     help="skip timing the fused next-digit histogram against the upfront read")
     ap.add_argument("--serve-loads", default="0.5,0.6,0.7,0.75", help="comma list of offered loads (fraction "
@@ -866,6 +868,39 @@ def main() -> int:
                           "0-2 count the next digit while they write")
         log(f"fused histogram: {fused}")
 
+    # the same sort with 11/11/10-bit digits (three passes instead of four),
+    # the alternative the autotuner also weighs: a few sorts, same input,
+    # output compared with the 8-bit sort's
+    widths = None
+    if not args.no_widths_compare and args.workload == "pairs_256m_uniform":
+        ref = (ko.clone(), None if vo is None else vo.clone())
+        wcfg = rts.Config((11, 11, 10), 512, 16, 0)
+        wk = min(K, 5)
+        for k, v in slots[:wk + 1]:
+            k.copy_(k0)
+            if v is not None:
+                v.copy_(v0)
+        wws = torch.empty(rts.workspace_bytes(n, vals_on, wcfg), dtype=torch.uint8, device=dev)
+        rts.sort_ex(slots[0][0], slots[0][1], wcfg, wws)
+        torch.cuda.synchronize()
+        rts.profile_start(max_marks=32 * wk + 32)
+        t0 = time.perf_counter()
+        for i in range(1, wk + 1):
+            rts.sort_ex(slots[i][0], slots[i][1], wcfg, wws)
+        torch.cuda.synchronize()
+        w_ms = 1e3 * (time.perf_counter() - t0) / wk
+        wm = rts.profile_stop(capacity=32 * wk + 32)
+        last = slots[wk]
+        same = bool(torch.equal(last[0], ref[0])) and (ref[1] is None or bool(torch.equal(last[1], ref[1])))
+        wpass = [ms for kind, ms in wm if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+        widths = {"digit_bits": [11, 11, 10], "shape": "512x16", "ms_per_sort": round(w_ms, 4),
+                  "Gkeys/s": round(n / (w_ms / 1e3) / 1e9, 3),
+                  "pass_ms": round(float(np.mean(wpass)), 4) if wpass else None,
+                  "against_8x4_ms_per_sort": round(ms_per_step, 4), "output_equal": same,
+                  "note": "three passes of 11, 11 and 10 bits; 2048-bin counters and lookback rows per tile"}
+        del wws, ref
+        log(f"11/11/10 digits: {widths}")
+
     digest = kernel_source_digest()
     counters = counters_from_profiles(digest)
     traffic = counters["traffic"]
@@ -978,6 +1013,7 @@ def main() -> int:
         "parity_properties_ok": props,
         "xcd_chunks": xcd,
         "fused_histogram": fused,
+        "digit_widths_11_11_10": widths,
         "transfer_inclusive": pcie,
         "msd_first": msd_first,
         "sort64": sort64,
@@ -994,6 +1030,7 @@ def main() -> int:
     ok = ok and all(not s.get("failures") for s in serving)
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (fused is None or all(fused[x]["output_equal"] for x in ("upfront", "fused")))
+    ok = ok and (widths is None or widths["output_equal"])
     ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
     ok = ok and (sort64 is None or sort64["parity_properties_ok"])
     ok = ok and (table1 is None or all(r["outputs_equal"] for k, r in table1.items() if "outputs_equal" in r))
