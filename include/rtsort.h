@@ -103,11 +103,17 @@ typedef enum rt_status {
  * (Section 4: digits are processed from the least significant one upward);
  * the widths must sum to 32 and each lies in 1..RT_MAX_DIGIT_BITS.
  * Every decomposition gives the same result; they differ in speed.
+ * Tile shapes built (block_threads x items_per_thread): 256x16, 512x16,
+ * 1024x8, 1024x12, 1024x16 and 512x32 for digits of up to 8 bits, and
+ * 256x16, 512x8 and 512x16 for wider ones.  512x32 stages the keys, then the
+ * values, through one LDS stage so that two blocks share a CU; with
+ * RT_FLAG_NT_STORES, RT_FLAG_DIRECT_SCATTER or RT_FLAG_FUSED_HISTOGRAM it is
+ * RT_ERR_UNSUPPORTED.
  */
 typedef struct rt_config {
     uint32_t num_passes;                 /* 0 = tuned default */
     uint32_t digit_bits[RT_MAX_PASSES];  /* used when num_passes > 0 */
-    uint32_t block_threads;              /* 0 = tuned (256 or 512) */
+    uint32_t block_threads;              /* 0 = tuned */
     uint32_t items_per_thread;           /* 0 = tuned */
     uint32_t flags;                      /* RT_FLAG_* */
 } rt_config;

@@ -37,7 +37,7 @@ from .api import Config, FLAG_NT_STORES
 
 # (bits class, threads, items per thread) the library compiles; keep in step
 # with RT_FOR_EACH_SHAPE in csrc/rt_common.h
-SHAPES = {8: [(256, 16), (512, 16), (1024, 8), (1024, 12), (1024, 16)],
+SHAPES = {8: [(256, 16), (512, 16), (1024, 8), (1024, 12), (1024, 16), (512, 32)],
           11: [(256, 16), (512, 8), (512, 16)]}
 WIDTHS = [(8, 8, 8, 8), (11, 11, 10)]
 SIZES = [1 << 16, 1 << 20, 1 << 24, 1 << 28]

@@ -7,14 +7,15 @@
 #include "rt_internal.h"
 
 // Tile shapes (digit bits class, threads per block, items per thread) for
-// which onesweep kernels are compiled.  Every shape exists for both digit
-// classes so that any mix of digit widths can use any shape.
+// which onesweep kernels are compiled.  512 x 32 (16K items, two blocks per
+// CU) is built for the staged pass with plain stores only.
 #define RT_FOR_EACH_SHAPE(X) \
     X(8, 256, 16)            \
     X(8, 512, 16)            \
     X(8, 1024, 8)            \
     X(8, 1024, 12)           \
     X(8, 1024, 16)           \
+    X(8, 512, 32)            \
     X(11, 256, 16)           \
     X(11, 512, 8)            \
     X(11, 512, 16)

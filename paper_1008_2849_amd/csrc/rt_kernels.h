@@ -1149,9 +1149,13 @@ template <int BITS, int BLOCK, int IPT, bool VALS, bool NT, typename S, bool STA
 __global__ __launch_bounds__(BLOCK) void k_onesweep(const SortPlan *__restrict__ plan, int pass, uint32_t n,
                                                     S *__restrict__ status, uint32_t *__restrict__ chunk_counter,
                                                     uint32_t *__restrict__ error_flag, uint32_t *__restrict__ hist) {
-    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, FUSED> lds;
-    onesweep_pass<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, NT, S, STAGE, FUSED>(lds, plan, pass, n, status,
-                                                                                  chunk_counter, error_flag, hist);
+    // 512 x 32 tiles stage keys, then values, through one 64 KiB stage, so
+    // that two blocks share a CU (their plain staged pass only)
+    constexpr bool SEQ = VALS && BLOCK == 512 && IPT == 32;
+    static_assert(!SEQ || (STAGE && !NT && !FUSED), "512 x 32 tiles: the staged pass with plain stores only");
+    __shared__ OnesweepLds<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, FUSED, SEQ> lds;
+    onesweep_pass<BITS, BLOCK, IPT, uint32_t, uint32_t, VALS, NT, S, STAGE, FUSED, SEQ>(lds, plan, pass, n, status,
+                                                                                       chunk_counter, error_flag, hist);
 }
 
 // ---------------------------------------------------------------------------

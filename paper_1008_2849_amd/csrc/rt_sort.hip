@@ -151,6 +151,9 @@ rt_status resolve_config(const rt_config *cfg, size_t n, int with_values, Resolv
     }
     if ((r.flags & RT_FLAG_ONE_CHAIN) && (r.flags & RT_FLAG_CHUNKS))
         return set_error(RT_ERR_INVALID_ARG, "RT_FLAG_ONE_CHAIN and RT_FLAG_CHUNKS exclude each other");
+    if (r.block == 512 && r.ipt == 32 &&
+        (r.flags & (RT_FLAG_NT_STORES | RT_FLAG_DIRECT_SCATTER | RT_FLAG_FUSED_HISTOGRAM)))
+        return set_error(RT_ERR_UNSUPPORTED, "512 x 32 tiles are built for the staged pass with plain stores only");
     // per-chunk counts need digits of at most 8 bits (kChunkRadix); below
     // kChunkMinItems the sample would cost more than chunks can save
     const bool forced = (r.flags & RT_FLAG_CHUNKS) != 0;
@@ -310,7 +313,10 @@ static void launch_pass_shape(const Layout &L, bool vals, uint32_t flags, hipStr
 #define RT_OS(V, NTV, S, STG, FU)                                                                                \
     hipLaunchKernelGGL((k_onesweep<BITS, BLOCK, IPT, V, NTV, S, STG, FU>), grid, block, 0, stream, plan, pass, n, \
                        static_cast<S *>(status), chunk_ctr, err, fused_hist)
-    if (fused_hist != nullptr) {  // resolve_config: staged, plain stores, digits of at most 8 bits
+    if constexpr (BLOCK == 512 && IPT == 32) {  // resolve_config: the plain staged pass only
+        if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, true, false); else RT_OS(false, false, uint64_t, true, false); }
+        else               { if (vals) RT_OS(true, false, uint32_t, true, false); else RT_OS(false, false, uint32_t, true, false); }
+    } else if (fused_hist != nullptr) {  // resolve_config: staged, plain stores, digits of at most 8 bits
         if constexpr (BITS == 8) {
             if (L.wide_status) { if (vals) RT_OS(true, false, uint64_t, true, true); else RT_OS(false, false, uint64_t, true, true); }
             else               { if (vals) RT_OS(true, false, uint32_t, true, true); else RT_OS(false, false, uint32_t, true, true); }

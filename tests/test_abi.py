@@ -160,6 +160,23 @@ def test_chunk_decision_argument_errors(so):
     assert so.rt_chunk_decision64(fake, 1 << 25, 4, ctypes.byref(both), mode, None) == _lib.RT_ERR_INVALID_ARG
 
 
+def test_two_blocks_per_cu_shape_flags(so):
+    """512 x 32 tiles (keys and values staged one after the other) are built
+    for the plain staged pass: with it, non-temporal stores, the direct
+    scatter and the fused histogram are refused before any launch."""
+    fake_k, fake_v = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
+    c = _lib.RtConfig()
+    c.num_passes = 4
+    for i in range(4):
+        c.digit_bits[i] = 8
+    c.block_threads, c.items_per_thread = 512, 32
+    assert so.rt_workspace_bytes(1 << 20, 1, ctypes.byref(c)) > 0
+    for flag in (_lib.RT_FLAG_NT_STORES, _lib.RT_FLAG_DIRECT_SCATTER, _lib.RT_FLAG_FUSED_HISTOGRAM):
+        c.flags = flag
+        assert so.rt_sort_pairs_ex(fake_k, fake_v, 1000, ctypes.byref(c), None, 0, None) == _lib.RT_ERR_UNSUPPORTED
+        assert so.rt_workspace_bytes(1000, 1, ctypes.byref(c)) == 0
+
+
 def test_fused_histogram_flag(so):
     """RT_FLAG_FUSED_HISTOGRAM resolves for 8-bit digits (and then never
     needs the second temporary: every pass runs), and is refused with wider

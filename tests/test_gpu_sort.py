@@ -103,7 +103,7 @@ def test_distributions_keys(dist):
 
 WIDTHS = [(8, 8, 8, 8), (11, 11, 10), (10, 11, 11), (4,) * 8, (6, 6, 6, 6, 8), (11, 8, 8, 5),
           (8, 8, 8, 4, 4), (11, 11, 6, 4)]
-SHAPES = [(256, 16), (512, 16), (1024, 8), (1024, 16)]
+SHAPES = [(256, 16), (512, 16), (1024, 8), (1024, 16), (512, 32)]
 SHAPES_WIDE = {(256, 16), (512, 8), (512, 16)}  # shapes built for 9..11-bit digits
 
 
@@ -123,6 +123,24 @@ def test_configs(widths, shape):
         assert e.value.status == 6
         return
     assert_same(gpu_sort(k, v, cfg), oracle.lsd_sort(k, v, widths), f"{widths} {shape}")
+
+
+@pytest.mark.parametrize("n", [2, 1000, 16383, 16384, 16385, 5 * 16384 + 77, 1_000_003, (1 << 25) + 77])
+def test_two_blocks_per_cu_shape(n):
+    """512 x 32 tiles (16K items; the values staged after the keys leave,
+    so two blocks share a CU): pairs and keys only, uniform and skewed keys,
+    forced XCD chunks, one chain and the probed default, each the oracle's."""
+    announce(f"512x32 n={n}")
+    v = inputs.index_values(n)
+    flag_sets = (0, FLAG_CHUNKS, FLAG_ONE_CHAIN | FLAG_NO_SKIP) if n < (1 << 25) else (0,)
+    for dist in ("uniform", "and4", "top_a5"):
+        k = inputs.uniform_keys(n, 95) if dist == "uniform" else _dist_cases(n)[dist]
+        want_kv = oracle.lsd_sort(k, v)
+        want_k = want_kv[0]
+        for flags in flag_sets:
+            cfg = Config((8, 8, 8, 8), 512, 32, flags)
+            assert_same(gpu_sort(k, v, cfg), want_kv, f"pairs {dist} flags={flags}")
+            assert_same(gpu_sort(k, None, cfg), (want_k, None), f"keys {dist} flags={flags}")
 
 
 @pytest.mark.parametrize("flags", [FLAG_NO_SKIP, FLAG_NT_STORES, FLAG_NO_SKIP | FLAG_NT_STORES,
@@ -248,7 +266,7 @@ def test_chunk_decision_fixed_cases():
 
 
 def test_probed_keys_only_tuned_shape():
-    """Keys only at 2^25 items with the tuned shape (1024 x 12 tiles, two
+    """Keys only at 2^25 items with the tuned shape (512 x 32 tiles, two
     blocks per CU) in XCD chunks: the oracle's result."""
     rts.load_default_tuning()
     n = (1 << 25) + 5
