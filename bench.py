@@ -279,44 +279,64 @@ def bench_batched(rts, inputs, dev, K, W, single_gkeys):
 
 
 def bench_msd_first(rts, dev, k0, v0, slots, K, W, single_gkeys, ref_k, ref_v):
-    """The MSD-first sort (one partition pass on the top digit, then LSD
-    passes over the three lower digits of each of the 256 buckets) on the
-    same workload, each call on its own re-staged copy; its last output must
-    equal the LSD sort's bit for bit."""
+    """The MSD-first sort on the same workload, with two MSD levels (the
+    default at this size: partition passes on digits 3 and 2, then digits 0
+    and 1 of each of the 65536 sub-buckets whole in LDS) and with one (one
+    partition pass, then LSD passes over the three lower digits of each of
+    the 256 buckets); each call on its own re-staged copy, and each form's
+    last output must equal the LSD sort's bit for bit."""
     import numpy as np
     import torch
-    from paper_1008_2849_amd._lib import RT_KIND_HISTOGRAM, RT_KIND_MSD_PASS, RT_KIND_PASS
+    from paper_1008_2849_amd._lib import RT_KIND_HISTOGRAM, RT_KIND_MSD_PASS, RT_KIND_PASS, RT_KIND_SEG_SMALL
     n = k0.numel()
     ws = torch.empty(rts.msd_first_workspace_bytes(n, v0 is not None), dtype=torch.uint8, device=dev)
-    for k, v in slots:
-        k.copy_(k0)
-        if v is not None:
-            v.copy_(v0)
-    for i in range(W):
-        rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws)
-    torch.cuda.synchronize()
-    rts.profile_start(max_marks=32 * K + 32)
-    t0 = time.perf_counter()
-    for i in range(W, W + K):
-        rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    calls = split_calls(rts.profile_stop(capacity=32 * K + 32))
-    part = [ms for c in calls for kind, ms in c[1] if kind == RT_KIND_MSD_PASS]
-    local = [ms for c in calls for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
-    hists = [[ms for kind, ms in c[1] if kind == RT_KIND_HISTOGRAM] for c in calls]
-    ko, vo = slots[W + K - 1]
-    same = bool(torch.equal(ko, ref_k)) and (vo is None or bool(torch.equal(vo, ref_v)))
-    gk = n / (wall / K) / 1e9
+    out = {}
+    for label, levels in (("two_levels", 2), ("one_level", 1)):
+        for k, v in slots:
+            k.copy_(k0)
+            if v is not None:
+                v.copy_(v0)
+        for i in range(W):
+            rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws, levels=levels)
+        torch.cuda.synchronize()
+        rts.profile_start(max_marks=32 * K + 32)
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            rts.sort_msd_first(slots[i][0], slots[i][1], workspace=ws, levels=levels)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        calls = split_calls(rts.profile_stop(capacity=32 * K + 32))
+        part = [ms for c in calls for kind, ms in c[1] if kind == RT_KIND_MSD_PASS]
+        hists = [[ms for kind, ms in c[1] if kind == RT_KIND_HISTOGRAM] for c in calls]
+        ko, vo = slots[W + K - 1]
+        same = bool(torch.equal(ko, ref_k)) and (vo is None or bool(torch.equal(vo, ref_v)))
+        gk = n / (wall / K) / 1e9
+        row = {"Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
+               "frac_of_single_array": round(gk / single_gkeys, 4),
+               "partition_pass_ms": round(float(np.mean(part)), 4) if part else None,
+               "msd_histogram_ms": round(float(np.mean([h[0] for h in hists if h])), 4) if hists else None,
+               "bucket_histogram_ms": round(float(np.mean([h[1] for h in hists if len(h) > 1])), 4)
+               if hists else None,
+               "matches_lsd_sort": same}
+        if levels == 2:
+            # per call: the digit-2 pass inside the buckets is the largest
+            # pass mark; the sub-buckets' tiled passes (none for uniform
+            # keys) are the others
+            second = [max(ms for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8) for c in calls]
+            local = [sum(ms for kind, ms in c[1] if kind == RT_KIND_SEG_SMALL) for c in calls]
+            row["second_partition_pass_ms"] = round(float(np.mean(second)), 4)
+            row["sub_bucket_lds_sort_ms"] = round(float(np.mean(local)), 4)
+        else:
+            local = [ms for c in calls for kind, ms in c[1] if RT_KIND_PASS <= kind < RT_KIND_PASS + 8]
+            row["local_pass_ms"] = round(float(np.mean(local)), 4) if local else None
+        out[label] = row
     del ws
-    return {"Gkeys/s": round(gk, 3), "ms_per_call": round(1e3 * wall / K, 4),
-            "frac_of_single_array": round(gk / single_gkeys, 4),
-            "partition_pass_ms": round(float(np.mean(part)), 4) if part else None,
-            "local_pass_ms": round(float(np.mean(local)), 4) if local else None,
-            "msd_histogram_ms": round(float(np.mean([h[0] for h in hists if h])), 4) if hists else None,
-            "bucket_histogram_ms": round(float(np.mean([h[1] for h in hists if len(h) > 1])), 4)
-            if hists else None,
-            "matches_lsd_sort": same}
+    res = dict(out["two_levels"])
+    res["levels"] = 2
+    res["one_level"] = out["one_level"]
+    res["note"] = ("default at this size: two MSD levels (digit 3, then digit 2 inside each bucket), then digits "
+                   "0 and 1 of each sub-bucket whole in LDS; one_level: one partition, then three local LSD passes")
+    return res
 
 
 def bench_sort64(rts, inputs, dev, K, W):
@@ -1045,7 +1065,7 @@ def main() -> int:
     ok = ok and (pcie is None or pcie["matches_device_sort"])
     ok = ok and (fused is None or all(fused[x]["output_equal"] for x in ("upfront", "fused")))
     ok = ok and (widths is None or widths["output_equal"])
-    ok = ok and (msd_first is None or msd_first["matches_lsd_sort"])
+    ok = ok and (msd_first is None or (msd_first["matches_lsd_sort"] and msd_first["one_level"]["matches_lsd_sort"]))
     ok = ok and (sort64 is None or sort64["parity_properties_ok"])
     ok = ok and (table1 is None or all(r["outputs_equal"] for k, r in table1.items() if "outputs_equal" in r))
     return 0 if ok else 3

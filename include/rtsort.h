@@ -96,6 +96,10 @@ typedef enum rt_status {
  * RT_FLAG_DIRECT_SCATTER or RT_FLAG_NT_STORES (RT_ERR_UNSUPPORTED).
  * Single-array 32-bit sorts only. */
 #define RT_FLAG_FUSED_HISTOGRAM 0x40u
+/* rt_sort_msd_first only: the number of MSD levels (see there).  By default
+ * the call picks by n; these force one or two.  They exclude each other. */
+#define RT_FLAG_MSD_ONE_LEVEL 0x80u
+#define RT_FLAG_MSD_TWO_LEVELS 0x100u
 
 /*
  * Sort configuration.  Zero-initialised fields mean "tuned default".
@@ -272,15 +276,22 @@ size_t rt_msd_first_workspace_bytes(size_t n, int with_values);
  * one counting-sort pass on the most significant 8-bit digit moves the
  * items into a temporary array of the workspace, partitioned into 256 MSD
  * buckets whose starts are the exclusive prefix sum of the MSD histogram;
- * then each bucket is sorted on its own by LSD passes over digits 0, 1
- * and 2, the last of which writes the caller's arrays.  The result equals
- * rt_sort_pairs_ex's bit for bit (a stable sort has one result); passes are never
- * skipped, so keys whose top byte is constant still pay the partition pass.
- * Buckets of at most 16384 items are sorted whole in LDS.
+ * then each bucket is sorted on its own.  With one MSD level, by LSD passes
+ * over digits 0, 1 and 2, the last of which writes the caller's arrays.
+ * With two, a second partition pass on digit 2 inside every bucket writes
+ * the caller's arrays, cut into 65536 sub-buckets (the buckets' digit-2
+ * counts give their bounds), and each sub-bucket is then sorted on digits 0
+ * and 1: whole in LDS when it holds at most 16384 items (the LDS is the
+ * fast memory the buckets are sized for, as the paper sizes them for the
+ * cache), else by two tiled passes.  The result equals rt_sort_pairs_ex's
+ * bit for bit (a stable sort has one result); passes are never skipped, so
+ * keys whose top byte is constant still pay the partition pass.  Buckets
+ * and sub-buckets of at most 16384 items are sorted whole in LDS.
  *
  * keys, vals: device u32[n], not overlapping; vals may be NULL (keys only).
- * flags: 0 or RT_FLAG_VALIDATE (wait, and report a device error word as
- * RT_ERR_HIP).  workspace: device memory of at least
+ * flags: 0 or any of RT_FLAG_VALIDATE (wait, and report a device error
+ * word as RT_ERR_HIP), RT_FLAG_MSD_ONE_LEVEL, RT_FLAG_MSD_TWO_LEVELS (by
+ * default two levels from 2^28 items).  workspace: device memory of at least
  * rt_msd_first_workspace_bytes(n, vals != NULL) bytes, 256-byte aligned,
  * or NULL for the library's per-stream cache; with a caller workspace and
  * no RT_FLAG_VALIDATE the call only enqueues kernels.  Argument errors are

@@ -30,6 +30,8 @@ RT_FLAG_DIRECT_SCATTER = 0x8
 RT_FLAG_ONE_CHAIN = 0x10
 RT_FLAG_CHUNKS = 0x20
 RT_FLAG_FUSED_HISTOGRAM = 0x40
+RT_FLAG_MSD_ONE_LEVEL = 0x80
+RT_FLAG_MSD_TWO_LEVELS = 0x100
 RT_FLAG_VALIDATE = 0x4
 RT_PROBE_COPY = 0
 RT_PROBE_COPY_NT = 1

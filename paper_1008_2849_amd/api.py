@@ -237,9 +237,15 @@ def msd_first_workspace_bytes(n: int, with_values: bool = True) -> int:
     return int(lib().rt_msd_first_workspace_bytes(n, 1 if with_values else 0))
 
 
-def sort_msd_first(keys, vals=None, validate: bool = False, workspace=None, stream=None) -> None:
-    """In-place stable sort by one MSD partition pass, then LSD passes over
-    the three lower digits of each MSD bucket (the paper's reverse sorting)."""
+def sort_msd_first(keys, vals=None, validate: bool = False, workspace=None, stream=None,
+                   levels: Optional[int] = None) -> None:
+    """In-place stable sort by MSD partition passes, then LSD passes over the
+    lower digits of each bucket (the paper's reverse sorting).  levels: 1 (one
+    partition, then digits 0..2 of each of 256 buckets), 2 (a second
+    partition on digit 2, then digits 0..1 of each of 65536 sub-buckets) or
+    None (the library picks by size)."""
+    if levels not in (None, 1, 2):
+        raise ValueError("levels must be None, 1 or 2")
     _check_tensor(keys, "keys")
     _check_tensor(vals, "vals")
     if vals is not None and vals.numel() != keys.numel():
@@ -248,8 +254,9 @@ def sort_msd_first(keys, vals=None, validate: bool = False, workspace=None, stre
     if workspace is not None:
         ws_ptr = workspace.data_ptr()
         ws_bytes = workspace.numel() * workspace.element_size()
-    check(lib().rt_sort_msd_first(_ptr(keys), _ptr(vals), keys.numel(),
-                                  _lib.RT_FLAG_VALIDATE if validate else 0, ws_ptr, ws_bytes, _stream(stream)),
+    flags = (_lib.RT_FLAG_VALIDATE if validate else 0) | {None: 0, 1: _lib.RT_FLAG_MSD_ONE_LEVEL,
+                                                           2: _lib.RT_FLAG_MSD_TWO_LEVELS}[levels]
+    check(lib().rt_sort_msd_first(_ptr(keys), _ptr(vals), keys.numel(), flags, ws_ptr, ws_bytes, _stream(stream)),
           "rt_sort_msd_first")
 
 

@@ -56,11 +56,13 @@ void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStre
 #undef RT_SEG_SHAPE_LAUNCH
 }
 
-SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps) {
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps,
+                          bool tiled_only, const SegClassTable *classes) {
     SegLayout L{};
     L.num_segments = num_segments;
     L.capacity = capacity;
-    L.classes = seg_class_table();
+    L.classes = classes ? *classes : seg_class_table();
+    if (tiled_only) L.classes.count = 0;
     const size_t large_cap = std::min<size_t>(num_segments, capacity / (L.classes.lds_max() + 1));
     L.large_capacity = static_cast<uint32_t>(large_cap);
     L.tile = L.classes.tile();
@@ -93,12 +95,15 @@ static uint32_t cap_grid(size_t want, uint32_t cap) {
 }
 
 // Per-segment histograms and prefix sums, whole-in-LDS segments, and passes
-// 0..passes-1 over the tiled segments.  The lists and the tiled list's
-// counter are already on the device.  to_temp: the result is wanted in the
-// temporaries (odd pass counts), where the tiled passes leave it.
+// 0..passes-1 (on digits digit0..digit0 + passes - 1) over the tiled
+// segments.  The lists and the tiled list's counter are already on the
+// device.  to_temp: the result is wanted in the temporaries (odd pass
+// counts), where the tiled passes leave it.  persistent: the passes run one
+// block per CU, each claiming tiles until none is left.
 template <bool VALS, typename S>
 static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint32_t list_stride, int passes,
-                                 int to_temp, uint32_t nchunks, hipStream_t stream) {
+                                 int to_temp, uint32_t nchunks, uint32_t digit0, bool persistent,
+                                 hipStream_t stream) {
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
     uint32_t *large_list = P.lists + static_cast<size_t>(kSegLarge) * list_stride;
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
@@ -107,7 +112,8 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
                        P.first_tile, P.header, P.tile_seg, nchunks);
     prof_mark(stream, RT_KIND_SEGMENTED);
     hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
-                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist, L.tile);
+                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist, L.tile,
+                       ((1u << passes) - 1u) << digit0);
     prof_mark(stream, RT_KIND_HISTOGRAM);
     hipLaunchKernelGGL(k_seg_plan, dim3(cap_grid(L.large_capacity, cus * 4)), dim3(256), 0, stream, P.descs,
                        large_list, P.header, P.hist, P.base);
@@ -123,9 +129,16 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
         uint32_t *ctr = P.header_words + offsetof(SegHeader, chunk_ctr) / 4 + p * kChunks;
         uint32_t *err = P.header_words + offsetof(SegHeader, error) / 4;
 #define RT_SEG_TILE_LAUNCH(BLK, I)                                                                               \
-    if (L.classes.tile_block == BLK && L.classes.tile_ipt == I)                                                  \
-        hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S>), dim3(L.max_tiles), dim3(BLK), 0, stream, P.descs,  \
-                           large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status, ctr, err, nchunks);
+    if (L.classes.tile_block == BLK && L.classes.tile_ipt == I) {                                                \
+        if (persistent)                                                                                          \
+            hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S, true>), dim3(cap_grid(L.max_tiles, cus)),        \
+                               dim3(BLK), 0, stream, P.descs, large_list, P.first_tile, P.tile_seg, P.header, p, \
+                               P.base, status, ctr, err, nchunks, digit0);                                       \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S>), dim3(L.max_tiles), dim3(BLK), 0, stream,       \
+                               P.descs, large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status, ctr,  \
+                               err, nchunks, digit0);                                                            \
+    }
         RT_FOR_EACH_SEG_TILE_SHAPE(RT_SEG_TILE_LAUNCH)
 #undef RT_SEG_TILE_LAUNCH
         prof_mark(stream, RT_KIND_PASS + p);
@@ -150,7 +163,7 @@ SegPointers seg_pointers(char *ws, const SegLayout &L) {
 
 void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, const uint32_t *offsets,
                      uint32_t num_segments, const SegLayout &L, char *ws, int passes, int to_temp,
-                     hipStream_t stream) {
+                     hipStream_t stream, uint32_t digit0, bool persistent) {
     const SegPointers P = seg_pointers(ws, L);
     const bool vals_on = vals != nullptr;
     hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, stream, P.header);
@@ -170,11 +183,11 @@ void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
     // chunk measured faster.  The segments' mean size bounds their tiles.
     const uint32_t nchunks = seg_chunk_count(L.capacity, num_segments, L.tile);
     if (L.wide_status) {
-        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
-        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
+        if (vals_on) launch_seg_sort_body<true, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, digit0, persistent, stream);
+        else launch_seg_sort_body<false, uint64_t>(P, L, num_segments, passes, to_temp, nchunks, digit0, persistent, stream);
     } else {
-        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
-        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, stream);
+        if (vals_on) launch_seg_sort_body<true, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, digit0, persistent, stream);
+        else launch_seg_sort_body<false, uint32_t>(P, L, num_segments, passes, to_temp, nchunks, digit0, persistent, stream);
     }
 }
 

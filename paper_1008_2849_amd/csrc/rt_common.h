@@ -91,6 +91,7 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     X(512, 4, 8)                       \
     X(512, 8, 8)                       \
     X(256, 16, 8)                      \
+    X(256, 20, 8)                      \
     X(512, 16, 8)                      \
     X(1024, 8, 8)                      \
     X(1024, 16, 8)                     \
@@ -181,16 +182,22 @@ struct SegPointers {
 
 // own_temps: the workspace holds the temporaries (capacity items each);
 // otherwise the caller supplies them.  The layout takes the current size
-// classes, and a call uses those of its layout.
-SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps);
+// classes (or `classes` when given), and a call uses those of its layout;
+// tiled_only: none, every segment of two or more items goes through the
+// tiled passes.
+SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_values, bool own_temps,
+                          bool tiled_only = false, const SegClassTable *classes = nullptr);
 SegPointers seg_pointers(char *ws, const SegLayout &L);
 // Sorts segment s = [offsets[s], offsets[s+1]) of keys/vals on digits
-// 0..passes-1 with temporaries tk/tv at the same distance from offsets[0];
-// an even pass count leaves the result in keys/vals, an odd one (to_temp
-// set) in tk/tv.
+// digit0..digit0 + passes - 1 with temporaries tk/tv at the same distance
+// from offsets[0]; an even pass count leaves the result in keys/vals, an odd
+// one (to_temp set) in tk/tv.  digit0 > 0 needs a tiled_only layout (the
+// whole-in-LDS classes sort from digit 0).  persistent: the tiled passes run
+// one block per CU that claims tiles until none is left, for calls whose
+// tiled segments are usually few.
 void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv, const uint32_t *offsets,
                      uint32_t num_segments, const SegLayout &L, char *ws, int passes, int to_temp,
-                     hipStream_t stream);
+                     hipStream_t stream, uint32_t digit0 = 0, bool persistent = false);
 void launch_batched(uint32_t *keys, uint32_t *vals, const uint32_t *offsets, uint32_t num_segments,
                     const SegLayout &L, char *ws, hipStream_t stream);
 

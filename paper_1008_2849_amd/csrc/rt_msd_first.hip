@@ -4,6 +4,14 @@
 // every bucket is sorted on its own by LSD passes over digits 0, 1 and 2,
 // the last of which writes the caller's arrays.
 //
+// The paper partitions until a bucket fits the cache and sorts it there.
+// On this GPU the fast memory a bucket can be sorted in is one block's LDS
+// (16K items), so large inputs take a second MSD level: a segmented pass on
+// digit 2 inside the buckets (their digit-2 counts, one read, give 65536
+// sub-bucket bounds), then digits 0 and 1 of each sub-bucket, whole in LDS
+// when it fits, else by two tiled passes.  Three passes over HBM instead of
+// four, the last of them with two digits' work in LDS.
+//
 // Algorithm 2's pieces map as follows.  The MSD histogram and its exclusive
 // prefix sum (bucketSizes, outputIndices) are the upfront histogram and plan
 // kernels of the single-array sort restricted to digit 3; the partition is
@@ -16,8 +24,10 @@
 // digits 0..2 are taken in one read of each bucket before its first local
 // pass (Algorithm 2 has no need for the first two: its buckets grow in
 // virtual memory).
+#include <algorithm>
+
 #include "rt_common.h"
-#include "rt_kernels.h"
+#include "rt_seg_kernels.h"
 
 namespace rt {
 
@@ -26,15 +36,37 @@ constexpr uint32_t kMsdShift = 24;
 constexpr uint32_t kMsdWidth = 8;
 constexpr uint32_t kMsdBuckets = 1u << kMsdWidth;
 constexpr int kLocalPasses = 3;
+constexpr uint32_t kSubBuckets = kMsdBuckets << 8;  // second level: digit 2 inside each bucket
+// Two levels by default from this size (sub-buckets of about 4096 items):
+// measured slower than one level at 2^26 and 2^27 items, faster at 2^28.
+constexpr size_t kTwoLevelMinItems = static_cast<size_t>(1) << 28;
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Size classes of the sub-buckets.  Uniform keys give sub-buckets of about
+// m = n / 65536 items (within a few sqrt(m)); from m = 2048 the classes sit
+// close above that, so a sub-bucket just past 4096 items takes a 5120-item
+// block rather than an 8192-item one.  Smaller m keeps the tuned classes.
+SegClassTable leaf_classes(size_t n) {
+    SegClassTable t = seg_class_table();
+    if (n / kSubBuckets < 2048) return t;
+    t.count = 4;
+    t.cls[0] = SegClass{4096, 256, 16, 8};
+    t.cls[1] = SegClass{5120, 256, 20, 8};
+    t.cls[2] = SegClass{8192, 512, 16, 8};
+    t.cls[3] = SegClass{16384, 1024, 16, 8};
+    return t;
+}
 
 struct MsdLayout {
     Resolved r;       // the partition pass
     Layout part;      // its histogram, plan and lookback words (at offset 0)
     size_t tk, tv;    // the partitioned copy
-    size_t seg;       // the segmented sort's tables
-    SegLayout local;
+    size_t sub;       // two levels: sub-bucket offsets (kSubBuckets + 1), then the first level's error word
+    size_t seg;       // the segmented sorts' tables (one call at a time)
+    SegLayout local;  // one level: digits 0..2 of every bucket
+    SegLayout level2; // two levels: digit 2 of every bucket (tiled only)
+    SegLayout leaf;   // two levels: digits 0..1 of every sub-bucket
     size_t total;
 };
 
@@ -66,9 +98,14 @@ MsdLayout make_msd_layout(size_t n, bool with_values) {
         M.tv = off;
         off += align256(n * sizeof(uint32_t));
     }
+    M.sub = off;
+    off += align256(sizeof(uint32_t) * (kSubBuckets + 2));
     M.seg = off;
     M.local = make_seg_layout(kMsdBuckets, n, with_values, false);
-    M.total = off + M.local.total;
+    M.level2 = make_seg_layout(kMsdBuckets, n, with_values, false, true);
+    const SegClassTable leaf = leaf_classes(n);
+    M.leaf = make_seg_layout(kSubBuckets, n, with_values, false, false, &leaf);
+    M.total = off + std::max(M.local.total, std::max(M.level2.total, M.leaf.total));
     return M;
 }
 }  // namespace
@@ -87,8 +124,11 @@ extern "C" rt_status rt_sort_msd_first(uint32_t *keys, uint32_t *vals, size_t n,
     const char *what = "rt_sort_msd_first";
     if (n >= (static_cast<size_t>(1) << 32))
         return set_error(RT_ERR_TOO_LARGE, "%s: n = %zu, the limit is 2^32 - 1", what, n);
-    if (flags & ~static_cast<uint32_t>(RT_FLAG_VALIDATE))
+    if (flags & ~static_cast<uint32_t>(RT_FLAG_VALIDATE | RT_FLAG_MSD_ONE_LEVEL | RT_FLAG_MSD_TWO_LEVELS))
         return set_error(RT_ERR_INVALID_ARG, "%s: unknown flags 0x%x", what, flags);
+    if ((flags & RT_FLAG_MSD_ONE_LEVEL) && (flags & RT_FLAG_MSD_TWO_LEVELS))
+        return set_error(RT_ERR_INVALID_ARG, "%s: RT_FLAG_MSD_ONE_LEVEL and RT_FLAG_MSD_TWO_LEVELS exclude each other",
+                         what);
     if (n < 2) return RT_OK;
     if (keys == nullptr) return set_error(RT_ERR_INVALID_ARG, "%s: keys is NULL with n = %zu", what, n);
     if ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(vals)) & 3u)
@@ -116,23 +156,38 @@ extern "C" rt_status rt_sort_msd_first(uint32_t *keys, uint32_t *vals, size_t n,
     uint32_t *tv = vals ? reinterpret_cast<uint32_t *>(w + M.tv) : nullptr;
     // partition: caller's arrays -> temporary, by the MSD
     launch_sort(keys, vals, static_cast<uint32_t>(n), M.r, M.part, w, true, tk, tv, stream, RT_KIND_MSD_PASS);
-    // local LSD over digits 0..2 of each bucket: temporary -> caller's arrays
     const uint32_t *bucket_offsets = reinterpret_cast<const uint32_t *>(w + M.part.base);
-    launch_segments(tk, tv, keys, vals, bucket_offsets, kMsdBuckets, M.local, w + M.seg, kLocalPasses, 1, stream);
+    const bool two = (flags & RT_FLAG_MSD_TWO_LEVELS) || (!(flags & RT_FLAG_MSD_ONE_LEVEL) && n >= kTwoLevelMinItems);
+    uint32_t *sub = reinterpret_cast<uint32_t *>(w + M.sub);
+    if (two) {
+        // digit 2 inside every bucket: temporary -> caller's arrays
+        launch_segments(tk, tv, keys, vals, bucket_offsets, kMsdBuckets, M.level2, w + M.seg, 1, 1, stream, 2);
+        const SegPointers P = seg_pointers(w + M.seg, M.level2);
+        hipLaunchKernelGGL(k_msd_subbuckets, dim3(kMsdBuckets), dim3(256), 0, stream, bucket_offsets, P.descs, P.hist,
+                           2u, kMsdBuckets, sub, P.header, sub + kSubBuckets + 1);
+        prof_mark(stream, RT_KIND_PLAN);
+        // digits 0 and 1 of every sub-bucket, in the caller's arrays
+        launch_segments(keys, vals, tk, tv, sub, kSubBuckets, M.leaf, w + M.seg, 2, 0, stream, 0, true);
+    } else {
+        // local LSD over digits 0..2 of each bucket: temporary -> caller's arrays
+        launch_segments(tk, tv, keys, vals, bucket_offsets, kMsdBuckets, M.local, w + M.seg, kLocalPasses, 1, stream);
+    }
     rt_status s = finish_call(stream, what);
     if (s != RT_OK) return s;
     if ((flags & RT_FLAG_VALIDATE) || debug_sync_enabled()) {
-        uint32_t part_err = 0;
+        uint32_t part_err = 0, level2_err = 0;
         SegHeader h;
         hipError_t e = hipMemcpyAsync(&part_err, w + M.part.ctr + sizeof(uint32_t) * kMaxPasses, sizeof part_err,
                                       hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&h, w + M.seg + M.local.header, sizeof h, hipMemcpyDeviceToHost, stream);
+        // every segmented layout starts with its header, at M.seg
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, w + M.seg, sizeof h, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && two)
+            e = hipMemcpyAsync(&level2_err, sub + kSubBuckets + 1, sizeof level2_err, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return set_error(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-        if (part_err || h.error)
-            return set_error(RT_ERR_HIP, "%s: device error words 0x%x (partition), 0x%x (local passes)", what,
-                             part_err, h.error);
+        if (part_err || level2_err || h.error)
+            return set_error(RT_ERR_HIP, "%s: device error words 0x%x (partition), 0x%x (second level), 0x%x (local passes)",
+                             what, part_err, level2_err, h.error);
     }
     return RT_OK;
 }

@@ -177,13 +177,15 @@ static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__re
 // ---------------------------------------------------------------------------
 
 // Sorts segments of at most BLOCK * IPT items, one per block at a time.  The
-// segment is loaded once from k/v, padded with all-ones keys that stay
-// behind every real item (they come last in input order and the sort is
-// stable), taken through the digits of passes 0..passes-1 in LDS, and stored
-// once: to k/v, or to tk/tv when to_temp is set (where the tiled passes
-// leave an odd pass count's result).  Ranking inside a pass is the onesweep
-// ranking: wave-local ballot match plus per-wave digit counters, then digit
-// offsets across the block.
+// segment is loaded once from k/v, taken through the digits of passes
+// 0..passes-1 in LDS, and stored once: to k/v, or to tk/tv when to_temp is
+// set (where the tiled passes leave an odd pass count's result).  Slots
+// wholly past the segment's end are neither ranked nor staged; the empty
+// lanes of the slot that holds the end take all-ones keys, which rank behind
+// every real item (they come last in input order and the sort is stable),
+// so the items' positions are those of the segment alone.  Ranking inside a
+// pass is the onesweep ranking: wave-local ballot match plus per-wave digit
+// counters, then digit offsets across the block.
 template <int BLOCK, int IPT, bool VALS, int BITS>
 __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__ descs,
                                                      const uint32_t *__restrict__ list,
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             uint32_t rnk[IPT];
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
+                if (wave * WAVE_ITEMS + j * 64 >= n) continue;  // a slot past the segment: no item to rank
                 const uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, width);
                 uint32_t lo, hi;
                 match_digit<BITS>(dg, lo, hi);
@@ -268,6 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
+                if (wave * WAVE_ITEMS + j * 64 >= n) continue;
                 const uint32_t r = wh[__builtin_amdgcn_ubfe(key[j], shift, width)] + rnk[j];
                 s_k[r] = key[j];
                 if constexpr (VALS) s_v[r] = val[j];
@@ -276,8 +280,9 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
             if (shift + BITS < static_cast<uint32_t>(key_bits)) {
 #pragma unroll
                 for (int j = 0; j < IPT; ++j) {
-                    key[j] = s_k[wslot0 + j * 64];
-                    if constexpr (VALS) val[j] = s_v[wslot0 + j * 64];
+                    const uint32_t i = wslot0 + j * 64;
+                    key[j] = i < n ? s_k[i] : ~0u;
+                    if constexpr (VALS) val[j] = i < n ? s_v[i] : 0u;
                 }
                 // s_k is rewritten only after the next pass's first barrier
             }
@@ -296,8 +301,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
 // tiled segments: per-segment histograms and prefix sums
 // ---------------------------------------------------------------------------
 
-// Counts the digits of all four passes per tiled segment into
-// hist[row][p][d] (zeroed before).  Block b walks a contiguous range of
+// Counts the digits of the passes in `digits` (bit p: digit p) per tiled
+// segment into hist[row][p][d] (zeroed before; other rows stay zero).  Block b walks a contiguous range of
 // tiles, so its counters stay in LDS across the tiles of one segment and
 // are flushed to HBM (atomics) only when the segment changes.  Counting is
 // as in k_histogram: C lane-class copies of the counters in padded LDS rows,
@@ -309,7 +314,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
                                                          const uint32_t *__restrict__ first_tile,
                                                          const uint32_t *__restrict__ tile_seg,
                                                          const SegHeader *__restrict__ h,
-                                                         uint32_t *__restrict__ hist, uint32_t tile) {
+                                                         uint32_t *__restrict__ hist, uint32_t tile,
+                                                         uint32_t digits) {
     constexpr int BINS = kSegPasses * kSegRadix;
     constexpr int ROW = BINS + 1;
     constexpr int WAVES = BLOCK / 64;
@@ -363,6 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
                 for (int u = 0; u < U; ++u) differ |= k[u] ^ k0;
 #pragma unroll
                 for (int p = 0; p < kSegPasses; ++p) {
+                    if (!((digits >> p) & 1u)) continue;
                     uint32_t *hp = hc + p * kSegRadix;
                     if (__builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(differ, p * kSegBits, kSegBits) != 0u) == 0u) {
                         if (lane == 0) atomicAdd(&hp[__builtin_amdgcn_ubfe(k0, p * kSegBits, kSegBits)], SPAN);
@@ -379,7 +386,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
                     const uint32_t key = src[i];
 #pragma unroll
                     for (int p = 0; p < kSegPasses; ++p)
-                        atomicAdd(&hc[p * kSegRadix + __builtin_amdgcn_ubfe(key, p * kSegBits, kSegBits)], 1u);
+                        if ((digits >> p) & 1u)
+                            atomicAdd(&hc[p * kSegRadix + __builtin_amdgcn_ubfe(key, p * kSegBits, kSegBits)], 1u);
                 }
             }
         }
@@ -414,11 +422,15 @@ static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restri
 // (chunk_counter: the launch's kChunks counters, zeroed before it; chunk
 // bounds from k_seg_tilemap with the same nchunks), then the pass body
 // of onesweep_tile on it.  The tile's segment runs pass `pass` (or its own
-// d.pass when pass < 0): even passes read k/v and write tk/tv, odd passes the
-// reverse, so four passes leave the result in k/v and three in tk/tv.  The
+// d.pass when pass < 0) on digit digit0 + pass: even passes read k/v and
+// write tk/tv, odd passes the reverse, so four passes leave the result in
+// k/v and three in tk/tv.  The
 // segment's lookback chain starts at its first tile.  Status words: one per
-// tile and digit, zeroed before the launch.
-template <int BLOCK, int IPT, bool VALS, typename S>
+// tile and digit, zeroed before the launch.  PERSIST: a block claims tiles
+// until none is left, so a grid of one block per CU covers any tile count
+// (for calls whose tiled list is usually short or empty: the full grid's
+// blocks would mostly start only to find nothing to do).
+template <int BLOCK, int IPT, bool VALS, typename S, bool PERSIST = false>
 __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
                                                         const uint32_t *__restrict__ list,
                                                         const uint32_t *__restrict__ first_tile,
@@ -426,39 +438,76 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
                                                         const SegHeader *__restrict__ h, int pass,
                                                         const uint32_t *__restrict__ base, S *__restrict__ status,
                                                         uint32_t *__restrict__ chunk_counter,
-                                                        uint32_t *__restrict__ error_flag, uint32_t nchunks) {
+                                                        uint32_t *__restrict__ error_flag, uint32_t nchunks,
+                                                        uint32_t digit0) {
     constexpr int TILE = BLOCK * IPT;
     constexpr bool SMALL = sizeof(S) == 4;  // every segment below 2^30 items
     __shared__ OnesweepLds<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS> lds;
 
-    for (uint32_t i = threadIdx.x & 63u; i < static_cast<uint32_t>(kSegRadix); i += 64)
-        lds.whist[(threadIdx.x >> 6) * kSegRadix + i] = 0u;
-    if (threadIdx.x == 0) {
-        uint32_t x = 0;
-        lds.claim[0] = claim_chunked(h->chunk_start, nchunks, chunk_counter, x);
+    for (;;) {
+        for (uint32_t i = threadIdx.x & 63u; i < static_cast<uint32_t>(kSegRadix); i += 64)
+            lds.whist[(threadIdx.x >> 6) * kSegRadix + i] = 0u;
+        if (threadIdx.x == 0) {
+            uint32_t x = 0;
+            lds.claim[0] = claim_chunked(h->chunk_start, nchunks, chunk_counter, x);
+        }
+        __syncthreads();
+        const uint32_t tile = lds.claim[0];
+        if (tile >= h->total_tiles) return;  // kNoTile too
+        const uint32_t e = tile_seg[tile];
+        const SegDesc d = descs[list[e]];
+        const uint32_t first = first_tile[e];
+        const uint32_t p = pass >= 0 ? static_cast<uint32_t>(pass) : d.pass;
+        TileJob<uint32_t, uint32_t> job;
+        job.src_k = (p & 1u) ? d.tk : d.k;
+        job.src_v = (p & 1u) ? d.tv : d.v;
+        job.dst_k = (p & 1u) ? d.k : d.tk;
+        job.dst_v = (p & 1u) ? d.v : d.tv;
+        const uint32_t dg = digit0 + p;
+        job.base = base + (static_cast<size_t>(d.row) * kSegPasses + dg) * kSegRadix;
+        job.item0 = static_cast<size_t>(tile - first) * TILE;
+        job.shift = dg * kSegBits;
+        job.width = kSegBits;
+        job.tile = tile;
+        job.first = first;
+        job.valid = min(static_cast<uint32_t>(TILE), d.n - (tile - first) * static_cast<uint32_t>(TILE));
+        job.bound = d.n;
+        onesweep_tile<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS, false, S, true, SMALL>(job, lds, status,
+                                                                                            error_flag);
+        if constexpr (!PERSIST) return;
+        __syncthreads();  // the tile is out of the LDS before the next claim
     }
-    __syncthreads();
-    const uint32_t tile = lds.claim[0];
-    if (tile >= h->total_tiles) return;  // kNoTile too
-    const uint32_t e = tile_seg[tile];
-    const SegDesc d = descs[list[e]];
-    const uint32_t first = first_tile[e];
-    const uint32_t p = pass >= 0 ? static_cast<uint32_t>(pass) : d.pass;
-    TileJob<uint32_t, uint32_t> job;
-    job.src_k = (p & 1u) ? d.tk : d.k;
-    job.src_v = (p & 1u) ? d.tv : d.v;
-    job.dst_k = (p & 1u) ? d.k : d.tk;
-    job.dst_v = (p & 1u) ? d.v : d.tv;
-    job.base = base + (static_cast<size_t>(d.row) * kSegPasses + p) * kSegRadix;
-    job.item0 = static_cast<size_t>(tile - first) * TILE;
-    job.shift = p * kSegBits;
-    job.width = kSegBits;
-    job.tile = tile;
-    job.first = first;
-    job.valid = min(static_cast<uint32_t>(TILE), d.n - (tile - first) * static_cast<uint32_t>(TILE));
-    job.bound = d.n;
-    onesweep_tile<kSegBits, BLOCK, IPT, uint32_t, uint32_t, VALS, false, S, true, SMALL>(job, lds, status,
-                                                                                        error_flag);
+}
+
+// ---------------------------------------------------------------------------
+// a second MSD level: sub-bucket bounds from the buckets' digit counts
+// ---------------------------------------------------------------------------
+
+// One block of 256 threads per bucket b = [off[b], off[b + 1]) of a
+// segmented call whose tiled list holds every bucket of two or more items
+// (no whole-in-LDS classes) and whose histogram counted digit `digit`:
+// sub[b * 256 + d] = off[b] + the bucket's items with a lower digit, so
+// sub-bucket b * 256 + d holds the bucket's items of digit d once the call's
+// pass on that digit has run.  A bucket of fewer than two items has no row:
+// its sub-buckets are empty but the last, which holds it.  sub[256 *
+// buckets] = off[buckets].
+// Block 0 also copies the call's error word to *err (the next segmented
+// call reuses the header).
+static __global__ __launch_bounds__(256) void k_msd_subbuckets(const uint32_t *__restrict__ off,
+                                                               const SegDesc *__restrict__ descs,
+                                                               const uint32_t *__restrict__ hist, uint32_t digit,
+                                                               uint32_t buckets, uint32_t *__restrict__ sub,
+                                                               const SegHeader *__restrict__ h,
+                                                               uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_wsum[4];
+    const uint32_t b = blockIdx.x, d = threadIdx.x;
+    const uint32_t a = off[b], e = off[b + 1];
+    uint32_t c = 0;
+    if (e - a >= 2u) c = hist[(static_cast<size_t>(descs[b].row) * kSegPasses + digit) * kSegRadix + d];
+    const uint32_t below = block_exclusive_sum<256>(c, s_wsum);
+    sub[static_cast<size_t>(b) * kSegRadix + d] = a + below;
+    if (b + 1 == buckets && d == 0) sub[static_cast<size_t>(buckets) * kSegRadix] = e;
+    if (b == 0 && d == 0) *err = h->error;
 }
 
 }  // namespace rt

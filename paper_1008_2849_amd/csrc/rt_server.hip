@@ -320,7 +320,8 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
                            d_hh, d_seg_h, 1u);
         hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_descs,
-                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist, static_cast<uint32_t>(kSegTile));
+                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist, static_cast<uint32_t>(kSegTile),
+                           (1u << kSegPasses) - 1u);
         hipLaunchKernelGGL(k_seg_plan, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
                            d_hist, d_base);
     }
@@ -340,11 +341,11 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
         if (P.vals)
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
-                               ctr, err, nchunks);
+                               ctr, err, nchunks, 0u);
         else
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
                                dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
-                               ctr, err, nchunks);
+                               ctr, err, nchunks, 0u);
     }
     for (uint32_t c = 0; c < s->classes.count; ++c)  // small requests, whole in LDS
         if (P.small[c])

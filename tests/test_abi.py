@@ -384,9 +384,11 @@ def test_msd_first_workspace_bytes(so):
     keys = so.rt_msd_first_workspace_bytes(n, 0)
     # one temporary per array (the local passes use the caller's arrays as
     # the other buffer), plus lookback words and tables (whose size follows
-    # the tuned tile of each)
+    # the tuned tile of each); the second MSD level's tables are sized for
+    # the most sub-buckets that can be too large for the LDS (n / 16385),
+    # about one byte per item
     assert abs((with_v - keys) - 4 * n) < (16 << 20)
-    assert keys >= 4 * n and keys < 4 * n + (128 << 20)
+    assert keys >= 4 * n and keys < 5 * n + (128 << 20)
 
 
 def test_sort64_argument_errors(so):

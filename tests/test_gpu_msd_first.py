@@ -5,7 +5,9 @@ The MSD buckets become segments of the segmented sort, so the cases aim at
 its edges: buckets of 0 and 1 items, buckets at and just past each
 whole-in-LDS class limit (2048, 8192, 16384) and the tile size, every item in
 one bucket (constant top byte), two extreme buckets, and the full 2^28-pair
-workload in the configuration the benchmark times.
+workload in the configuration the benchmark times.  Each runs with one MSD
+level and with two; with two, the sub-buckets (top 16 bits) get the same
+edge cases.
 """
 import numpy as np
 import pytest
@@ -27,28 +29,34 @@ def gpu_msd_first(keys, vals=None, **kw):
     return to_host(k), (None if v is None else to_host(v))
 
 
+LEVELS = [1, 2]
+
+
+@pytest.mark.parametrize("levels", LEVELS)
 @pytest.mark.parametrize("n", SIZES)
-def test_pairs_uniform_sizes(n):
-    announce(f"msd-first pairs uniform n={n}")
+def test_pairs_uniform_sizes(n, levels):
+    announce(f"msd-first pairs uniform n={n} levels={levels}")
     k = inputs.uniform_keys(n, 300 + n % 997)
     v = inputs.index_values(n)
-    assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), f"n={n}")
+    assert_same(gpu_msd_first(k, v, validate=True, levels=levels), oracle.reverse_sort(k, v), f"n={n}")
 
 
+@pytest.mark.parametrize("levels", [None] + LEVELS)
 @pytest.mark.parametrize("n", [2, 65, 16385, (1 << 20) + 1])
-def test_keys_uniform_sizes(n):
-    announce(f"msd-first keys uniform n={n}")
+def test_keys_uniform_sizes(n, levels):
+    announce(f"msd-first keys uniform n={n} levels={levels}")
     k = inputs.uniform_keys(n, 400 + n % 991)
-    assert_same(gpu_msd_first(k), oracle.reverse_sort(k), f"n={n}")
+    assert_same(gpu_msd_first(k, levels=levels), oracle.reverse_sort(k), f"n={n}")
 
 
+@pytest.mark.parametrize("levels", LEVELS)
 @pytest.mark.parametrize("dist", list(_dist_cases(8).keys()))
-def test_distributions_pairs(dist):
+def test_distributions_pairs(dist, levels):
     n = (1 << 20) + 123
-    announce(f"msd-first pairs dist={dist} n={n}")
+    announce(f"msd-first pairs dist={dist} n={n} levels={levels}")
     k = _dist_cases(n)[dist]
     v = inputs.index_values(n)
-    assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), dist)
+    assert_same(gpu_msd_first(k, v, validate=True, levels=levels), oracle.reverse_sort(k, v), dist)
 
 
 def _bucketed_keys(counts, seed):
@@ -62,8 +70,9 @@ def _bucketed_keys(counts, seed):
     return k
 
 
+@pytest.mark.parametrize("levels", LEVELS)
 @pytest.mark.parametrize("case", ["class_edges", "tile_edges", "sparse", "one_heavy"])
-def test_bucket_size_edges(case):
+def test_bucket_size_edges(case, levels):
     counts = np.zeros(256, dtype=np.int64)
     if case == "class_edges":
         for d, c in zip(range(0, 256, 16), [0, 1, 2, 2047, 2048, 2049, 8191, 8192, 8193, 16383, 16384,
@@ -78,19 +87,60 @@ def test_bucket_size_edges(case):
         counts[:] = 3
         counts[128] = 400_000
     n = int(counts.sum())
-    announce(f"msd-first bucket sizes {case} n={n}")
+    announce(f"msd-first bucket sizes {case} n={n} levels={levels}")
     k = _bucketed_keys(counts, 500 + len(case))
     v = inputs.index_values(n)
-    assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), case)
-    assert_same(gpu_msd_first(k), oracle.reverse_sort(k), case + " keys")
+    assert_same(gpu_msd_first(k, v, validate=True, levels=levels), oracle.reverse_sort(k, v), case)
+    assert_same(gpu_msd_first(k, levels=levels), oracle.reverse_sort(k), case + " keys")
 
 
-def test_explicit_workspace_repeat_and_graph():
+def _subbucketed_keys(counts, seed):
+    """Keys whose sub-bucket s (top 16 bits) holds counts[s] items, lower 16
+    bits uniform, in a shuffled order."""
+    rng = np.random.default_rng(seed)
+    top = np.repeat(np.arange(len(counts), dtype=np.uint32), counts)
+    low = rng.integers(0, 1 << 16, size=top.size, dtype=np.uint32)
+    k = (top << np.uint32(16)) | low
+    rng.shuffle(k)
+    return k
+
+
+@pytest.mark.parametrize("case", ["class_edges", "tile_edges", "one_bucket", "tiny_buckets"])
+def test_sub_bucket_size_edges(case):
+    """Two MSD levels: sub-buckets of 0 and 1 items, at and just past each
+    whole-in-LDS class limit and the tile size (two tiled passes), all of a
+    bucket's items in one sub-bucket, and buckets of one item (no digit-2
+    counts) beside full ones."""
+    counts = np.zeros(1 << 16, dtype=np.int64)
+    if case == "class_edges":
+        for i, c in enumerate([0, 1, 2, 3, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
+                               8191, 8192, 8193, 16383, 16384, 16385]):
+            counts[(i * 7919) % (1 << 16)] = c
+    elif case == "tile_edges":
+        for s, c in zip([5, 300, 301, 40000, 65535], [16384 * 2, 16384 * 2 + 1, 16384 * 5 - 1, 16385, 16384 * 3]):
+            counts[s] = c
+    elif case == "one_bucket":
+        counts[(77 << 8) + 3] = 300_000  # every item of bucket 77 in one sub-bucket
+        counts[(78 << 8):(79 << 8)] = 5
+    else:
+        counts[0::256] = 1  # buckets of one item
+        counts[(200 << 8):(201 << 8)] = 700  # and one full bucket
+        counts[65535] = 2
+    n = int(counts.sum())
+    announce(f"msd-first sub-bucket sizes {case} n={n}")
+    k = _subbucketed_keys(counts, 700 + len(case))
+    v = inputs.index_values(n)
+    assert_same(gpu_msd_first(k, v, validate=True, levels=2), oracle.reverse_sort(k, v), case)
+    assert_same(gpu_msd_first(k, levels=2), oracle.reverse_sort(k), case + " keys")
+
+
+@pytest.mark.parametrize("levels", LEVELS)
+def test_explicit_workspace_repeat_and_graph(levels):
     """A caller workspace; three eager calls and a captured graph replayed
     three times (with eager work between) all give the oracle's result."""
     import torch
     n = 3 * 16384 + 4321
-    announce(f"msd-first workspace + graph n={n}")
+    announce(f"msd-first workspace + graph n={n} levels={levels}")
     k_h = inputs.uniform_keys(n, 600)
     v_h = inputs.index_values(n)
     want = oracle.reverse_sort(k_h, v_h)
@@ -100,7 +150,7 @@ def test_explicit_workspace_repeat_and_graph():
     for rep in range(3):
         k.copy_(k0)
         v.copy_(v0)
-        rts.sort_msd_first(k, v, workspace=ws)
+        rts.sort_msd_first(k, v, workspace=ws, levels=levels)
         sync()
         assert_same((to_host(k), to_host(v)), want, f"eager {rep}")
     s = torch.cuda.Stream()
@@ -108,12 +158,12 @@ def test_explicit_workspace_repeat_and_graph():
     with torch.cuda.stream(s):
         k.copy_(k0)
         v.copy_(v0)
-        rts.sort_msd_first(k, v, workspace=ws, stream=s)  # warm up on the capture stream
+        rts.sort_msd_first(k, v, workspace=ws, stream=s, levels=levels)  # warm up on the capture stream
     torch.cuda.current_stream().wait_stream(s)
     sync()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
-        rts.sort_msd_first(k, v, workspace=ws, stream=s)
+        rts.sort_msd_first(k, v, workspace=ws, stream=s, levels=levels)
     for rep in range(3):
         k.copy_(k0)
         v.copy_(v0)
@@ -122,7 +172,7 @@ def test_explicit_workspace_repeat_and_graph():
         sync()
         assert_same((to_host(k), to_host(v)), want, f"replay {rep}")
         k2, v2 = k0.clone(), v0.clone()
-        rts.sort_msd_first(k2, v2)
+        rts.sort_msd_first(k2, v2, levels=levels)
         sync()
         assert_same((to_host(k2), to_host(v2)), want, f"eager after replay {rep}")
 
