@@ -74,7 +74,7 @@ SegLayout make_seg_layout(uint32_t num_segments, size_t capacity, bool with_valu
     L.descs = off;      off += align256(sizeof(SegDesc) * num_segments);
     L.lists = off;      off += align256(sizeof(uint32_t) * (kSegMaxClasses + 1) * static_cast<size_t>(num_segments));
     L.first_tile = off; off += align256(sizeof(uint32_t) * (large_cap + 1));
-    L.tile_seg = off;   off += align256(sizeof(uint32_t) * L.max_tiles);
+    L.tile_seg = off;   off += align256(sizeof(SegDesc) * L.max_tiles);
     L.hist = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
     L.base = off;       off += align256(sizeof(uint32_t) * kSegPasses * kSegRadix * large_cap);
     L.status_pass = static_cast<size_t>(L.max_tiles) * kSegRadix * sw;
@@ -109,10 +109,10 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, stream, P.descs, large_list, P.first_tile, P.header,
                        L.large_capacity, L.max_tiles, L.tile);
     hipLaunchKernelGGL(k_seg_tilemap, dim3(cap_grid((L.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, stream,
-                       P.first_tile, P.header, P.tile_seg, nchunks);
+                       P.descs, large_list, P.first_tile, P.header, P.tile_seg, nchunks);
     prof_mark(stream, RT_KIND_SEGMENTED);
     hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
-                       P.descs, large_list, P.first_tile, P.tile_seg, P.header, P.hist, L.tile,
+                       P.tile_seg, P.header, P.hist, L.tile,
                        ((1u << passes) - 1u) << digit0);
     prof_mark(stream, RT_KIND_HISTOGRAM);
     hipLaunchKernelGGL(k_seg_plan, dim3(cap_grid(L.large_capacity, cus * 4)), dim3(256), 0, stream, P.descs,
@@ -132,11 +132,11 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     if (L.classes.tile_block == BLK && L.classes.tile_ipt == I) {                                                \
         if (persistent)                                                                                          \
             hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S, true>), dim3(cap_grid(L.max_tiles, cus)),        \
-                               dim3(BLK), 0, stream, P.descs, large_list, P.first_tile, P.tile_seg, P.header, p, \
+                               dim3(BLK), 0, stream, P.tile_seg, P.header, p,                                    \
                                P.base, status, ctr, err, nchunks, digit0);                                       \
         else                                                                                                     \
             hipLaunchKernelGGL((k_seg_onesweep<BLK, I, VALS, S>), dim3(L.max_tiles), dim3(BLK), 0, stream,       \
-                               P.descs, large_list, P.first_tile, P.tile_seg, P.header, p, P.base, status, ctr,  \
+                               P.tile_seg, P.header, p, P.base, status, ctr,                                     \
                                err, nchunks, digit0);                                                            \
     }
         RT_FOR_EACH_SEG_TILE_SHAPE(RT_SEG_TILE_LAUNCH)
@@ -152,7 +152,7 @@ SegPointers seg_pointers(char *ws, const SegLayout &L) {
     P.descs = reinterpret_cast<SegDesc *>(ws + L.descs);
     P.lists = reinterpret_cast<uint32_t *>(ws + L.lists);
     P.first_tile = reinterpret_cast<uint32_t *>(ws + L.first_tile);
-    P.tile_seg = reinterpret_cast<uint32_t *>(ws + L.tile_seg);
+    P.tile_seg = reinterpret_cast<SegDesc *>(ws + L.tile_seg);
     P.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     P.base = reinterpret_cast<uint32_t *>(ws + L.base);
     P.status = ws + L.status;

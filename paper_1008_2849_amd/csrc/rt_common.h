@@ -172,7 +172,7 @@ struct SegPointers {
     SegDesc *descs;
     uint32_t *lists;
     uint32_t *first_tile;
-    uint32_t *tile_seg;
+    SegDesc *tile_seg;  // per tile: its segment's descriptor, pad = the segment's first tile
     uint32_t *hist;
     uint32_t *base;
     char *status;

@@ -134,13 +134,17 @@ static __global__ __launch_bounds__(1024) void k_seg_tiles(const SegDesc *__rest
     }
 }
 
-// tile_seg[t] = the list entry that tile t belongs to (first_tile is
-// strictly increasing: every listed segment has at least one tile).  Block 0
-// also cuts the tile list into nchunks (1 or kChunks) chunks of about equal
-// tile counts at segment ends (a segment's tiles stay on one XCD).
-static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__restrict__ first_tile,
+// tile_desc[t] = the descriptor of the segment that tile t belongs to, with
+// pad = that segment's first tile (first_tile is strictly increasing: every
+// listed segment has at least one tile), so that a tile's kernel reaches its
+// segment in one load rather than a chain of three.  Block 0 also cuts the
+// tile list into nchunks (1 or kChunks) chunks of about equal tile counts at
+// segment ends (a segment's tiles stay on one XCD).
+static __global__ __launch_bounds__(256) void k_seg_tilemap(const SegDesc *__restrict__ descs,
+                                                     const uint32_t *__restrict__ list,
+                                                     const uint32_t *__restrict__ first_tile,
                                                      SegHeader *__restrict__ h,
-                                                     uint32_t *__restrict__ tile_seg, uint32_t nchunks) {
+                                                     SegDesc *__restrict__ tile_desc, uint32_t nchunks) {
     const uint32_t count = h->count[kSegLarge];
     const uint32_t total = h->total_tiles;
     if (blockIdx.x == 0 && threadIdx.x <= kChunks) {
@@ -168,7 +172,9 @@ static __global__ __launch_bounds__(256) void k_seg_tilemap(const uint32_t *__re
             if (first_tile[mid] <= t) lo = mid;
             else hi = mid - 1;
         }
-        tile_seg[t] = lo;
+        SegDesc d = descs[list[lo]];
+        d.pad = first_tile[lo];
+        tile_desc[t] = d;
     }
 }
 
@@ -302,17 +308,15 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
 // ---------------------------------------------------------------------------
 
 // Counts the digits of the passes in `digits` (bit p: digit p) per tiled
-// segment into hist[row][p][d] (zeroed before; other rows stay zero).  Block b walks a contiguous range of
-// tiles, so its counters stay in LDS across the tiles of one segment and
+// segment into hist[row][p][d] (zeroed before; other rows stay zero).  Block
+// b walks a contiguous range of tiles (tile_desc from k_seg_tilemap), so its
+// counters stay in LDS across the tiles of one segment and
 // are flushed to HBM (atomics) only when the segment changes.  Counting is
 // as in k_histogram: C lane-class copies of the counters in padded LDS rows,
 // and a wave batch whose keys share a pass's digit is counted with one add.
 // The input of pass 0 is the segment's own arrays.
 template <int BLOCK, int C>
-__global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restrict__ descs,
-                                                         const uint32_t *__restrict__ list,
-                                                         const uint32_t *__restrict__ first_tile,
-                                                         const uint32_t *__restrict__ tile_seg,
+__global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restrict__ tile_desc,
                                                          const SegHeader *__restrict__ h,
                                                          uint32_t *__restrict__ hist, uint32_t tile,
                                                          uint32_t digits) {
@@ -332,9 +336,9 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
     const uint32_t t_begin = min(total, blockIdx.x * per);
     const uint32_t t_end = min(total, t_begin + per);
     // adds the LDS counters into the segment's row and clears them
-    auto flush = [&](uint32_t e) {
+    auto flush = [&](uint32_t row) {
         __syncthreads();
-        uint32_t *out = hist + static_cast<size_t>(descs[list[e]].row) * BINS;
+        uint32_t *out = hist + static_cast<size_t>(row) * BINS;
         for (uint32_t i = tid; i < BINS; i += BLOCK) {
             uint32_t c = 0;
 #pragma unroll
@@ -347,15 +351,14 @@ __global__ __launch_bounds__(BLOCK) void k_seg_histogram(const SegDesc *__restri
         __syncthreads();
     };
     __syncthreads();
-    uint32_t cur = ~0u;  // list entry whose counts are in LDS (uniform)
+    uint32_t cur = ~0u;  // row of the segment whose counts are in LDS (uniform)
     for (uint32_t t = t_begin; t < t_end; ++t) {
-        const uint32_t e = tile_seg[t];
-        if (e != cur) {
+        const SegDesc d = tile_desc[t];
+        if (d.row != cur) {
             if (cur != ~0u) flush(cur);
-            cur = e;
+            cur = d.row;
         }
-        const SegDesc d = descs[list[e]];
-        const uint32_t start = (t - first_tile[e]) * tile;
+        const uint32_t start = (t - d.pad) * tile;
         const uint32_t valid = min(tile, d.n - start);
         const uint32_t *src = d.k + start;
         for (uint32_t base = wave * SPAN; base < valid; base += WAVES * SPAN) {
@@ -420,21 +423,18 @@ static __global__ __launch_bounds__(256) void k_seg_plan(const SegDesc *__restri
 // One block per tile (of BLOCK * IPT items: the tile the tile map was built
 // for), claimed as in k_onesweep from nchunks chunks of whole segments
 // (chunk_counter: the launch's kChunks counters, zeroed before it; chunk
-// bounds from k_seg_tilemap with the same nchunks), then the pass body
-// of onesweep_tile on it.  The tile's segment runs pass `pass` (or its own
-// d.pass when pass < 0) on digit digit0 + pass: even passes read k/v and
-// write tk/tv, odd passes the reverse, so four passes leave the result in
-// k/v and three in tk/tv.  The
-// segment's lookback chain starts at its first tile.  Status words: one per
+// bounds from k_seg_tilemap with the same nchunks), then the pass body of
+// onesweep_tile on it; the tile's segment and first tile come from
+// tile_desc.  The tile's segment runs pass `pass` (or its own d.pass when
+// pass < 0) on digit digit0 + pass: even passes read k/v and write tk/tv,
+// odd passes the reverse, so four passes leave the result in k/v and three
+// in tk/tv.  The segment's lookback chain starts at its first tile.  Status words: one per
 // tile and digit, zeroed before the launch.  PERSIST: a block claims tiles
 // until none is left, so a grid of one block per CU covers any tile count
 // (for calls whose tiled list is usually short or empty: the full grid's
 // blocks would mostly start only to find nothing to do).
 template <int BLOCK, int IPT, bool VALS, typename S, bool PERSIST = false>
-__global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ descs,
-                                                        const uint32_t *__restrict__ list,
-                                                        const uint32_t *__restrict__ first_tile,
-                                                        const uint32_t *__restrict__ tile_seg,
+__global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restrict__ tile_desc,
                                                         const SegHeader *__restrict__ h, int pass,
                                                         const uint32_t *__restrict__ base, S *__restrict__ status,
                                                         uint32_t *__restrict__ chunk_counter,
@@ -454,9 +454,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_onesweep(const SegDesc *__restric
         __syncthreads();
         const uint32_t tile = lds.claim[0];
         if (tile >= h->total_tiles) return;  // kNoTile too
-        const uint32_t e = tile_seg[tile];
-        const SegDesc d = descs[list[e]];
-        const uint32_t first = first_tile[e];
+        const SegDesc d = tile_desc[tile];
+        const uint32_t first = d.pad;
         const uint32_t p = pass >= 0 ? static_cast<uint32_t>(pass) : d.pass;
         TileJob<uint32_t, uint32_t> job;
         job.src_k = (p & 1u) ? d.tk : d.k;

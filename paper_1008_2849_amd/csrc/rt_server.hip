@@ -97,8 +97,8 @@ Meta make_meta(uint32_t max_active, size_t arena_bytes, uint32_t lds_max) {
     m.gen = off;        off += a(sizeof(GenDesc) * max_active);
     m.first_pass = off; off += a(sizeof(uint32_t) * (max_active + 1));
     m.first_hist = off; off += a(sizeof(uint32_t) * (max_active + 1));
-    m.seg_pass = off;   off += a(sizeof(uint32_t) * m.max_tiles);
-    m.seg_hist = off;   off += a(sizeof(uint32_t) * m.max_tiles);
+    m.seg_pass = off;   off += a(sizeof(SegDesc) * m.max_tiles);
+    m.seg_hist = off;   off += a(sizeof(SegDesc) * m.max_tiles);
     m.hist = off;       off += a(sizeof(uint32_t) * kSegPasses * kSegRadix * max_active);
     m.base = off;       off += a(sizeof(uint32_t) * kSegPasses * kSegRadix * max_active);
     m.status = off;     off += a(sizeof(uint32_t) * kSegRadix * static_cast<size_t>(m.max_tiles));
@@ -295,8 +295,8 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
     uint32_t *d_plist = d_lists + static_cast<size_t>(kSegLarge) * stride;
     uint32_t *d_first_p = reinterpret_cast<uint32_t *>(dm + m.first_pass);
     uint32_t *d_first_h = reinterpret_cast<uint32_t *>(dm + m.first_hist);
-    uint32_t *d_seg_p = reinterpret_cast<uint32_t *>(dm + m.seg_pass);
-    uint32_t *d_seg_h = reinterpret_cast<uint32_t *>(dm + m.seg_hist);
+    SegDesc *d_seg_p = reinterpret_cast<SegDesc *>(dm + m.seg_pass);
+    SegDesc *d_seg_h = reinterpret_cast<SegDesc *>(dm + m.seg_hist);
     uint32_t *d_hist = reinterpret_cast<uint32_t *>(dm + m.hist);
     uint32_t *d_base = reinterpret_cast<uint32_t *>(dm + m.base);
     uint32_t *d_status = reinterpret_cast<uint32_t *>(dm + m.status);
@@ -317,10 +317,10 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
                            d_hh, d_hist);
         hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, d_descs, d_hlist, d_first_h, d_hh, stride,
                            m.max_tiles, static_cast<uint32_t>(kSegTile));
-        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_h,
-                           d_hh, d_seg_h, 1u);
-        hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_descs,
-                           d_hlist, d_first_h, d_seg_h, d_hh, d_hist, static_cast<uint32_t>(kSegTile),
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_descs,
+                           d_hlist, d_first_h, d_hh, d_seg_h, 1u);
+        hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(grid(P.tiles, cus * 2)), dim3(512), 0, st, d_seg_h,
+                           d_hh, d_hist, static_cast<uint32_t>(kSegTile),
                            (1u << kSegPasses) - 1u);
         hipLaunchKernelGGL(k_seg_plan, dim3(grid(P.fresh_tiled, cus * 4)), dim3(256), 0, st, d_descs, d_hlist, d_hh,
                            d_hist, d_base);
@@ -332,19 +332,19 @@ rt_status enqueue_step(rt_server *s, StepSlot &slot, const StepPlan &P) {
                            m.max_tiles, static_cast<uint32_t>(kSegTile));
         // XCD chunks when the step's tiled requests are long (see seg_chunk_count)
         const uint32_t nchunks = seg_chunk_count(P.tiles * kSegTile, P.tiled, kSegTile);
-        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_first_p,
-                           d_hp, d_seg_p, nchunks);
+        hipLaunchKernelGGL(k_seg_tilemap, dim3(grid((P.tiles + 255) / 256, cus * 4)), dim3(256), 0, st, d_descs,
+                           d_plist, d_first_p, d_hp, d_seg_p, nchunks);
         uint32_t *ctr = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, chunk_ctr) / 4;
         uint32_t *err = reinterpret_cast<uint32_t *>(d_hp) + offsetof(SegHeader, error) / 4;
         // a server holds one value layout (checked at submit), so one
         // kernel flavour serves every request of the step
         if (P.vals)
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, true, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
-                               dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
+                               dim3(1024), 0, st, d_seg_p, d_hp, -1, d_base, d_status,
                                ctr, err, nchunks, 0u);
         else
             hipLaunchKernelGGL((k_seg_onesweep<1024, 16, false, uint32_t>), dim3(static_cast<uint32_t>(P.tiles)),
-                               dim3(1024), 0, st, d_descs, d_plist, d_first_p, d_seg_p, d_hp, -1, d_base, d_status,
+                               dim3(1024), 0, st, d_seg_p, d_hp, -1, d_base, d_status,
                                ctr, err, nchunks, 0u);
     }
     for (uint32_t c = 0; c < s->classes.count; ++c)  // small requests, whole in LDS
