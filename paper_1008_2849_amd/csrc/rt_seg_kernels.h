@@ -238,11 +238,15 @@ __global__ __launch_bounds__(BLOCK) void k_seg_small(const SegDesc *__restrict__
                 const uint32_t dg = __builtin_amdgcn_ubfe(key[j], shift, width);
                 uint32_t lo, hi;
                 match_digit<BITS>(dg, lo, hi);
-                const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
                 const uint32_t cnt = wh[dg];
-                rnk[j] = cnt + below;
-                uint32_t *dst = below == 0 ? wh + dg : scratch;
-                *dst = cnt + __builtin_popcount(lo) + __builtin_popcount(hi);
+                // mbcnt and bcnt add the counter while they count
+                const uint32_t r = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, cnt));
+                rnk[j] = r;
+                uint32_t *dst = r == cnt ? wh + dg : scratch;
+                uint32_t t;
+                asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(t) : "v"(lo), "v"(cnt));
+                asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(t) : "v"(hi), "v"(t));
+                *dst = t;
                 compiler_fence();
             }
             __syncthreads();
