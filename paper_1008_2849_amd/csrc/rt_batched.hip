@@ -38,9 +38,13 @@ bool seg_tile_shape_supported(int block, int ipt) {
 
 void launch_seg_small(const SegClass &c, bool vals, uint32_t max_listed, hipStream_t stream, const SegDesc *descs,
                       const uint32_t *list, const SegHeader *h, int which, int key_bits, int to_temp) {
-    // enough blocks to fill the CUs: more per CU for smaller shapes (LDS)
+    // enough blocks to fill the CUs: more per CU for smaller shapes, as many
+    // as the LDS holds (stage, per-wave counters and scratch rows)
     const uint32_t cus = static_cast<uint32_t>(device_cu_count());
-    const uint32_t per_cu = std::max<uint32_t>(1u, kSegLdsMax / static_cast<uint32_t>(c.block * c.ipt));
+    const uint32_t lds = static_cast<uint32_t>(c.block * c.ipt) * (vals ? 8u : 4u) +
+                         static_cast<uint32_t>(c.block / 64) * ((1u << c.bits) + 64u) * 4u + 64u;
+    const uint32_t per_cu = std::max<uint32_t>(
+        {1u, kSegLdsMax / static_cast<uint32_t>(c.block * c.ipt), kLdsBytesPerCu / lds});
     const uint32_t grid = std::max<uint32_t>(1u, std::min<uint32_t>(max_listed, cus * per_cu));
 #define RT_SEG_SHAPE_LAUNCH(BLK, I, B)                                                                           \
     if (c.block == BLK && c.ipt == I && c.bits == B) {                                                           \
@@ -111,6 +115,10 @@ static void launch_seg_sort_body(const SegPointers &P, const SegLayout &L, uint3
     hipLaunchKernelGGL(k_seg_tilemap, dim3(cap_grid((L.max_tiles + 255) / 256, cus * 4)), dim3(256), 0, stream,
                        P.descs, large_list, P.first_tile, P.header, P.tile_seg, nchunks);
     prof_mark(stream, RT_KIND_SEGMENTED);
+    // the histogram rows and lookback words this call uses start at zero
+    hipLaunchKernelGGL(k_seg_clear, dim3(cus * 4), dim3(256), 0, stream, P.header, P.hist,
+                       reinterpret_cast<uint32_t *>(P.status), L.status_pass / 4, L.wide_status ? 2u : 1u, passes);
+    prof_mark(stream, RT_KIND_FILL);
     hipLaunchKernelGGL((k_seg_histogram<512, 16>), dim3(cap_grid(L.max_tiles, cus * 2)), dim3(512), 0, stream,
                        P.tile_seg, P.header, P.hist, L.tile,
                        ((1u << passes) - 1u) << digit0);
@@ -167,14 +175,6 @@ void launch_segments(uint32_t *keys, uint32_t *vals, uint32_t *tk, uint32_t *tv,
     const SegPointers P = seg_pointers(ws, L);
     const bool vals_on = vals != nullptr;
     hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, stream, P.header);
-    const size_t hist_words = static_cast<size_t>(kSegPasses) * kSegRadix * L.large_capacity;
-    if (hist_words)
-        hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((hist_words + 4095) / 4096, 1024)), dim3(256), 0, stream,
-                           P.hist, hist_words);
-    const size_t status_words = L.status_pass * static_cast<size_t>(passes) / 4;
-    hipLaunchKernelGGL(k_fill_zero, dim3(cap_grid((status_words + 4095) / 4096, 4096)), dim3(256), 0, stream,
-                       reinterpret_cast<uint32_t *>(P.status), status_words);
-    prof_mark(stream, RT_KIND_FILL);
     hipLaunchKernelGGL(k_seg_classify, dim3((num_segments + 255) / 256), dim3(256), 0, stream, offsets,
                        num_segments, keys, vals, tk, vals_on ? tv : nullptr, L.capacity, L.large_capacity,
                        to_temp, L.classes.limits(), P.descs, P.lists, P.header);

@@ -80,6 +80,7 @@ constexpr int kSegRadix = 1 << kSegBits;
 constexpr int kSegTile = 1024 * 16;  // items per tile of the server's passes (batched calls: tuned)
 constexpr int kSegMaxClasses = 4;    // whole-in-LDS size classes at most
 constexpr uint32_t kSegLdsMax = 1024 * 16;  // largest segment one block sorts in LDS
+constexpr uint32_t kLdsBytesPerCu = 160 * 1024;  // LDS of one gfx950 CU
 constexpr int kSegLarge = kSegMaxClasses;   // list index of the tiled segments
 constexpr uint32_t kSegErrBounds = 2u;  // a segment reached past the workspace
 

@@ -37,24 +37,25 @@ constexpr uint32_t kMsdWidth = 8;
 constexpr uint32_t kMsdBuckets = 1u << kMsdWidth;
 constexpr int kLocalPasses = 3;
 constexpr uint32_t kSubBuckets = kMsdBuckets << 8;  // second level: digit 2 inside each bucket
-// Two levels by default from this size (sub-buckets of about 4096 items):
-// measured slower than one level at 2^26 and 2^27 items, faster at 2^28.
-constexpr size_t kTwoLevelMinItems = static_cast<size_t>(1) << 28;
+// Two levels by default from this size (sub-buckets of about 2048 items and
+// up): measured faster than one level at 2^27 and 2^28 items, slower at
+// 2^26.
+constexpr size_t kTwoLevelMinItems = static_cast<size_t>(1) << 27;
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 // Size classes of the sub-buckets.  Uniform keys give sub-buckets of about
-// m = n / 65536 items (within a few sqrt(m)); from m = 2048 the classes sit
-// close above that, so a sub-bucket just past 4096 items takes a 5120-item
-// block rather than an 8192-item one.  Smaller m keeps the tuned classes.
+// m = n / 65536 items, within a few sqrt(m).  From m = 2048 one class of
+// 256 x 17 blocks (4352 items, four blocks per CU) takes nearly all of them
+// in one launch: at 2^28 items m = 4096 and 4352 is four standard
+// deviations above it.  Smaller m keeps the tuned classes.
 SegClassTable leaf_classes(size_t n) {
     SegClassTable t = seg_class_table();
     if (n / kSubBuckets < 2048) return t;
-    t.count = 4;
-    t.cls[0] = SegClass{4096, 256, 16, 8};
-    t.cls[1] = SegClass{5120, 256, 20, 8};
-    t.cls[2] = SegClass{8192, 512, 16, 8};
-    t.cls[3] = SegClass{16384, 1024, 16, 8};
+    t.count = 3;
+    t.cls[0] = SegClass{4352, 256, 17, 8};
+    t.cls[1] = SegClass{8192, 512, 16, 8};
+    t.cls[2] = SegClass{16384, 1024, 16, 8};
     return t;
 }
 

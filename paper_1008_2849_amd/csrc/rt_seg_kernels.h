@@ -134,6 +134,24 @@ static __global__ __launch_bounds__(1024) void k_seg_tiles(const SegDesc *__rest
     }
 }
 
+// Zeroes what a segmented call's counting and passes will use: the
+// histogram rows of its listed tiled segments and, for each of `passes`
+// passes, the lookback words of its tiles (both counts from k_seg_tiles),
+// rather than the tables' full size, which holds the most tiled segments and
+// tiles the workspace allows.  status_pass_words: one pass's region, in
+// 32-bit words; word_u32s: 32-bit words per lookback word (1 or 2).
+static __global__ __launch_bounds__(256) void k_seg_clear(const SegHeader *__restrict__ h,
+                                                   uint32_t *__restrict__ hist, uint32_t *__restrict__ status,
+                                                   size_t status_pass_words, uint32_t word_u32s, int passes) {
+    const size_t hist_words = static_cast<size_t>(h->count[kSegLarge]) * kSegPasses * kSegRadix;
+    const size_t status_words = static_cast<size_t>(h->total_tiles) * kSegRadix * word_u32s;
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
+    const size_t first = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    for (size_t i = first; i < hist_words; i += stride) hist[i] = 0u;
+    for (int p = 0; p < passes; ++p)
+        for (size_t i = first; i < status_words; i += stride) status[p * status_pass_words + i] = 0u;
+}
+
 // tile_desc[t] = the descriptor of the segment that tile t belongs to, with
 // pad = that segment's first tile (first_tile is strictly increasing: every
 // listed segment has at least one tile), so that a tile's kernel reaches its

@@ -28,7 +28,7 @@ TABLES = {
                     (1024, 16)),
     "mixed_tile8k": ([(512, 64, 8), (2048, 256, 8), (8192, 512, 16)], [11, 8, 11], (512, 16)),
     # the sub-bucket classes of a two-level MSD-first sort of 2^28 items
-    "tight_4k": ([(4096, 256, 16), (5120, 256, 20), (8192, 512, 16), (16384, 1024, 16)], [8] * 4, (1024, 16)),
+    "tight_4k": ([(4352, 256, 17), (8192, 512, 16), (16384, 1024, 16)], [8] * 3, (1024, 16)),
 }
 BITS = {8: [8, 8, 8, 8], 11: [11, 11, 10]}
 
