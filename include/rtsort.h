@@ -291,7 +291,7 @@ size_t rt_msd_first_workspace_bytes(size_t n, int with_values);
  * keys, vals: device u32[n], not overlapping; vals may be NULL (keys only).
  * flags: 0 or any of RT_FLAG_VALIDATE (wait, and report a device error
  * word as RT_ERR_HIP), RT_FLAG_MSD_ONE_LEVEL, RT_FLAG_MSD_TWO_LEVELS (by
- * default two levels from 2^27 items).  workspace: device memory of at least
+ * default two levels from 2^26 items).  workspace: device memory of at least
  * rt_msd_first_workspace_bytes(n, vals != NULL) bytes, 256-byte aligned,
  * or NULL for the library's per-stream cache; with a caller workspace and
  * no RT_FLAG_VALIDATE the call only enqueues kernels.  Argument errors are

@@ -125,7 +125,7 @@ def tune(sizes, reps, log=print):
 # whole-in-LDS shapes the library compiles; keep in step with
 # RT_FOR_EACH_SEG_SMALL_SHAPE in csrc/rt_common.h
 SEG_SHAPES = [(64, 4), (64, 8), (128, 4), (128, 8), (256, 4), (256, 8), (512, 4), (512, 8), (256, 16),
-              (256, 17), (512, 16), (1024, 8), (1024, 16)]
+              (128, 9), (256, 9), (256, 17), (512, 16), (1024, 8), (1024, 16)]
 SEG_RANGES = list(range(6, 15))  # (2^(k-1), 2^k]
 SEG_BATCH_ITEMS = 1 << 23
 

@@ -91,6 +91,8 @@ void launch_sort(uint32_t *keys, uint32_t *vals, uint32_t n, const Resolved &r, 
     X(512, 4, 8)                       \
     X(512, 8, 8)                       \
     X(256, 16, 8)                      \
+    X(128, 9, 8)                       \
+    X(256, 9, 8)                       \
     X(256, 17, 8)                      \
     X(512, 16, 8)                      \
     X(1024, 8, 8)                      \

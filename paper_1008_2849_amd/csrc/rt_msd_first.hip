@@ -37,25 +37,41 @@ constexpr uint32_t kMsdWidth = 8;
 constexpr uint32_t kMsdBuckets = 1u << kMsdWidth;
 constexpr int kLocalPasses = 3;
 constexpr uint32_t kSubBuckets = kMsdBuckets << 8;  // second level: digit 2 inside each bucket
-// Two levels by default from this size (sub-buckets of about 2048 items and
-// up): measured faster than one level at 2^27 and 2^28 items, slower at
-// 2^26.
-constexpr size_t kTwoLevelMinItems = static_cast<size_t>(1) << 27;
+// Two levels by default from this size (sub-buckets of about 1024 items and
+// up, with the classes of leaf_classes): measured faster than one level at
+// 2^26, 2^27 and 2^28 items.
+constexpr size_t kTwoLevelMinItems = static_cast<size_t>(1) << 26;
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 // Size classes of the sub-buckets.  Uniform keys give sub-buckets of about
-// m = n / 65536 items, within a few sqrt(m).  From m = 2048 one class of
-// 256 x 17 blocks (4352 items, four blocks per CU) takes nearly all of them
-// in one launch: at 2^28 items m = 4096 and 4352 is four standard
-// deviations above it.  Smaller m keeps the tuned classes.
+// m = n / 65536 items, within a few sqrt(m).  The first class sits about
+// four standard deviations above m, so one launch of blocks hardly larger
+// than the sub-buckets takes nearly all of them: 256 x 17 (4352 items) for
+// m = 4096 (2^28 items), 256 x 9 (2304) for m = 2048, 128 x 9 (1152) for
+// m = 1024; the rare larger ones go to the next classes.  Smaller m keeps
+// the tuned classes.
 SegClassTable leaf_classes(size_t n) {
     SegClassTable t = seg_class_table();
-    if (n / kSubBuckets < 2048) return t;
-    t.count = 3;
-    t.cls[0] = SegClass{4352, 256, 17, 8};
-    t.cls[1] = SegClass{8192, 512, 16, 8};
-    t.cls[2] = SegClass{16384, 1024, 16, 8};
+    const size_t m = n / kSubBuckets;
+    if (m < 768) return t;
+    t.count = 4;
+    if (m >= 3072) {
+        t.count = 3;
+        t.cls[0] = SegClass{4352, 256, 17, 8};
+        t.cls[1] = SegClass{8192, 512, 16, 8};
+        t.cls[2] = SegClass{16384, 1024, 16, 8};
+    } else if (m >= 1536) {
+        t.cls[0] = SegClass{2304, 256, 9, 8};
+        t.cls[1] = SegClass{4352, 256, 17, 8};
+        t.cls[2] = SegClass{8192, 512, 16, 8};
+        t.cls[3] = SegClass{16384, 1024, 16, 8};
+    } else {
+        t.cls[0] = SegClass{1152, 128, 9, 8};
+        t.cls[1] = SegClass{2304, 256, 9, 8};
+        t.cls[2] = SegClass{4352, 256, 17, 8};
+        t.cls[3] = SegClass{16384, 1024, 16, 8};
+    }
     return t;
 }
 

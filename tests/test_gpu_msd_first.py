@@ -134,6 +134,16 @@ def test_sub_bucket_size_edges(case):
     assert_same(gpu_msd_first(k, levels=2), oracle.reverse_sort(k), case + " keys")
 
 
+@pytest.mark.parametrize("n", [(1 << 26) + 12345, (1 << 27) + 777])
+def test_two_levels_sized_classes(n):
+    """Sizes whose sub-buckets (about 1024 and 2048 items) take the classes
+    sized to them, by default: the whole output against the oracle."""
+    announce(f"msd-first default two levels n={n}")
+    k = inputs.uniform_keys(n, 800 + n % 97)
+    v = inputs.index_values(n)
+    assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), f"n={n}")
+
+
 @pytest.mark.parametrize("levels", LEVELS)
 def test_explicit_workspace_repeat_and_graph(levels):
     """A caller workspace; three eager calls and a captured graph replayed

@@ -27,8 +27,9 @@ TABLES = {
     "eleven_bits": ([(256, 64, 4), (1024, 256, 4), (4096, 256, 16), (8192, 512, 16)], [11, 11, 11, 11],
                     (1024, 16)),
     "mixed_tile8k": ([(512, 64, 8), (2048, 256, 8), (8192, 512, 16)], [11, 8, 11], (512, 16)),
-    # the sub-bucket classes of a two-level MSD-first sort of 2^28 items
+    # the sub-bucket classes of two-level MSD-first sorts of 2^28 and 2^26 items
     "tight_4k": ([(4352, 256, 17), (8192, 512, 16), (16384, 1024, 16)], [8] * 3, (1024, 16)),
+    "tight_1k": ([(1152, 128, 9), (2304, 256, 9), (4352, 256, 17), (16384, 1024, 16)], [8] * 4, (1024, 16)),
 }
 BITS = {8: [8, 8, 8, 8], 11: [11, 11, 10]}
 
