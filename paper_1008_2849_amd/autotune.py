@@ -126,6 +126,9 @@ def tune(sizes, reps, log=print):
 # RT_FOR_EACH_SEG_SMALL_SHAPE in csrc/rt_common.h
 SEG_SHAPES = [(64, 4), (64, 8), (128, 4), (128, 8), (256, 4), (256, 8), (512, 4), (512, 8), (256, 16),
               (128, 9), (256, 9), (256, 17), (512, 16), (1024, 8), (1024, 16)]
+# the 11-bit ones (11-bit counters need 8 KiB a wave: at most 512 threads)
+SEG_SHAPES_11 = [(64, 4), (64, 8), (128, 4), (128, 8), (256, 4), (256, 8), (256, 16), (512, 4), (512, 8),
+                 (512, 16)]
 SEG_RANGES = list(range(6, 15))  # (2^(k-1), 2^k]
 SEG_BATCH_ITEMS = 1 << 23
 
@@ -136,8 +139,8 @@ SEG_TILES = [(1024, 16), (512, 16)]  # tiles of the tiled segments' passes; keep
 
 def seg_small_supported(b, i, bits):
     """Whether the library compiles the whole-in-LDS kernel b x i with
-    bits-bit digits (11-bit counters need 8 KiB a wave: at most 512 threads)."""
-    return bits == 8 or b <= 512
+    bits-bit digits."""
+    return (b, i) in (SEG_SHAPES if bits == 8 else SEG_SHAPES_11)
 
 
 def _segment_table(classes, tile=(1024, 16)):

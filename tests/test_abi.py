@@ -472,3 +472,28 @@ def test_committed_tuning_table_loads(so):
     tile = [(e["block"], e["ipt"]) for e in table["entries"] if e["op"] == "segments_tiled"]
     assert api.segment_config() == (bits, tile[0] if tile else (1024, 16))
     assert so.rt_load_tuning(None) == _lib.RT_OK
+
+
+def test_autotuner_segment_shapes_match_the_library(so, tmp_path):
+    """Every whole-in-LDS shape the autotuner may try loads as a class, and
+    an 8-bit-only shape is refused with 11-bit digits (host-side checks)."""
+    import json
+    from paper_1008_2849_amd import autotune
+
+    def load(block, ipt, bits):
+        path = tmp_path / "t.json"
+        path.write_text(json.dumps({"entries": [
+            {"op": "segments", "min_n": 0, "max_n": min(block * ipt, 16384), "block": block, "ipt": ipt,
+             "digit_bits": list(autotune.SEG_BITS[bits])}]}))
+        return so.rt_load_tuning(str(path).encode())
+
+    try:
+        for b, i in autotune.SEG_SHAPES:
+            assert load(b, i, 8) == 0, (b, i, 8)
+        for b, i in autotune.SEG_SHAPES_11:
+            assert load(b, i, 11) == 0, (b, i, 11)
+        for b, i in set(autotune.SEG_SHAPES) - set(autotune.SEG_SHAPES_11):
+            assert load(b, i, 11) == _lib.RT_ERR_INVALID_ARG, (b, i, 11)
+    finally:
+        from paper_1008_2849_amd import api
+        api.load_default_tuning()  # the committed table, as the package loads it
