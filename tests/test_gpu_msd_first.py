@@ -144,6 +144,19 @@ def test_two_levels_sized_classes(n):
     assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), f"n={n}")
 
 
+@pytest.mark.parametrize("dist", ["and4", "zipf16", "top_00", "low_byte_only", "sorted"])
+def test_two_levels_skewed_at_size(dist):
+    """Two levels by default (2^26 + 99 items) on skewed keys: sub-buckets
+    far from the uniform mean, the largest through the persistent tiled
+    passes, the smallest empty; pairs and keys only, against the oracle."""
+    n = (1 << 26) + 99
+    announce(f"msd-first default two levels dist={dist} n={n}")
+    k = _dist_cases(n)[dist]
+    v = inputs.index_values(n)
+    assert_same(gpu_msd_first(k, v, validate=True), oracle.reverse_sort(k, v), dist)
+    assert_same(gpu_msd_first(k), oracle.reverse_sort(k), dist + " keys")
+
+
 @pytest.mark.parametrize("levels", LEVELS)
 def test_explicit_workspace_repeat_and_graph(levels):
     """A caller workspace; three eager calls and a captured graph replayed
