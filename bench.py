@@ -671,7 +671,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build sorts on one GPU; multi-GPU runs are not part of it "
+        print("bench.py: the library sorts on one GPU; multi-GPU runs are not provided "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         return 2
 

@@ -46,7 +46,7 @@ typedef enum rt_status {
     RT_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
     RT_ERR_HIP = 4,           /* a HIP call or kernel launch failed */
     RT_ERR_BUDGET = 5,        /* serving: request larger than the HBM budget */
-    RT_ERR_UNSUPPORTED = 6,   /* configuration this build does not provide */
+    RT_ERR_UNSUPPORTED = 6,   /* a configuration the library does not provide */
     RT_ERR_CANCELLED = 7,     /* serving: request cancelled, or dropped at shutdown */
     RT_ERR_TIMEOUT = 8,       /* serving: wait timed out, request still live */
     RT_ERR_NOT_FOUND = 9      /* serving: unknown or already collected ticket */

@@ -100,7 +100,7 @@ def tune(sizes, reps, log=print):
             for cfg in candidates():
                 try:
                     t = time_config(cfg, keys, vals, r, check)
-                except Exception as e:  # a shape this build lacks, or a wrong result
+                except Exception as e:  # a shape the library lacks, or a wrong result
                     log(f"  skip {cfg}: {e}")
                     continue
                 results.append((t, cfg))
