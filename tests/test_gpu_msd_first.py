@@ -230,3 +230,26 @@ def test_headline_workload_full_size_sampled():
     assert np.all(gk[1:] >= gk[:-1])
     eq = gk[1:] == gk[:-1]
     assert np.all(gv[1:][eq] > gv[:-1][eq])
+
+
+@pytest.mark.parametrize("levels", LEVELS)
+def test_full_size_keys_only(levels):
+    """2^28 uniform keys without values, each form: the output equals numpy's
+    sort of the input (for keys alone a stable sort and any sort agree), and
+    a sample of MSD buckets equals the oracle's sort of that bucket."""
+    import torch
+    n = 1 << 28
+    announce(f"msd-first full size keys only levels={levels}")
+    k_h = inputs.uniform_keys(n, 21)
+    k = to_dev(k_h)
+    rts.sort_msd_first(k, validate=True, levels=levels)
+    sync()
+    gk = to_host(k)
+    del k
+    torch.cuda.empty_cache()
+    assert np.array_equal(gk, np.sort(k_h))
+    msd = (k_h >> np.uint32(24)).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(np.bincount(msd, minlength=256))])
+    for d in [3, 200]:
+        wk, _ = oracle.reverse_sort(k_h[msd == d])
+        assert np.array_equal(gk[int(starts[d]):int(starts[d + 1])], wk), f"bucket {d}"
